@@ -1,0 +1,175 @@
+/*
+ * CPU oracle for the irradiance matrix -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, brute-force FP64 evaluation of what the paper defines:
+ *   - one surface element per mesh triangle (Sec. III-B, discrete
+ *     formulation), sampled at its centroid;
+ *   - the inverse-square, cosine-weighted point-source irradiance of Sec. IV-C
+ *     (equation "inverse square law"), counted only when the element faces the
+ *     source with a strictly positive cosine and nothing else lies on the
+ *     segment between them;
+ *   - extended lamps as several point sources whose contributions add
+ *     (Sec. IV-C, "Non-Point Light Sources").
+ * Every (pose, source, element) segment is tested against every triangle.
+ * Only the test suite, the smoke check and the benchmark's CPU baseline may
+ * load this library; the product path never does.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -fno-fast-math -shared -fPIC
+ * (no contraction, no reassociation: every FP64 operation below is one IEEE
+ * operation in the written order).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <omp.h>
+
+typedef struct { double x, y, z; } d3;
+
+static d3 ld(const float* p) { d3 r = {(double)p[0], (double)p[1], (double)p[2]}; return r; }
+static d3 sub(d3 a, d3 b) { d3 r = {a.x - b.x, a.y - b.y, a.z - b.z}; return r; }
+static d3 cross(d3 a, d3 b) {
+    d3 r = {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+    return r;
+}
+static double dot(d3 a, d3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+
+/* Surface elements.  Centroid: ((a + b) + c) / 3 in FP64, rounded once to
+ * FP32 -- this FP32 point is the element's sampling point, the target of its
+ * occlusion segments.  m = (b - a) x (c - a) in FP64; unit normal m / |m|;
+ * area |m| / 2. */
+void oracle_elements(const float* verts, const int32_t* tris, int64_t n,
+                     float* c32, double* n64, double* area64, double* m64)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        d3 a = ld(verts + 3 * (int64_t)tris[3 * i + 0]);
+        d3 b = ld(verts + 3 * (int64_t)tris[3 * i + 1]);
+        d3 c = ld(verts + 3 * (int64_t)tris[3 * i + 2]);
+        c32[3 * i + 0] = (float)(((a.x + b.x) + c.x) / 3.0);
+        c32[3 * i + 1] = (float)(((a.y + b.y) + c.y) / 3.0);
+        c32[3 * i + 2] = (float)(((a.z + b.z) + c.z) / 3.0);
+        d3 m = cross(sub(b, a), sub(c, a));
+        double len = sqrt(dot(m, m));
+        n64[3 * i + 0] = m.x / len;
+        n64[3 * i + 1] = m.y / len;
+        n64[3 * i + 2] = m.z / len;
+        area64[i] = 0.5 * len;
+        m64[3 * i + 0] = m.x;
+        m64[3 * i + 1] = m.y;
+        m64[3 * i + 2] = m.z;
+    }
+}
+
+/* Front-facing test: <p - c, m> > 0, strict (the paper requires a strictly
+ * positive inner product with the surface normal). */
+static int front64(d3 p, d3 c, d3 m) { return dot(sub(p, c), m) > 0.0; }
+
+/* Segment / triangle occlusion predicate.
+ * The open segment O->T (0 < t < 1) meets the closed triangle v0 v1 v2 iff
+ *  (1) O and T lie strictly on opposite sides of the triangle's plane, and
+ *  (2) the line through O and T passes through the closed triangle: the three
+ *      edge orientations D . ((vi - O) x (vj - O)) with D = T - O, taken for
+ *      the edges (v1,v2), (v2,v0), (v0,v1), are not of mixed strict sign.
+ * A degenerate triangle (m = 0) never occludes.  An edge shared by two
+ * triangles enters them with opposite vertex order, so its orientation is
+ * computed as exact negatives of each other and no segment slips between
+ * the two triangles. */
+static int hit64(d3 O, d3 T, d3 v0, d3 v1, d3 v2)
+{
+    d3 m = cross(sub(v1, v0), sub(v2, v0));
+    double sO = dot(sub(O, v0), m);
+    double sT = dot(sub(T, v0), m);
+    if (!((sO > 0.0 && sT < 0.0) || (sO < 0.0 && sT > 0.0))) return 0;
+    d3 D = sub(T, O);
+    d3 a = sub(v0, O), b = sub(v1, O), c = sub(v2, O);
+    double U = dot(D, cross(b, c));
+    double V = dot(D, cross(c, a));
+    double W = dot(D, cross(a, b));
+    int neg = (U < 0.0) || (V < 0.0) || (W < 0.0);
+    int pos = (U > 0.0) || (V > 0.0) || (W > 0.0);
+    return !(neg && pos);
+}
+
+int oracle_hit(const float* O, const float* T, const float* v0, const float* v1, const float* v2)
+{
+    return hit64(ld(O), ld(T), ld(v0), ld(v1), ld(v2));
+}
+
+/* Reciprocal visibility test used by the invariant checks: is any triangle
+ * other than `skip` hit by the open segment O->T? */
+int oracle_segment_blocked(const float* verts, const int32_t* tris, int64_t n,
+                           const float* O, const float* T, int64_t skip)
+{
+    d3 o = ld(O), t = ld(T);
+    for (int64_t m = 0; m < n; ++m) {
+        if (m == skip) continue;
+        d3 v0 = ld(verts + 3 * (int64_t)tris[3 * m + 0]);
+        d3 v1 = ld(verts + 3 * (int64_t)tris[3 * m + 1]);
+        d3 v2 = ld(verts + 3 * (int64_t)tris[3 * m + 2]);
+        if (hit64(o, t, v0, v1, v2)) return 1;
+    }
+    return 0;
+}
+
+/* Irradiance entries for a list of (pose, element) pairs.
+ *   poses: K x pose_dim floats (x, y) or (x, y, z); source j sits at
+ *          (x, y, z + dz[j]) with the height sum taken in FP32 (z = 0 for
+ *          pose_dim 2).
+ *   E_out[p]   = sum over sources j (ascending) of
+ *                P_j * max(0, <p_j - c, n>) / (4 pi |p_j - c|^3) * V_j
+ *   vis_out[p] = bit j set iff V_j = 1 (front-facing and unoccluded).
+ * The element's own triangle is excluded from its occlusion test by index. */
+int oracle_irradiance_pairs(const float* verts, const int32_t* tris, int64_t n,
+                            const float* poses, int64_t K, int32_t pose_dim,
+                            int32_t S, const float* dz, const float* power,
+                            const int64_t* pk, const int64_t* pi, int64_t npairs,
+                            double* E_out, uint32_t* vis_out, int32_t nthreads)
+{
+    if (S < 1 || S > 32 || (pose_dim != 2 && pose_dim != 3)) return -1;
+    (void)K;
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    const double four_pi = 4.0 * M_PI;
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t q = 0; q < npairs; ++q) {
+        int64_t k = pk[q], i = pi[q];
+        d3 a = ld(verts + 3 * (int64_t)tris[3 * i + 0]);
+        d3 b = ld(verts + 3 * (int64_t)tris[3 * i + 1]);
+        d3 cc = ld(verts + 3 * (int64_t)tris[3 * i + 2]);
+        float cf[3] = {(float)(((a.x + b.x) + cc.x) / 3.0),
+                       (float)(((a.y + b.y) + cc.y) / 3.0),
+                       (float)(((a.z + b.z) + cc.z) / 3.0)};
+        d3 c = ld(cf);
+        d3 m = cross(sub(b, a), sub(cc, a));
+        double len = sqrt(dot(m, m));
+        d3 nrm = {m.x / len, m.y / len, m.z / len};
+        const float* pp = poses + pose_dim * k;
+        float zb = (pose_dim == 3) ? pp[2] : 0.0f;
+        double acc = 0.0;
+        uint32_t bits = 0;
+        for (int j = 0; j < S; ++j) {
+            float pz = zb + dz[j]; /* FP32 sum */
+            float pf[3] = {pp[0], pp[1], pz};
+            d3 p = ld(pf);
+            if (!front64(p, c, m)) continue;
+            int blocked = 0;
+            for (int64_t mm = 0; mm < n && !blocked; ++mm) {
+                if (mm == i) continue;
+                d3 v0 = ld(verts + 3 * (int64_t)tris[3 * mm + 0]);
+                d3 v1 = ld(verts + 3 * (int64_t)tris[3 * mm + 1]);
+                d3 v2 = ld(verts + 3 * (int64_t)tris[3 * mm + 2]);
+                blocked = hit64(p, c, v0, v1, v2);
+            }
+            if (blocked) continue;
+            d3 d = sub(p, c);
+            double r2 = dot(d, d);
+            double r = sqrt(r2);
+            double s = dot(d, nrm);
+            if (s < 0.0) s = 0.0;
+            acc += (double)power[j] * s / (four_pi * r2 * r);
+            bits |= 1u << j;
+        }
+        E_out[q] = acc;
+        vis_out[q] = bits;
+    }
+    return 0;
+}
+
+int oracle_max_threads(void) { return omp_get_max_threads(); }

@@ -1,0 +1,323 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by geometry.
+
+Each test checks the oracle against something other than itself: textbook
+closed forms (inverse-square law with Lambert's cosine, Sec. IV-C), energy
+conservation of a point source inside a closed surface, an independent
+slab-test shadow footprint, exact rational arithmetic, brute-force hand
+cases, and exact invariants (power-of-two scaling, superposition of point
+sources, mirror symmetry, reciprocity).
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import exact, ref
+from paper_2103_14137_amd import workloads as wl
+
+
+def _mesh(*parts):
+    mb = wl.MeshBuilder()
+    for v, t in parts:
+        mb.add(v, t)
+    return mb.mesh()
+
+
+def _empty_box(cell=0.4, L=(4.0, 4.0, 3.0)):
+    return _mesh(wl.box_surface((0, 0, 0), L, [wl._ncells(x, cell) for x in L], inward=True))
+
+
+# ---------------------------------------------------------------- elements
+def test_elements_area_and_normals_box_room():
+    w = wl.box_room()
+    c, n, a, m = ref.elements(w.mesh.verts, w.mesh.tris)
+    # 4x4x3 shell = 2*16 + 4*12 = 80 m^2; 0.5 m cube = 6 * 0.25 = 1.5 m^2
+    assert abs(a.sum() - 81.5) < 1e-9
+    # every normal is an axis unit vector
+    assert np.allclose(np.sort(np.abs(n), axis=1), [0, 0, 1], atol=1e-15)
+    # room shell normals point into the room (towards its centre)
+    shell = slice(0, 1040)
+    to_centre = np.array([2.0, 2.0, 1.5]) - c[shell].astype(np.float64)
+    assert np.all((to_centre * n[shell]).sum(1) > 0)
+    # cube normals point away from the cube centre
+    x0, y0, _ = w.meta["cube_lo"]
+    cc = np.array([x0 + 0.25, y0 + 0.25, 0.25])
+    assert np.all(((c[1040:] - cc) * n[1040:]).sum(1) > 0)
+
+
+def test_centroid_is_rounded_mean():
+    w = wl.ward()
+    v, t = w.mesh.verts, w.mesh.tris
+    c, _, _, _ = ref.elements(v, t)
+    rng = np.random.default_rng(5)
+    for i in rng.choice(len(t), 400, replace=False):
+        for ax in range(3):
+            ex = sum(Fraction(float(v[t[i, k], ax])) for k in range(3)) / 3
+            got = Fraction(float(c[i, ax]))
+            ulp = Fraction(float(np.spacing(np.float32(abs(float(ex)) + 1e-30))))
+            assert abs(got - ex) <= ulp / 2 + ulp / 2 ** 20  # round-to-nearest of the mean
+
+
+# ------------------------------------------------------ closed-form entries
+def _entry(mesh, pose_xy, dz, power, i):
+    E, vis = ref.irradiance_pairs(mesh.verts, mesh.tris, np.array([pose_xy], np.float32),
+                                  np.array([dz], np.float32), np.array([power], np.float32), [0], [i])
+    return E[0], vis[0]
+
+
+def test_inverse_square_directly_below_lamp():
+    mesh = _empty_box()
+    c, _, _, _ = ref.elements(mesh.verts, mesh.tris)
+    i = int(np.argmin(np.abs(c[:, 2]) + np.abs(c[:, 0] - 1.7) + np.abs(c[:, 1] - 2.2)))
+    assert c[i, 2] == 0.0
+    h = 1.25
+    E, vis = _entry(mesh, (c[i, 0], c[i, 1]), h, 80.0, i)
+    assert vis == 1
+    assert abs(E - 80.0 / (4 * math.pi * h * h)) <= 1e-13 * E
+
+
+@pytest.mark.parametrize("rho", [0.3, 1.1, 2.7])
+def test_lambert_cosine_lateral_offset(rho):
+    mesh = _empty_box()
+    c, _, _, _ = ref.elements(mesh.verts, mesh.tris)
+    floor = np.nonzero(c[:, 2] == 0.0)[0]
+    i = int(floor[np.argmin(np.abs(c[floor, 0] - 0.7) + np.abs(c[floor, 1] - 0.9))])
+    h = 1.0
+    px, py = float(c[i, 0]) + rho * 0.6, float(c[i, 1]) + rho * 0.8
+    pxy = np.array([px, py], np.float32)
+    E, vis = _entry(mesh, pxy, h, 80.0, i)
+    dx, dy = float(pxy[0]) - float(c[i, 0]), float(pxy[1]) - float(c[i, 1])
+    r2 = dx * dx + dy * dy + h * h
+    expect = 80.0 * (h / math.sqrt(r2)) / (4 * math.pi * r2)
+    assert vis == 1
+    assert abs(E - expect) <= 1e-12 * expect
+
+
+def test_back_facing_and_source_in_plane():
+    mesh = _empty_box()
+    c, _, _, _ = ref.elements(mesh.verts, mesh.tris)
+    i = int(np.nonzero(c[:, 2] == 0.0)[0][0])
+    # a source exactly in the floor plane sees the floor with zero cosine: not counted
+    E, vis = _entry(mesh, (1.0, 1.0), 0.0, 80.0, i)
+    assert E == 0.0 and vis == 0
+
+
+# ------------------------------------------------------- energy conservation
+def test_energy_conservation_second_order():
+    """A point source inside a closed empty box sends all of its power P
+    through the walls; the centroid quadrature of sum_i A_i E_i converges to
+    P at second order in the cell size."""
+    P = 80.0
+    errs = []
+    for cell in (0.8, 0.4, 0.2):
+        mesh = _empty_box(cell)
+        _, _, a, _ = ref.elements(mesh.verts, mesh.tris)
+        N = mesh.n_tris
+        E, vis = ref.irradiance_pairs(mesh.verts, mesh.tris, np.array([[1.3, 2.1]], np.float32),
+                                      np.array([1.1], np.float32), np.array([P], np.float32),
+                                      np.zeros(N, np.int64), np.arange(N))
+        assert np.all(vis == 1)  # convex room: everything is lit
+        errs.append(abs((a * E).sum() - P) / P)
+    assert errs[-1] < 2e-3
+    for e0, e1 in zip(errs, errs[1:]):
+        assert 3.0 < e0 / e1 < 5.5, errs
+
+
+# -------------------------------------------------------------- cube shadow
+def _slab(O, T, lo, hi):
+    """Kay-Kajiya: parameter interval of segment O->T inside the closed box."""
+    t0, t1 = -np.inf, np.inf
+    for ax in range(3):
+        d = T[ax] - O[ax]
+        if d == 0.0:
+            if O[ax] < lo[ax] or O[ax] > hi[ax]:
+                return None
+            continue
+        a, b = (lo[ax] - O[ax]) / d, (hi[ax] - O[ax]) / d
+        t0, t1 = max(t0, min(a, b)), min(t1, max(a, b))
+    return (t0, t1) if t0 <= t1 else None
+
+
+def _blocked_by_box(O, T, lo, hi):
+    """Does the open segment (0 < t < 1) meet the closed box?"""
+    iv = _slab(O, T, lo, hi)
+    return iv is not None and iv[0] < 1.0 and iv[1] > 0.0
+
+
+def test_cube_shadow_matches_slab_footprint():
+    w = wl.box_room()
+    v, t = w.mesh.verts, w.mesh.tris
+    c, n, _, _ = ref.elements(v, t)
+    x0, y0, _ = w.meta["cube_lo"]
+    lo = np.array([np.float32(x0), np.float32(y0), 0.0], np.float64)
+    hi = np.array([np.float32(x0 + 0.5), np.float32(y0 + 0.5), 0.5], np.float64)
+    rng = np.random.default_rng(11)
+    ks = rng.choice(w.K, 12, replace=False)
+    shell = np.arange(1040)
+    kk, ii = np.meshgrid(ks, shell, indexing="ij")
+    E, vis = ref.irradiance_pairs(v, t, w.poses, w.lamp.dz, w.lamp.power, kk.ravel(), ii.ravel())
+    eps = 1e-6
+    checked = shadowed = 0
+    for q, (k, i) in enumerate(zip(kk.ravel(), ii.ravel())):
+        O = np.array([w.poses[k, 0], w.poses[k, 1], np.float32(1.0)], np.float64)
+        T = c[i].astype(np.float64)
+        grow = _blocked_by_box(O, T, lo - eps, hi + eps)
+        shrink = _blocked_by_box(O, T, lo + eps, hi - eps)
+        if grow != shrink:
+            continue  # within 1e-6 of the shadow boundary
+        checked += 1
+        shadowed += grow
+        assert vis[q] == (0 if grow else 1), (k, i)
+    assert checked > 0.99 * len(vis) and shadowed > 50
+
+
+# ------------------------------------------------------- exact predicate pins
+def _adversarial_rays(rng, n):
+    """Rays aimed at the shared diagonal, edges and vertices of a unit quad
+    split into two triangles, with targets rounded to FP32 and nudged by a
+    few ulps."""
+    v = np.array([[0, 0, 0], [1, 0, 0], [1, 1, 0], [0, 1, 0]], np.float32)
+    v[:, 2] = 0.5
+    rot = rng.normal(size=(3, 3))
+    q, _ = np.linalg.qr(rot)
+    v = (v.astype(np.float64) @ q.T).astype(np.float32)
+    tris = np.array([[0, 1, 2], [0, 2, 3]], np.int32)
+    cases = []
+    for _ in range(n):
+        kind = rng.integers(4)
+        if kind == 0:      # on the shared diagonal
+            s = rng.uniform(0.05, 0.95)
+            P = (1 - s) * v[0].astype(np.float64) + s * v[2]
+        elif kind == 1:    # on an outer edge
+            e = rng.integers(4)
+            s = rng.uniform(0, 1)
+            P = (1 - s) * v[e].astype(np.float64) + s * v[(e + 1) % 4]
+        elif kind == 2:    # at a vertex
+            P = v[rng.integers(4)].astype(np.float64)
+        else:              # anywhere near the quad
+            P = (v[0] + rng.uniform(-0.2, 1.2) * (v[1] - v[0]) + rng.uniform(-0.2, 1.2) * (v[3] - v[0])).astype(np.float64)
+        normal = np.cross(v[1].astype(np.float64) - v[0], v[3].astype(np.float64) - v[0])
+        O = P + normal * rng.uniform(0.3, 2.0) + rng.normal(size=3) * 0.3
+        T = P - (O - P) * rng.uniform(0.2, 1.5)
+        T = T.astype(np.float32)
+        T = T + (rng.integers(-3, 4, size=3) * np.spacing(np.abs(T))).astype(np.float32)
+        cases.append((O.astype(np.float32), T.astype(np.float32)))
+    return v, tris, cases
+
+
+def test_fp64_predicate_agrees_with_exact_outside_band():
+    rng = np.random.default_rng(7)
+    v, tris, cases = _adversarial_rays(rng, 600)
+    disagree_outside = 0
+    for O, T in cases:
+        for tri in tris:
+            a, b, c = v[tri[0]], v[tri[1]], v[tri[2]]
+            h64 = ref.hit(O, T, a, b, c)
+            hx = exact.hit(O, T, a, b, c)
+            if h64 != hx and not exact.near_boundary(O, T, a, b, c, 1e-12):
+                disagree_outside += 1
+    assert disagree_outside == 0
+
+
+def test_shared_diagonal_is_watertight():
+    """A segment crossing the quad through its shared diagonal is blocked by
+    at least one of the two triangles, both exactly and in FP64."""
+    rng = np.random.default_rng(8)
+    v, tris, _ = _adversarial_rays(rng, 1)
+    normal = np.cross(v[1].astype(np.float64) - v[0], v[3].astype(np.float64) - v[0])
+    for _ in range(300):
+        s = rng.uniform(0.02, 0.98)
+        P = (1 - s) * v[0].astype(np.float64) + s * v[2]
+        O = (P + normal * rng.uniform(0.5, 2.0) + rng.normal(size=3) * 0.2).astype(np.float32)
+        T = (P - (O - P) * rng.uniform(0.3, 1.0)).astype(np.float32)
+        hits64 = [ref.hit(O, T, v[t[0]], v[t[1]], v[t[2]]) for t in tris]
+        hitsx = [exact.hit(O, T, v[t[0]], v[t[1]], v[t[2]]) for t in tris]
+        assert any(hits64) and any(hitsx)
+
+
+def test_hand_cases():
+    v0, v1, v2 = [0, 0, 0.5], [1, 0, 0.5], [0, 1, 0.5]
+    assert ref.hit([0.2, 0.2, 1], [0.2, 0.2, 0], v0, v1, v2) == 1      # straight through
+    assert ref.hit([0.2, 0.2, 1], [2.0, 2.0, 0], v0, v1, v2) == 0      # passes beside
+    assert ref.hit([0.2, 0.2, 1], [0.2, 0.2, 0.5], v0, v1, v2) == 0    # ends on the plane (open segment)
+    assert ref.hit([0.2, 0.2, 0.5], [0.2, 0.2, 0], v0, v1, v2) == 0    # starts on the plane
+    assert ref.hit([0.2, 0.2, 1], [0.2, 0.2, 0.9], v0, v1, v2) == 0    # stops short
+    assert ref.hit([0.0, 0.0, 1], [0.0, 0.0, 0], v0, v1, v2) == 1      # through a vertex (closed)
+    assert ref.hit([0.5, 0.0, 1], [0.5, 0.0, 0], v0, v1, v2) == 1      # through an edge (closed)
+    assert ref.hit([0.2, 0.2, 1], [0.2, 0.2, 0], v0, v1, [2, 0, 0.5]) == 0  # degenerate triangle
+    assert ref.hit([-1, 0.2, 0.5], [2, 0.2, 0.5], v0, v1, v2) == 0     # in the plane: never blocks
+    for O, T in (([0.3, 0.3, 2], [0.3, 0.1, -1]), ([0.9, 0.9, 1], [0.6, 0.6, 0])):
+        assert ref.hit(O, T, v0, v1, v2) == exact.hit(O, T, v0, v1, v2)
+
+
+# ------------------------------------------------------------- invariants
+@pytest.mark.parametrize("m", [-3, 2])
+def test_power_of_two_scaling(m):
+    w = wl.box_room()
+    s = np.float32(2.0 ** m)
+    ks = np.arange(0, w.K, 17)
+    kk, ii = np.meshgrid(ks, np.arange(w.N), indexing="ij")
+    E0, v0 = ref.irradiance_pairs(w.mesh.verts, w.mesh.tris, w.poses, w.lamp.dz, w.lamp.power, kk.ravel(), ii.ravel())
+    E1, v1 = ref.irradiance_pairs(w.mesh.verts * s, w.mesh.tris, w.poses * s, w.lamp.dz * s, w.lamp.power,
+                                  kk.ravel(), ii.ravel())
+    assert np.array_equal(v0, v1)
+    assert np.array_equal(E1 * 2.0 ** (2 * m), E0)
+
+
+def test_superposition_of_sources():
+    w = wl.ward()
+    rng = np.random.default_rng(3)
+    pk = rng.integers(0, w.K, 60)
+    pi = rng.integers(0, w.N, 60)
+    E, vis = ref.irradiance_pairs(w.mesh.verts, w.mesh.tris, w.poses, w.lamp.dz, w.lamp.power, pk, pi)
+    tot = np.zeros_like(E)
+    bits = np.zeros_like(vis)
+    for j in range(w.lamp.n_src):
+        Ej, vj = ref.irradiance_pairs(w.mesh.verts, w.mesh.tris, w.poses, w.lamp.dz[j:j + 1], w.lamp.power[j:j + 1],
+                                      pk, pi)
+        tot += Ej
+        bits |= vj << j
+    assert np.array_equal(bits, vis)
+    assert np.allclose(tot, E, rtol=1e-12, atol=0)
+
+
+def test_mirror_symmetry_x_equals_y():
+    """Room, cube and lamp symmetric under x <-> y: irradiance and shadow are
+    symmetric (the lattice triangulation maps onto itself under the swap)."""
+    L = (4.0, 4.0, 3.0)
+    mesh = _mesh(wl.box_surface((0, 0, 0), L, (10, 10, 8), inward=True),
+                 wl.box_surface((1.75, 1.75, 0.0), (2.25, 2.25, 0.5), (1, 1, 1), inward=False))
+    c, _, _, _ = ref.elements(mesh.verts, mesh.tris)
+    N = mesh.n_tris
+    key = {tuple(np.round(ci.astype(np.float64), 5)): i for i, ci in enumerate(c)}
+    perm = np.array([key[(round(float(ci[1]), 5), round(float(ci[0]), 5), round(float(ci[2]), 5))] for ci in c])
+    E, vis = ref.irradiance_pairs(mesh.verts, mesh.tris, np.array([[0.9, 0.9]], np.float32),
+                                  np.array([1.2], np.float32), np.array([80.0], np.float32),
+                                  np.zeros(N, np.int64), np.arange(N))
+    assert (vis == 0).sum() > 20   # the cube casts a shadow
+    assert np.array_equal(vis, vis[perm])
+    assert np.allclose(E, E[perm], rtol=2e-6, atol=0)
+
+
+def test_reciprocity_outside_band():
+    """V(p -> c) equals V(c -> p) except where the exact predicate is within
+    a tiny band of a decision boundary."""
+    w = wl.ward()
+    c, _, _, m = ref.elements(w.mesh.verts, w.mesh.tris)
+    rng = np.random.default_rng(4)
+    pk = rng.integers(0, w.K, 150)
+    pi = rng.integers(0, w.N, 150)
+    dz = w.lamp.dz[3:4]
+    E, vis = ref.irradiance_pairs(w.mesh.verts, w.mesh.tris, w.poses, dz, w.lamp.power[3:4], pk, pi)
+    n_front = 0
+    for q, (k, i) in enumerate(zip(pk, pi)):
+        p = np.array([w.poses[k, 0], w.poses[k, 1], dz[0]], np.float32)
+        front = float(np.dot(p.astype(np.float64) - c[i], m[i])) > 0
+        if not front:
+            assert vis[q] == 0
+            continue
+        n_front += 1
+        back = ref.segment_blocked(w.mesh.verts, w.mesh.tris, c[i], p, skip=i)
+        assert vis[q] == 1 - back
+    assert n_front > 30

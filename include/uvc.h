@@ -1,0 +1,195 @@
+/*
+ * uvc.h -- C ABI of the MI355X irradiance-matrix library.
+ *
+ * The library assembles the irradiance matrix of "Optimized Coverage Planning
+ * for UV Surface Disinfection" (arXiv 2103.14137): for K candidate lamp poses
+ * and the N triangles of a mesh, the irradiance that each triangle receives
+ * from a lamp dwelling at each pose (Sec. III-B, discrete irradiance; Sec.
+ * IV-C, inverse-square law with the visibility condition), and solves the
+ * relaxed dosage LP that consumes it (Sec. IV-D, relaxed LP).
+ *
+ * Matrix layout: the paper writes I_i(x_k) with one column per pose; this
+ * library stores it pose-major, E[k * N + i] = I_i(x_k), so one paper column
+ * is one row of E.
+ *
+ * Conventions for every entry point
+ *  - Every function returns uvc_status; nothing throws across the ABI.  On a
+ *    failure uvc_last_error() returns a thread-local message naming the cause.
+ *  - "dev" pointers are HIP device pointers on the current device; "host"
+ *    pointers are ordinary host memory.  Caller-owned buffers are borrowed for
+ *    the duration of the call only.  Scenes and CSR jobs are owned by the
+ *    library and released by their destroy functions.
+ *  - hip_stream is a hipStream_t (NULL = the default stream).  Work is
+ *    enqueued on it and the call returns without waiting, except where a
+ *    function says it synchronises.
+ *  - Inputs are validated before any kernel is launched: non-finite
+ *    coordinates, indices out of range, zero-area triangles, source counts
+ *    outside [1, 32] or non-positive powers return UVC_EINVAL.  K = 0 or
+ *    N = 0 succeed with empty output.
+ */
+#ifndef UVC_H
+#define UVC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    UVC_OK = 0,
+    UVC_EINVAL = -1,        /* invalid argument (message names it)          */
+    UVC_ENOMEM = -2,        /* device allocation failed                     */
+    UVC_EDEVICE = -3,       /* HIP runtime error                            */
+    UVC_ENOTCONV = -4,      /* LP iteration limit; best iterate returned    */
+    UVC_EUNSUPPORTED = -5   /* request outside what this build supports     */
+} uvc_status;
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char* uvc_last_error(void);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int32_t uvc_version(void);
+
+/* ------------------------------------------------------------------------
+ * Scene: the mesh, its surface elements and its bounding volume hierarchy.
+ * ------------------------------------------------------------------------ */
+typedef struct uvc_scene uvc_scene;
+
+/* Build a scene from a triangle mesh (Sec. III-B: the surface is a simplicial
+ * complex of N triangles, one surface element per triangle).
+ *   verts_xyz : n_verts x 3 FP32, row-major (x, y, z) in metres.
+ *   tri_idx   : n_tris x 3 int32 vertex indices.  The right-hand normal
+ *               (v1 - v0) x (v2 - v0) of every triangle must point into free
+ *               space, the side lamps are on.
+ *   inputs_on_device : 0 if both arrays are host memory, 1 if device memory
+ *               (they are copied to the host once for validation).
+ * The scene keeps its own copies; the inputs may be freed on return.  This
+ * call synchronises hip_stream.  Errors: UVC_EINVAL for non-finite vertices,
+ * indices outside [0, n_verts) or a triangle whose FP64 cross product is
+ * exactly zero (the message names the first such triangle); UVC_ENOMEM;
+ * UVC_EDEVICE. */
+uvc_status uvc_build_scene(const float* verts_xyz, int64_t n_verts,
+                           const int32_t* tri_idx, int64_t n_tris,
+                           int32_t inputs_on_device, void* hip_stream,
+                           uvc_scene** out);
+
+/* Scene facts: triangle count, depth of the hierarchy (root = 1) and the
+ * largest absolute vertex coordinate.  Any output pointer may be NULL. */
+uvc_status uvc_scene_info(const uvc_scene* scene, int64_t* n_tris,
+                          int32_t* bvh_depth, float* max_abs_coord);
+
+/* Surface elements in the input triangle order (Sec. III-B), into caller
+ * device buffers: centroid c_xyz (N x 3 FP32; the FP64 mean of the three
+ * vertices rounded once to FP32 -- the element's sampling point), unit
+ * normal n_xyz (N x 3 FP32) and area (N FP32).  Any pointer may be NULL. */
+uvc_status uvc_scene_elements(const uvc_scene* scene, float* c_xyz_dev,
+                              float* n_xyz_dev, float* area_dev,
+                              void* hip_stream);
+
+/* Copy the hierarchy to host buffers for inspection (tests):
+ *   nodes : (N - 1) x 16 FP32 -- per internal node the boxes of its two
+ *           children (lo xyz, hi xyz for left, then for right), the two child
+ *           references as int32 bit patterns (>= 0 internal node, < 0 leaf
+ *           slot ~ref), then two words of traversal hints;
+ *   perm  : N int32, the input triangle index stored in each leaf slot;
+ *   codes : N uint32, the sorted Morton codes.
+ * Any pointer may be NULL.  Synchronises hip_stream. */
+uvc_status uvc_scene_export_bvh(const uvc_scene* scene, float* nodes_host,
+                                int32_t* perm_host, uint32_t* codes_host,
+                                void* hip_stream);
+
+/* Release a scene (NULL is allowed).  Waits for the device to be idle. */
+void uvc_destroy_scene(uvc_scene* scene);
+
+/* ------------------------------------------------------------------------
+ * Irradiance matrix (Sec. IV-C).
+ * ------------------------------------------------------------------------ */
+
+/* A lamp is n_src point sources mounted dz[j] metres above the pose base
+ * point, each emitting power_w[j] watts isotropically (Sec. IV-C: an extended
+ * lamp as evenly distributed point sources of equal power).  Host arrays,
+ * copied by the call.  1 <= n_src <= 32, power_w[j] > 0, dz[j] finite. */
+typedef struct {
+    int32_t n_src;
+    const float* dz;
+    const float* power_w;
+} uvc_lamp;
+
+enum { UVC_PATH_AUTO = 0, UVC_PATH_LBVH = 1, UVC_PATH_BRUTE = 2 };
+
+/* Counters accumulated by an instrumented launch (opts.stats_dev). */
+enum {
+    UVC_STAT_RAYS = 0,       /* occlusion segments cast (front-facing triples) */
+    UVC_STAT_NODES = 1,      /* per-ray hierarchy node visits (2 child boxes)  */
+    UVC_STAT_TRIS = 2,       /* per-ray segment/triangle tests                 */
+    UVC_STAT_RECHECK = 3,    /* triangle decisions re-taken in FP64            */
+    UVC_STAT_FRONT64 = 4,    /* front-facing decisions re-taken in FP64        */
+    UVC_STAT_VISIBLE = 5,    /* visible (pose, source, element) triples        */
+    UVC_STAT_N = 8
+};
+
+typedef struct {
+    int32_t path;        /* UVC_PATH_*; AUTO picks the brute-force path for
+                            small meshes and the hierarchy otherwise          */
+    int32_t reserved0;
+    float band_scale;    /* multiplies the FP32 decision bands: 1 = default;
+                            +inf re-takes every decision in FP64 (slow);
+                            0 leaves only exact ties to FP64 (unsafe: FP32
+                            may then disagree with the exact predicate)       */
+    int32_t tile_tris;   /* brute-force path: triangles per LDS tile (0 = default) */
+    uint64_t* stats_dev; /* NULL, or UVC_STAT_N device counters that an
+                            instrumented (slower) kernel adds to              */
+} uvc_opts;
+
+/* Dense irradiance matrix.
+ *   poses_dev : K x pose_dim FP32 lamp base points, (x, y) with base height 0
+ *               or (x, y, z).  Source j of pose k sits at
+ *               (x_k, y_k, fl32(z_k + dz[j])).  Every source point must lie
+ *               within 2 * max_abs_coord of the origin (UVC_EINVAL otherwise).
+ *   E_dev     : K x N FP32, caller-owned, fully overwritten:
+ *               E[k*N + i] = sum over j ascending (FP32 adds) of
+ *                 V_kji * P_j * <p_kj - c_i, n_i> / (4 pi |p_kj - c_i|^3),
+ *               where V_kji = 1 iff <p_kj - c_i, n_i> > 0 and no triangle
+ *               other than i meets the open segment p_kj -> c_i (closed
+ *               triangles; the paper's visibility condition after its
+ *               inverse-square law).  A visible term is never below
+ *               FLT_MIN, so E[k*N+i] != 0 exactly when some V_kji = 1.
+ *   vis_dev   : NULL, or K x N uint32 with bit j = V_kji.
+ * Visibility is decided in FP32 where the FP32 value is provably on the same
+ * side of zero as the exact one, and re-decided in FP64 otherwise, so every
+ * bit equals the FP64 segment/triangle predicate.  Validates poses on the
+ * device and synchronises once before the main launch. */
+uvc_status uvc_compute_irradiance_dense(const uvc_scene* scene,
+                                        const float* poses_dev, int64_t K,
+                                        int32_t pose_dim, const uvc_lamp* lamp,
+                                        const uvc_opts* opts, float* E_dev,
+                                        uint32_t* vis_dev, void* hip_stream);
+
+/* CSR irradiance matrix (rows = poses, ascending columns, only entries with
+ * some V_kji = 1 stored), in two phases so that the caller owns the output.
+ * begin computes everything, keeps the compacted entries in library memory,
+ * returns the nonzero count and synchronises hip_stream.  finish writes
+ * row_ptr (K+1 int64), col (nnz int32) and val (nnz FP32, bit-identical to
+ * the dense values) into caller device buffers and releases the job.
+ * uvc_csr_job_destroy releases a job without finishing it. */
+typedef struct uvc_csr_job uvc_csr_job;
+
+uvc_status uvc_compute_irradiance_csr_begin(const uvc_scene* scene,
+                                            const float* poses_dev, int64_t K,
+                                            int32_t pose_dim,
+                                            const uvc_lamp* lamp,
+                                            const uvc_opts* opts,
+                                            void* hip_stream,
+                                            uvc_csr_job** job, int64_t* nnz);
+uvc_status uvc_compute_irradiance_csr_finish(uvc_csr_job* job,
+                                             int64_t* row_ptr_dev,
+                                             int32_t* col_dev, float* val_dev,
+                                             void* hip_stream);
+void uvc_csr_job_destroy(uvc_csr_job* job);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UVC_H */

@@ -1,0 +1,850 @@
+// Irradiance matrix assembly (Sec. IV-C): per (pose k, source j, element i)
+// the inverse-square, cosine-weighted point-source irradiance, counted when
+// the element faces the source and no other triangle meets the segment from
+// the source to the element's centroid.
+//
+// Work decomposition: one wavefront = one packet of 64 elements (consecutive
+// leaf slots, i.e. a compact patch in Morton order) for one pose; the wave
+// loops over the lamp's sources in ascending order, so all 64 occlusion
+// segments of a source share their origin.  Both occlusion paths keep the
+// control flow uniform across the wave:
+//  - hierarchy path: the packet walks the LBVH together; every node carries
+//    the 64-bit mask of lanes whose segment entered it, the stack of deferred
+//    (node, mask) pairs lives in three VGPRs indexed by lane, node and
+//    triangle records are read with uniform (scalar) loads;
+//  - brute-force path: the workgroup (4 packets, one pose) stages per-source
+//    triangle data -- the three edge cross products relative to the shared
+//    origin -- in LDS tiles, after which each segment/triangle edge test is
+//    three dot products per lane.
+// Every decision is taken in FP32 only when the FP32 value is provably on
+// the same side of zero as the exact one; otherwise the FP64 predicate is
+// evaluated with the same operations in the same order as its definition.
+#include "uvc_common.hpp"
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstring>
+
+namespace uvc {
+
+constexpr float INV_4PI = 0.0795774715459476678844f;  // 1 / (4 pi)
+
+struct LampArgs {
+    int32_t S;
+    float dz[32];
+    float pw[32];  // P_j / (4 pi)
+};
+
+struct IrrParams {
+    const float* tri;
+    const float* elem;
+    const float* nodes;
+    const float* poses;  // already offset to the first pose of the launch
+    int64_t K;           // poses in this launch
+    int64_t N;
+    int64_t ntiles;      // ceil(N / 64)
+    int64_t nquads;      // ceil(ntiles / 4)
+    int32_t pose_dim;
+    int32_t tile_tris;   // brute-force LDS tile
+    float tau_f, tau_e, tau_p;
+    float* E;            // rows of this launch, K x N
+    uint32_t* vis;       // NULL or K x N
+    unsigned long long* stats;
+    LampArgs lamp;
+};
+
+// ------------------------------------------------------------------ FP64
+// The segment/triangle predicate, evaluated in FP64 on the FP32 inputs:
+// open segment O->T, closed triangle v0 v1 v2.  Same operations and order as
+// its definition: m = (v1-v0) x (v2-v0); the plane sides (O-v0).m and
+// (T-v0).m must be strictly opposite; with D = T-O and a, b, c = v0-O,
+// v1-O, v2-O the edge orientations D.(b x c), D.(c x a), D.(a x b) must not
+// be of mixed strict sign.  Dot products are ((x x' + y y') + z z').
+__device__ __noinline__ bool seg_tri_fp64(float fox, float foy, float foz, float ftx, float fty, float ftz,
+                                          float f0x, float f0y, float f0z, float f1x, float f1y, float f1z,
+                                          float f2x, float f2y, float f2z) {
+#pragma clang fp contract(off)
+    const double ox = fox, oy = foy, oz = foz, tx = ftx, ty = fty, tz = ftz;
+    const double v0x = f0x, v0y = f0y, v0z = f0z, v1x = f1x, v1y = f1y, v1z = f1z, v2x = f2x, v2y = f2y, v2z = f2z;
+    const double e1x = v1x - v0x, e1y = v1y - v0y, e1z = v1z - v0z;
+    const double e2x = v2x - v0x, e2y = v2y - v0y, e2z = v2z - v0z;
+    const double mx = e1y * e2z - e1z * e2y;
+    const double my = e1z * e2x - e1x * e2z;
+    const double mz = e1x * e2y - e1y * e2x;
+    const double sO = ((ox - v0x) * mx + (oy - v0y) * my) + (oz - v0z) * mz;
+    const double sT = ((tx - v0x) * mx + (ty - v0y) * my) + (tz - v0z) * mz;
+    if (!((sO > 0.0 && sT < 0.0) || (sO < 0.0 && sT > 0.0))) return false;
+    const double Dx = tx - ox, Dy = ty - oy, Dz = tz - oz;
+    const double ax = v0x - ox, ay = v0y - oy, az = v0z - oz;
+    const double bx = v1x - ox, by = v1y - oy, bz = v1z - oz;
+    const double cx = v2x - ox, cy = v2y - oy, cz = v2z - oz;
+    const double bcx = by * cz - bz * cy, bcy = bz * cx - bx * cz, bcz = bx * cy - by * cx;
+    const double cax = cy * az - cz * ay, cay = cz * ax - cx * az, caz = cx * ay - cy * ax;
+    const double abx = ay * bz - az * by, aby = az * bx - ax * bz, abz = ax * by - ay * bx;
+    const double U = (Dx * bcx + Dy * bcy) + Dz * bcz;
+    const double V = (Dx * cax + Dy * cay) + Dz * caz;
+    const double W = (Dx * abx + Dy * aby) + Dz * abz;
+    const bool neg = (U < 0.0) || (V < 0.0) || (W < 0.0);
+    const bool pos = (U > 0.0) || (V > 0.0) || (W > 0.0);
+    return !(neg && pos);
+}
+
+// Front-facing test in FP64: (p - c) . ((v1-v0) x (v2-v0)) > 0, strict.
+__device__ __noinline__ bool front_fp64(float fpx, float fpy, float fpz, float fcx, float fcy, float fcz,
+                                        float f0x, float f0y, float f0z, float f1x, float f1y, float f1z,
+                                        float f2x, float f2y, float f2z) {
+#pragma clang fp contract(off)
+    const double v0x = f0x, v0y = f0y, v0z = f0z;
+    const double e1x = (double)f1x - v0x, e1y = (double)f1y - v0y, e1z = (double)f1z - v0z;
+    const double e2x = (double)f2x - v0x, e2y = (double)f2y - v0y, e2z = (double)f2z - v0z;
+    const double mx = e1y * e2z - e1z * e2y;
+    const double my = e1z * e2x - e1x * e2z;
+    const double mz = e1x * e2y - e1y * e2x;
+    const double dx = (double)fpx - (double)fcx, dy = (double)fpy - (double)fcy, dz = (double)fpz - (double)fcz;
+    return ((dx * mx + dy * my) + dz * mz) > 0.0;
+}
+
+// ------------------------------------------------------------------ FP32
+struct Ray {
+    float ox, oy, oz;     // origin: the source (uniform across the packet)
+    float dx, dy, dz;     // D = T - O
+    float ix, iy, iz;     // 1 / D, zero components replaced by +-1e-30
+    float nx, ny, nz;     // -O / D
+    float l1;             // |D|_1
+    float tx, ty, tz;     // target: the element centroid
+    int self;             // input index of the target's own triangle
+};
+
+__device__ __forceinline__ float max3f(float a, float b, float c) { return fmaxf(fmaxf(a, b), c); }
+__device__ __forceinline__ float min3f(float a, float b, float c) { return fminf(fminf(a, b), c); }
+__device__ __forceinline__ float amax3(float a, float b, float c) { return max3f(fabsf(a), fabsf(b), fabsf(c)); }
+
+__device__ __forceinline__ float guard_inv(float d) {
+    const float g = (fabsf(d) < 1e-30f) ? copysignf(1e-30f, d) : d;
+    return 1.0f / g;
+}
+
+__device__ __forceinline__ void make_ray(Ray& r, float ox, float oy, float oz, float tx, float ty, float tz,
+                                         int self) {
+    r.ox = ox; r.oy = oy; r.oz = oz;
+    r.tx = tx; r.ty = ty; r.tz = tz;
+    r.dx = tx - ox; r.dy = ty - oy; r.dz = tz - oz;
+    r.ix = guard_inv(r.dx); r.iy = guard_inv(r.dy); r.iz = guard_inv(r.dz);
+    r.nx = -ox * r.ix; r.ny = -oy * r.iy; r.nz = -oz * r.iz;
+    r.l1 = fabsf(r.dx) + fabsf(r.dy) + fabsf(r.dz);
+    r.self = self;
+}
+
+// Does the segment's parameter interval [0, 1] meet the (padded) box?
+__device__ __forceinline__ bool slab(const Ray& r, float lx, float ly, float lz, float hx, float hy, float hz) {
+    const float t0x = fmaf(lx, r.ix, r.nx), t1x = fmaf(hx, r.ix, r.nx);
+    const float t0y = fmaf(ly, r.iy, r.ny), t1y = fmaf(hy, r.iy, r.ny);
+    const float t0z = fmaf(lz, r.iz, r.nz), t1z = fmaf(hz, r.iz, r.nz);
+    const float tn = fmaxf(max3f(fminf(t0x, t1x), fminf(t0y, t1y), fminf(t0z, t1z)), 0.0f);
+    const float tf = fminf(min3f(fmaxf(t0x, t1x), fmaxf(t0y, t1y), fmaxf(t0z, t1z)), 1.0f);
+    return tn <= tf;
+}
+
+// Slow part of the triangle decision, reached when the edge orientations do
+// not already prove a miss: certain "inside" edges go on to the FP32 plane
+// test; any decision within its band is re-taken in FP64.
+// Returns bit 0 = hit, bit 1 = the decision was re-taken in FP64.
+__device__ __noinline__ int tri_rare(float rox, float roy, float roz, float rtx, float rty, float rtz, float v0x,
+                                     float v0y, float v0z, float v1x, float v1y, float v1z, float v2x, float v2y,
+                                     float v2z, float mn, float mx, float be, float tau_p) {
+    const bool inside = (mn > be) || (mx < -be);
+    if (inside) {
+        const float e1x = v1x - v0x, e1y = v1y - v0y, e1z = v1z - v0z;
+        const float e2x = v2x - v0x, e2y = v2y - v0y, e2z = v2z - v0z;
+        const float mx_ = fmaf(e1y, e2z, -e1z * e2y);
+        const float my_ = fmaf(e1z, e2x, -e1x * e2z);
+        const float mz_ = fmaf(e1x, e2y, -e1y * e2x);
+        const float gm = amax3(e1x, e1y, e1z) * amax3(e2x, e2y, e2z);
+        const float wox = rox - v0x, woy = roy - v0y, woz = roz - v0z;
+        const float wtx = rtx - v0x, wty = rty - v0y, wtz = rtz - v0z;
+        const float sO = fmaf(woz, mz_, fmaf(woy, my_, wox * mx_));
+        const float sT = fmaf(wtz, mz_, fmaf(wty, my_, wtx * mx_));
+        const float bO = tau_p * amax3(wox, woy, woz) * gm;
+        const float bT = tau_p * amax3(wtx, wty, wtz) * gm;
+        if (fabsf(sO) > bO && fabsf(sT) > bT) return ((sO > 0.0f) != (sT > 0.0f)) ? 1 : 0;
+    }
+    return 2 | (seg_tri_fp64(rox, roy, roz, rtx, rty, rtz, v0x, v0y, v0z, v1x, v1y, v1z, v2x, v2y, v2z) ? 1 : 0);
+}
+
+// Full per-lane triangle decision for the hierarchy path.  The vertex
+// differences and cross products are the same for every lane (shared
+// origin); only the three dot products with D are per lane.
+__device__ __forceinline__ bool tri_hit(const Ray& r, float v0x, float v0y, float v0z, float v1x, float v1y,
+                                        float v1z, float v2x, float v2y, float v2z, float tau_e, float tau_p,
+                                        int* rechecks) {
+    const float ax = v0x - r.ox, ay = v0y - r.oy, az = v0z - r.oz;
+    const float bx = v1x - r.ox, by = v1y - r.oy, bz = v1z - r.oz;
+    const float cx = v2x - r.ox, cy = v2y - r.oy, cz = v2z - r.oz;
+    const float ux = fmaf(by, cz, -bz * cy), uy = fmaf(bz, cx, -bx * cz), uz = fmaf(bx, cy, -by * cx);
+    const float vx = fmaf(cy, az, -cz * ay), vy = fmaf(cz, ax, -cx * az), vz = fmaf(cx, ay, -cy * ax);
+    const float wx = fmaf(ay, bz, -az * by), wy = fmaf(az, bx, -ax * bz), wz = fmaf(ax, by, -ay * bx);
+    const float g = max3f(amax3(ax, ay, az), amax3(bx, by, bz), amax3(cx, cy, cz));
+    const float U = fmaf(r.dz, uz, fmaf(r.dy, uy, r.dx * ux));
+    const float V = fmaf(r.dz, vz, fmaf(r.dy, vy, r.dx * vx));
+    const float W = fmaf(r.dz, wz, fmaf(r.dy, wy, r.dx * wx));
+    const float be = (tau_e * g * g) * r.l1;
+    const float mn = min3f(U, V, W), mx = max3f(U, V, W);
+    if (mn < -be && mx > be) return false;
+    const int q = tri_rare(r.ox, r.oy, r.oz, r.tx, r.ty, r.tz, v0x, v0y, v0z, v1x, v1y, v1z, v2x, v2y, v2z, mn, mx,
+                           be, tau_p);
+    *rechecks += q >> 1;
+    return (q & 1) != 0;
+}
+
+// Irradiance term of one visible source: P_j/(4 pi) * <d, n> / |d|^3, never
+// below FLT_MIN (the exact term of a visible source is positive).  Written
+// with explicit FMAs and no contraction so that every kernel produces the
+// same bits.
+__device__ __forceinline__ float entry_term(float dx, float dy, float dz, float s, float pw) {
+#pragma clang fp contract(off)
+    const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    const float w = (pw * fmaxf(s, 0.0f)) * ((ri * ri) * ri);
+    return fmaxf(w, FLT_MIN);
+}
+
+__device__ __forceinline__ float cos_numerator(float dx, float dy, float dz, float nx, float ny, float nz) {
+#pragma clang fp contract(off)
+    return __builtin_fmaf(dz, nz, __builtin_fmaf(dy, ny, dx * nx));
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+
+__device__ __forceinline__ unsigned long long wave_sum_u32(unsigned v) {
+    unsigned long long s = v;
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    return s;
+}
+
+// Workgroup (4 packets) -> (pose, quad of tiles), spreading consecutive
+// logical workgroups over the 8 XCDs in contiguous ranges so that each XCD's
+// L2 serves a compact region of the element space.
+__device__ __forceinline__ void block_coords(const IrrParams& P, int64_t& kk, int64_t& quad) {
+    const uint64_t B = gridDim.x, b = blockIdx.x;
+    const uint64_t xcd = b & 7u, loc = b >> 3, per = B >> 3, rem = B & 7u;
+    const uint64_t logical = xcd * per + (xcd < rem ? xcd : rem) + loc;
+    kk = (int64_t)(logical % (uint64_t)P.K);
+    quad = (int64_t)(logical / (uint64_t)P.K);
+}
+
+struct ElemLane {
+    float cx, cy, cz, nx, ny, nz;
+    int self;
+    bool valid;
+};
+
+__device__ __forceinline__ ElemLane load_elem(const IrrParams& P, int64_t slot) {
+    ElemLane e;
+    e.valid = slot < P.N;
+    if (e.valid) {
+        const float4* q = reinterpret_cast<const float4*>(P.elem + slot * ELEM_WORDS);
+        const float4 a = q[0], b = q[1];
+        e.cx = a.x; e.cy = a.y; e.cz = a.z; e.nx = a.w; e.ny = b.x; e.nz = b.y;
+        e.self = __float_as_int(b.z);
+    } else {
+        e.cx = e.cy = e.cz = e.nx = e.ny = e.nz = 0.f;
+        e.self = -1;
+    }
+    return e;
+}
+
+// Front-facing decision for the lane's element: FP32 with band, FP64 inside.
+__device__ __forceinline__ bool front_face(const IrrParams& P, const ElemLane& e, int64_t slot, float ox, float oy,
+                                           float oz, float dx, float dy, float dz, float s, int* f64) {
+    const float l1 = fabsf(dx) + fabsf(dy) + fabsf(dz);
+    if (fabsf(s) > P.tau_f * l1) return s > 0.0f;
+    ++*f64;
+    const float* t = P.tri + slot * TRI_WORDS;
+    return front_fp64(ox, oy, oz, e.cx, e.cy, e.cz, t[0], t[1], t[2], t[3], t[4], t[5], t[6], t[7], t[8]);
+}
+
+// ------------------------------------------------------------ hierarchy
+template <bool STATS>
+__device__ __forceinline__ unsigned long long traverse(const IrrParams& P, const Ray& r, unsigned long long live,
+                                                       unsigned long long& n_nodes, unsigned long long& n_tris,
+                                                       int* rechecks) {
+    const int lane = lane_id();
+    unsigned long long occl = 0;
+    if (P.N < 2) return 0;
+    int node = 0;
+    unsigned long long m = live;
+    int sp = 0;
+    int stk_node = 0, stk_lo = 0, stk_hi = 0;
+    const float* __restrict__ nodes = P.nodes;
+    const float* __restrict__ tri = P.tri;
+    while (true) {
+        const float4* q = reinterpret_cast<const float4*>(nodes + (int64_t)node * NODE_WORDS);
+        const float4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
+        const bool in_m = (m >> lane) & 1ull;
+        const bool hL = in_m && slab(r, q0.x, q0.y, q0.z, q0.w, q1.x, q1.y);
+        const bool hR = in_m && slab(r, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w);
+        unsigned long long mL = __ballot(hL), mR = __ballot(hR);
+        const int cl = __float_as_int(q3.x), cr = __float_as_int(q3.y);
+        if (STATS) n_nodes += (unsigned long long)__popcll(m);
+        if (cl < 0 && mL) {
+            const float* t = tri + (int64_t)(~cl) * TRI_WORDS;
+            const int who = __float_as_int(t[9]);
+            const bool act = ((mL >> lane) & 1ull) && r.self != who;
+            bool h = false;
+            if (act) h = tri_hit(r, t[0], t[1], t[2], t[3], t[4], t[5], t[6], t[7], t[8], P.tau_e, P.tau_p, rechecks);
+            if (STATS) n_tris += (unsigned long long)__popcll(__ballot(act));
+            occl |= __ballot(h);
+            mL = 0;
+        }
+        if (cr < 0 && mR) {
+            const float* t = tri + (int64_t)(~cr) * TRI_WORDS;
+            const int who = __float_as_int(t[9]);
+            const bool act = ((mR >> lane) & 1ull) && r.self != who;
+            bool h = false;
+            if (act) h = tri_hit(r, t[0], t[1], t[2], t[3], t[4], t[5], t[6], t[7], t[8], P.tau_e, P.tau_p, rechecks);
+            if (STATS) n_tris += (unsigned long long)__popcll(__ballot(act));
+            occl |= __ballot(h);
+            mR = 0;
+        }
+        mL &= ~occl;
+        mR &= ~occl;
+        if (mL && mR) {
+            const int hint = __float_as_int(q3.z);
+            const int axis = hint & 3;
+            const float o = axis == 0 ? r.ox : (axis == 1 ? r.oy : r.oz);
+            const bool left_first = ((o < q3.w) == ((hint & 4) != 0));
+            const int nnear = left_first ? cl : cr, nfar = left_first ? cr : cl;
+            const unsigned long long mnear = left_first ? mL : mR, mfar = left_first ? mR : mL;
+            const bool here = lane == sp;  // the stack entry sp lives in lane sp
+            stk_node = here ? nfar : stk_node;
+            stk_lo = here ? (int)(unsigned)mfar : stk_lo;
+            stk_hi = here ? (int)(unsigned)(mfar >> 32) : stk_hi;
+            ++sp;
+            node = nnear;
+            m = mnear;
+        } else if (mL) {
+            node = cl;
+            m = mL;
+        } else if (mR) {
+            node = cr;
+            m = mR;
+        } else {
+            bool done = false;
+            while (true) {
+                if (sp == 0) {
+                    done = true;
+                    break;
+                }
+                --sp;
+                node = __builtin_amdgcn_readlane(stk_node, sp);
+                const unsigned lo = (unsigned)__builtin_amdgcn_readlane(stk_lo, sp);
+                const unsigned hi = (unsigned)__builtin_amdgcn_readlane(stk_hi, sp);
+                m = (((unsigned long long)hi << 32) | lo) & ~occl;
+                if (m) break;
+            }
+            if (done) break;
+        }
+        if ((live & ~occl) == 0ull) break;
+    }
+    return occl;
+}
+
+template <bool STATS>
+__global__ __launch_bounds__(256) void k_irr_lbvh(IrrParams P) {
+    int64_t kk, quad;
+    block_coords(P, kk, quad);
+    const int lane = lane_id(), w = (int)(threadIdx.x >> 6);
+    const int64_t tile = quad * 4 + w;
+    if (tile >= P.ntiles) return;
+    const int64_t slot = tile * 64 + lane;
+    const ElemLane e = load_elem(P, slot);
+    const float* pp = P.poses + kk * P.pose_dim;
+    const float px = pp[0], py = pp[1], pz0 = (P.pose_dim == 3) ? pp[2] : 0.0f;
+    float acc = 0.0f;
+    uint32_t bits = 0;
+    int rechecks = 0, f64 = 0;
+    unsigned long long n_rays = 0, n_nodes = 0, n_tris = 0, n_vis = 0;
+    for (int j = 0; j < P.lamp.S; ++j) {
+        const float oz = pz0 + P.lamp.dz[j];
+        const float dx = px - e.cx, dy = py - e.cy, dz = oz - e.cz;
+        const float s = cos_numerator(dx, dy, dz, e.nx, e.ny, e.nz);
+        bool f = false;
+        if (e.valid) f = front_face(P, e, slot, px, py, oz, dx, dy, dz, s, &f64);
+        const unsigned long long live = __ballot(f);
+        if (!live) continue;
+        Ray r;
+        make_ray(r, px, py, oz, e.cx, e.cy, e.cz, e.self);
+        const unsigned long long occl = traverse<STATS>(P, r, live, n_nodes, n_tris, &rechecks);
+        const bool vis = f && !((occl >> lane) & 1ull);
+        if (STATS) {
+            n_rays += (unsigned long long)__popcll(live);
+            n_vis += (unsigned long long)__popcll(__ballot(vis));
+        }
+        if (vis) {
+            acc = acc + entry_term(dx, dy, dz, s, P.lamp.pw[j]);
+            bits |= 1u << j;
+        }
+    }
+    if (e.valid) {
+        P.E[kk * P.N + e.self] = acc;
+        if (P.vis) P.vis[kk * P.N + e.self] = bits;
+    }
+    if (STATS) {
+        const unsigned long long rc = wave_sum_u32((unsigned)rechecks), fc = wave_sum_u32((unsigned)f64);
+        if (lane == 0) {
+            atomicAdd(P.stats + UVC_STAT_RAYS, n_rays);
+            atomicAdd(P.stats + UVC_STAT_NODES, n_nodes);
+            atomicAdd(P.stats + UVC_STAT_TRIS, n_tris);
+            atomicAdd(P.stats + UVC_STAT_RECHECK, rc);
+            atomicAdd(P.stats + UVC_STAT_FRONT64, fc);
+            atomicAdd(P.stats + UVC_STAT_VISIBLE, n_vis);
+        }
+    }
+}
+
+// ---------------------------------------------------------- brute force
+template <bool STATS>
+__global__ __launch_bounds__(256) void k_irr_brute(IrrParams P) {
+    extern __shared__ float4 lds[];  // tile_tris x 3 float4
+    int64_t kk, quad;
+    block_coords(P, kk, quad);
+    const int lane = lane_id(), w = (int)(threadIdx.x >> 6), tid = (int)threadIdx.x;
+    const int64_t tile = quad * 4 + w;
+    const int64_t slot = tile * 64 + lane;
+    const ElemLane e = load_elem(P, slot);  // invalid lanes (and whole waves past the end) idle
+    const float* pp = P.poses + kk * P.pose_dim;
+    const float px = pp[0], py = pp[1], pz0 = (P.pose_dim == 3) ? pp[2] : 0.0f;
+    const int TT = P.tile_tris;
+    float acc = 0.0f;
+    uint32_t bits = 0;
+    int rechecks = 0, f64 = 0;
+    unsigned long long n_rays = 0, n_tris = 0, n_vis = 0;
+    for (int j = 0; j < P.lamp.S; ++j) {
+        const float oz = pz0 + P.lamp.dz[j];
+        const float dx = px - e.cx, dy = py - e.cy, dz = oz - e.cz;
+        const float s = cos_numerator(dx, dy, dz, e.nx, e.ny, e.nz);
+        bool f = false;
+        if (e.valid) f = front_face(P, e, slot, px, py, oz, dx, dy, dz, s, &f64);
+        const unsigned long long live = __ballot(f);
+        Ray r;
+        make_ray(r, px, py, oz, e.cx, e.cy, e.cz, e.self);
+        bool occluded = false;
+        const int any_live = __syncthreads_or(live != 0ull);
+        if (any_live) {
+            for (int64_t base = 0; base < P.N; base += TT) {
+                const int cnt = (int)((P.N - base) < TT ? (P.N - base) : TT);
+                __syncthreads();
+                for (int t = tid; t < cnt; t += 256) {
+                    const float* tp = P.tri + (base + t) * TRI_WORDS;
+                    const float4 q0 = reinterpret_cast<const float4*>(tp)[0];
+                    const float4 q1 = reinterpret_cast<const float4*>(tp)[1];
+                    const float4 q2 = reinterpret_cast<const float4*>(tp)[2];
+                    const float ax = q0.x - px, ay = q0.y - py, az = q0.z - oz;
+                    const float bx = q0.w - px, by = q1.x - py, bz = q1.y - oz;
+                    const float cx = q1.z - px, cy = q1.w - py, cz = q2.x - oz;
+                    const float g = max3f(amax3(ax, ay, az), amax3(bx, by, bz), amax3(cx, cy, cz));
+                    float4 o0, o1, o2;
+                    o0.x = fmaf(by, cz, -bz * cy); o0.y = fmaf(bz, cx, -bx * cz); o0.z = fmaf(bx, cy, -by * cx);
+                    o0.w = fmaf(cy, az, -cz * ay); o1.x = fmaf(cz, ax, -cx * az); o1.y = fmaf(cx, ay, -cy * ax);
+                    o1.z = fmaf(ay, bz, -az * by); o1.w = fmaf(az, bx, -ax * bz); o2.x = fmaf(ax, by, -ay * bx);
+                    o2.y = P.tau_e * g * g;
+                    o2.z = q2.y;  // input index (int bits)
+                    o2.w = 0.f;
+                    lds[3 * t + 0] = o0;
+                    lds[3 * t + 1] = o1;
+                    lds[3 * t + 2] = o2;
+                }
+                __syncthreads();
+                for (int t0 = 0; t0 < cnt; t0 += 32) {
+                    const unsigned long long act = live & ~__ballot(occluded);
+                    if (!act) break;
+                    const int t1 = (cnt - t0) < 32 ? cnt : t0 + 32;
+                    if (STATS) n_tris += (unsigned long long)__popcll(act) * (unsigned long long)(t1 - t0);
+                    for (int t = t0; t < t1; ++t) {
+                        const float4 o0 = lds[3 * t + 0], o1 = lds[3 * t + 1], o2 = lds[3 * t + 2];
+                        const float U = fmaf(r.dz, o0.z, fmaf(r.dy, o0.y, r.dx * o0.x));
+                        const float V = fmaf(r.dz, o1.y, fmaf(r.dy, o1.x, r.dx * o0.w));
+                        const float W = fmaf(r.dz, o2.x, fmaf(r.dy, o1.w, r.dx * o1.z));
+                        const float be = o2.y * r.l1;
+                        const float mn = min3f(U, V, W), mx = max3f(U, V, W);
+                        if (!(mn < -be && mx > be) && f && !occluded && __float_as_int(o2.z) != e.self) {
+                            const float* tp = P.tri + (base + t) * TRI_WORDS;
+                            const int q = tri_rare(r.ox, r.oy, r.oz, r.tx, r.ty, r.tz, tp[0], tp[1], tp[2], tp[3],
+                                                   tp[4], tp[5], tp[6], tp[7], tp[8], mn, mx, be, P.tau_p);
+                            rechecks += q >> 1;
+                            occluded = (q & 1) != 0;
+                        }
+                    }
+                }
+            }
+        }
+        const bool vis = f && !occluded;
+        if (STATS) {
+            n_rays += (unsigned long long)__popcll(live);
+            n_vis += (unsigned long long)__popcll(__ballot(vis));
+        }
+        if (vis) {
+            acc = acc + entry_term(dx, dy, dz, s, P.lamp.pw[j]);
+            bits |= 1u << j;
+        }
+    }
+    if (e.valid) {
+        P.E[kk * P.N + e.self] = acc;
+        if (P.vis) P.vis[kk * P.N + e.self] = bits;
+    }
+    if (STATS) {
+        const unsigned long long rc = wave_sum_u32((unsigned)rechecks), fc = wave_sum_u32((unsigned)f64);
+        if (lane == 0) {
+            atomicAdd(P.stats + UVC_STAT_RAYS, n_rays);
+            atomicAdd(P.stats + UVC_STAT_TRIS, n_tris);
+            atomicAdd(P.stats + UVC_STAT_RECHECK, rc);
+            atomicAdd(P.stats + UVC_STAT_FRONT64, fc);
+            atomicAdd(P.stats + UVC_STAT_VISIBLE, n_vis);
+        }
+    }
+}
+
+// ------------------------------------------------------------ validation
+__global__ void k_pose_check(const float* __restrict__ poses, int64_t K, int pd, float dzmin, float dzmax, float lim,
+                             unsigned* __restrict__ flag) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    const float x = poses[k * pd], y = poses[k * pd + 1], z = (pd == 3) ? poses[k * pd + 2] : 0.0f;
+    unsigned f = 0;
+    if (!isfinite(x) || !isfinite(y) || !isfinite(z)) f |= 1u;
+    const float z0 = z + dzmin, z1 = z + dzmax;
+    if (fabsf(x) > lim || fabsf(y) > lim || fabsf(z0) > lim || fabsf(z1) > lim) f |= 2u;
+    if (f) atomicOr(flag, f);
+}
+
+// ------------------------------------------------------------ CSR pieces
+// One wave per row: number of nonzero entries.
+__global__ void k_row_count(const float* __restrict__ E, int64_t rows, int64_t N, int64_t* __restrict__ counts) {
+    const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int lane = lane_id();
+    if (row >= rows) return;
+    const float* e = E + row * N;
+    unsigned long long c = 0;
+    for (int64_t base = 0; base < N; base += 64) {
+        const int64_t i = base + lane;
+        const bool nz = i < N && e[i] != 0.0f;
+        c += (unsigned long long)__popcll(__ballot(nz));
+    }
+    if (lane == 0) counts[row] = (int64_t)c;
+}
+
+// Exclusive scan of n int64 counts into out[0..n] (out[n] = total), plus a
+// base offset; one block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_scan_i64(const int64_t* __restrict__ in, int64_t* __restrict__ out,
+                                                   int64_t n, int64_t base) {
+    __shared__ int64_t part[1024];
+    __shared__ int64_t carry;
+    const int tid = threadIdx.x;
+    if (tid == 0) carry = base;
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < n; b0 += 1024) {
+        const int64_t i = b0 + tid;
+        const int64_t v = (i < n) ? in[i] : 0;
+        part[tid] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const int64_t t = (tid >= off) ? part[tid - off] : 0;
+            __syncthreads();
+            part[tid] += t;
+            __syncthreads();
+        }
+        if (i < n) out[i] = carry + part[tid] - v;
+        __syncthreads();
+        if (tid == 1023) carry += part[1023];
+        __syncthreads();
+    }
+    if (tid == 0) out[n] = carry;
+}
+
+// One wave per row: write the row's nonzeros in ascending column order.
+__global__ void k_row_gather(const float* __restrict__ E, int64_t rows, int64_t N, const int64_t* __restrict__ offs,
+                             int32_t* __restrict__ col, float* __restrict__ val) {
+    const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int lane = lane_id();
+    if (row >= rows) return;
+    const float* e = E + row * N;
+    int64_t pos = offs[row];
+    const unsigned long long lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    for (int64_t base = 0; base < N; base += 64) {
+        const int64_t i = base + lane;
+        const float v = (i < N) ? e[i] : 0.0f;
+        const bool nz = v != 0.0f;
+        const unsigned long long mk = __ballot(nz);
+        if (nz) {
+            const int64_t p = pos + __popcll(mk & lt);
+            col[p] = (int32_t)i;
+            val[p] = v;
+        }
+        pos += __popcll(mk);
+    }
+}
+
+// ------------------------------------------------------------------ host
+static uvc_status make_params(const uvc_scene* s, const float* poses, int64_t K, int32_t pd, const uvc_lamp* lamp,
+                              const uvc_opts* opts, IrrParams& P) {
+    if (!s) return fail(UVC_EINVAL, "scene is NULL");
+    if (K < 0) return fail(UVC_EINVAL, "K < 0");
+    if (pd != 2 && pd != 3) return fail(UVC_EINVAL, "pose_dim must be 2 or 3");
+    if (!lamp || lamp->n_src < 1 || lamp->n_src > 32 || !lamp->dz || !lamp->power_w)
+        return fail(UVC_EINVAL, "lamp must have 1..32 sources with dz and power arrays");
+    if (K > 0 && s->n > 0 && !poses) return fail(UVC_EINVAL, "poses is NULL");
+    std::memset(&P, 0, sizeof(P));
+    P.lamp.S = lamp->n_src;
+    for (int j = 0; j < lamp->n_src; ++j) {
+        if (!std::isfinite(lamp->dz[j])) return fail(UVC_EINVAL, "lamp dz[" + std::to_string(j) + "] is not finite");
+        if (!(lamp->power_w[j] > 0.f) || !std::isfinite(lamp->power_w[j]))
+            return fail(UVC_EINVAL, "lamp power[" + std::to_string(j) + "] must be positive and finite");
+        P.lamp.dz[j] = lamp->dz[j];
+        P.lamp.pw[j] = (float)((double)lamp->power_w[j] / (4.0 * M_PI));
+    }
+    const float bs = opts ? opts->band_scale : 1.0f;
+    if (!(bs >= 0.f)) return fail(UVC_EINVAL, "band_scale must be >= 0");
+    P.tau_f = TAU_F * bs;
+    P.tau_e = TAU_E * bs;
+    P.tau_p = TAU_P * bs;
+    P.tri = s->tri;
+    P.elem = s->elem;
+    P.nodes = s->nodes;
+    P.poses = poses;
+    P.K = K;
+    P.N = s->n;
+    P.pose_dim = pd;
+    P.ntiles = (s->n + 63) / 64;
+    P.nquads = (P.ntiles + 3) / 4;
+    P.tile_tris = (opts && opts->tile_tris > 0) ? opts->tile_tris : 512;
+    if (P.tile_tris > 2048) return fail(UVC_EINVAL, "tile_tris must be <= 2048");
+    P.stats = opts ? reinterpret_cast<unsigned long long*>(opts->stats_dev) : nullptr;
+    return UVC_OK;
+}
+
+static uvc_status check_poses(const uvc_scene* s, const float* poses, int64_t K, int pd, const LampArgs& L,
+                              hipStream_t st) {
+    if (K == 0) return UVC_OK;
+    float dzmin = L.dz[0], dzmax = L.dz[0];
+    for (int j = 1; j < L.S; ++j) {
+        dzmin = std::min(dzmin, L.dz[j]);
+        dzmax = std::max(dzmax, L.dz[j]);
+    }
+    const float lim = 2.0f * std::max(s->max_abs, 1e-30f);
+    unsigned* flag = nullptr;
+    UVC_TRY(dalloc_n(&flag, 1, "pose check flag"));
+    unsigned h = 0;
+    hipError_t e = hipMemsetAsync(flag, 0, 4, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_pose_check, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st, poses, K, pd, dzmin,
+                           dzmax, lim, flag);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(flag);
+    if (e != hipSuccess) return fail(UVC_EDEVICE, std::string("pose validation: ") + hipGetErrorString(e));
+    if (h & 1u) return fail(UVC_EINVAL, "a pose coordinate is not finite");
+    if (h & 2u) return fail(UVC_EINVAL, "a source point lies farther than 2 * max_abs_coord from the origin");
+    return UVC_OK;
+}
+
+static int choose_path(const uvc_scene* s, const uvc_opts* opts) {
+    const int p = opts ? opts->path : UVC_PATH_AUTO;
+    if (p == UVC_PATH_LBVH || p == UVC_PATH_BRUTE) return p;
+    return s->n <= 2048 ? UVC_PATH_BRUTE : UVC_PATH_LBVH;
+}
+
+// Launch the irradiance kernel for P.K poses into P.E / P.vis.
+static uvc_status launch_irr(const IrrParams& P, int path, hipStream_t st) {
+    if (P.K == 0 || P.N == 0) return UVC_OK;
+    const uint64_t blocks = (uint64_t)P.nquads * (uint64_t)P.K;
+    if (blocks > 0x7fffffffull) return fail(UVC_EUNSUPPORTED, "launch too large; split the poses");
+    const bool stats = P.stats != nullptr;
+    if (path == UVC_PATH_BRUTE) {
+        const size_t shm = (size_t)P.tile_tris * 48;
+        if (stats)
+            hipLaunchKernelGGL(k_irr_brute<true>, dim3((unsigned)blocks), dim3(256), shm, st, P);
+        else
+            hipLaunchKernelGGL(k_irr_brute<false>, dim3((unsigned)blocks), dim3(256), shm, st, P);
+    } else {
+        if (stats)
+            hipLaunchKernelGGL(k_irr_lbvh<true>, dim3((unsigned)blocks), dim3(256), 0, st, P);
+        else
+            hipLaunchKernelGGL(k_irr_lbvh<false>, dim3((unsigned)blocks), dim3(256), 0, st, P);
+    }
+    UVC_HIP(hipGetLastError());
+    return UVC_OK;
+}
+
+}  // namespace uvc
+
+using namespace uvc;
+
+struct uvc_csr_job {
+    int device = 0;
+    int64_t K = 0, N = 0, nnz = 0;
+    int64_t* counts = nullptr;  // K row counts (device)
+    struct Chunk {
+        int32_t* col;
+        float* val;
+        int64_t nnz;
+    };
+    std::vector<Chunk> chunks;
+};
+
+extern "C" uvc_status uvc_compute_irradiance_dense(const uvc_scene* scene, const float* poses_dev, int64_t K,
+                                                   int32_t pose_dim, const uvc_lamp* lamp, const uvc_opts* opts,
+                                                   float* E_dev, uint32_t* vis_dev, void* hip_stream) {
+    IrrParams P;
+    UVC_TRY(make_params(scene, poses_dev, K, pose_dim, lamp, opts, P));
+    if (K == 0 || scene->n == 0) return UVC_OK;
+    if (!E_dev) return fail(UVC_EINVAL, "E is NULL");
+    hipStream_t st = (hipStream_t)hip_stream;
+    UVC_TRY(check_poses(scene, poses_dev, K, pose_dim, P.lamp, st));
+    P.E = E_dev;
+    P.vis = vis_dev;
+    return launch_irr(P, choose_path(scene, opts), st);
+}
+
+static void free_job(uvc_csr_job* j) {
+    if (!j) return;
+    if (j->counts) (void)hipFree(j->counts);
+    for (auto& c : j->chunks) {
+        if (c.col) (void)hipFree(c.col);
+        if (c.val) (void)hipFree(c.val);
+    }
+    delete j;
+}
+
+extern "C" uvc_status uvc_compute_irradiance_csr_begin(const uvc_scene* scene, const float* poses_dev, int64_t K,
+                                                       int32_t pose_dim, const uvc_lamp* lamp, const uvc_opts* opts,
+                                                       void* hip_stream, uvc_csr_job** job, int64_t* nnz) {
+    if (!job || !nnz) return fail(UVC_EINVAL, "job / nnz output is NULL");
+    *job = nullptr;
+    *nnz = 0;
+    IrrParams P;
+    UVC_TRY(make_params(scene, poses_dev, K, pose_dim, lamp, opts, P));
+    hipStream_t st = (hipStream_t)hip_stream;
+    uvc_csr_job* J = new uvc_csr_job();
+    (void)hipGetDevice(&J->device);
+    J->K = K;
+    J->N = scene->n;
+    if (K == 0 || scene->n == 0) {
+        uvc_status r = dalloc_n(&J->counts, (size_t)std::max<int64_t>(K, 1), "row counts");
+        if (r != UVC_OK) {
+            free_job(J);
+            return r;
+        }
+        if (K > 0 && hipMemsetAsync(J->counts, 0, (size_t)K * 8, st) != hipSuccess) {
+            free_job(J);
+            return fail(UVC_EDEVICE, "hipMemsetAsync failed");
+        }
+        *job = J;
+        return UVC_OK;
+    }
+    uvc_status r = check_poses(scene, poses_dev, K, pose_dim, P.lamp, st);
+    if (r != UVC_OK) {
+        free_job(J);
+        return r;
+    }
+    const int64_t N = scene->n;
+    const int64_t budget = (int64_t)1 << 28;  // dense scratch entries per batch
+    const int64_t Kb = std::max<int64_t>(1, std::min<int64_t>(K, budget / N));
+    float* scratch = nullptr;
+    int64_t* offs = nullptr;
+    if ((r = dalloc_n(&J->counts, (size_t)K, "row counts")) != UVC_OK ||
+        (r = dalloc_n(&scratch, (size_t)Kb * N, "dense batch scratch")) != UVC_OK ||
+        (r = dalloc_n(&offs, (size_t)Kb + 1, "batch offsets")) != UVC_OK) {
+        if (scratch) (void)hipFree(scratch);
+        if (offs) (void)hipFree(offs);
+        free_job(J);
+        return r;
+    }
+    const int path = choose_path(scene, opts);
+    hipError_t he = hipSuccess;
+    for (int64_t k0 = 0; k0 < K && r == UVC_OK; k0 += Kb) {
+        const int64_t kb = std::min(Kb, K - k0);
+        IrrParams Q = P;
+        Q.poses = poses_dev + k0 * pose_dim;
+        Q.K = kb;
+        Q.E = scratch;
+        Q.vis = nullptr;
+        r = launch_irr(Q, path, st);
+        if (r != UVC_OK) break;
+        const unsigned rb = (unsigned)((kb * 64 + 255) / 256);
+        hipLaunchKernelGGL(k_row_count, dim3(rb), dim3(256), 0, st, scratch, kb, N, J->counts + k0);
+        hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, J->counts + k0, offs, kb, (int64_t)0);
+        int64_t bnnz = 0;
+        he = hipMemcpyAsync(&bnnz, offs + kb, 8, hipMemcpyDeviceToHost, st);
+        if (he == hipSuccess) he = hipStreamSynchronize(st);
+        if (he != hipSuccess) {
+            r = fail(UVC_EDEVICE, std::string("CSR batch: ") + hipGetErrorString(he));
+            break;
+        }
+        uvc_csr_job::Chunk c{nullptr, nullptr, bnnz};
+        if ((r = dalloc_n(&c.col, (size_t)std::max<int64_t>(bnnz, 1), "CSR columns")) != UVC_OK) break;
+        if ((r = dalloc_n(&c.val, (size_t)std::max<int64_t>(bnnz, 1), "CSR values")) != UVC_OK) {
+            (void)hipFree(c.col);
+            break;
+        }
+        J->chunks.push_back(c);
+        hipLaunchKernelGGL(k_row_gather, dim3(rb), dim3(256), 0, st, scratch, kb, N, offs, c.col, c.val);
+        he = hipGetLastError();
+        if (he != hipSuccess) {
+            r = fail(UVC_EDEVICE, std::string("CSR gather: ") + hipGetErrorString(he));
+            break;
+        }
+        J->nnz += bnnz;
+    }
+    if (r == UVC_OK) {
+        he = hipStreamSynchronize(st);
+        if (he != hipSuccess) r = fail(UVC_EDEVICE, std::string("CSR begin: ") + hipGetErrorString(he));
+    }
+    (void)hipFree(scratch);
+    (void)hipFree(offs);
+    if (r != UVC_OK) {
+        free_job(J);
+        return r;
+    }
+    *nnz = J->nnz;
+    *job = J;
+    return UVC_OK;
+}
+
+extern "C" uvc_status uvc_compute_irradiance_csr_finish(uvc_csr_job* J, int64_t* row_ptr, int32_t* col, float* val,
+                                                        void* hip_stream) {
+    if (!J) return fail(UVC_EINVAL, "job is NULL");
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (!row_ptr || (J->nnz > 0 && (!col || !val))) {
+        free_job(J);
+        return fail(UVC_EINVAL, "NULL CSR output buffer");
+    }
+    uvc_status r = UVC_OK;
+    if (J->K == 0) {
+        if (hipMemsetAsync(row_ptr, 0, 8, st) != hipSuccess) r = fail(UVC_EDEVICE, "hipMemsetAsync failed");
+    } else {
+        hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(1024), 0, st, J->counts, row_ptr, J->K, (int64_t)0);
+        int64_t at = 0;
+        for (auto& c : J->chunks) {
+            if (c.nnz > 0) {
+                if (hipMemcpyAsync(col + at, c.col, (size_t)c.nnz * 4, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                    hipMemcpyAsync(val + at, c.val, (size_t)c.nnz * 4, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+                    r = fail(UVC_EDEVICE, "CSR copy failed");
+                    break;
+                }
+            }
+            at += c.nnz;
+        }
+    }
+    if (r == UVC_OK && hipStreamSynchronize(st) != hipSuccess) r = fail(UVC_EDEVICE, "CSR finish sync failed");
+    free_job(J);
+    return r;
+}
+
+extern "C" void uvc_csr_job_destroy(uvc_csr_job* J) {
+    if (!J) return;
+    (void)hipDeviceSynchronize();
+    free_job(J);
+}

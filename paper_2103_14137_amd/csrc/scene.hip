@@ -1,0 +1,610 @@
+// Scene build: validation, surface elements, Morton codes, LSD radix sort,
+// Karras-style hierarchy emission and bottom-up box refit, all on the GPU.
+#include "uvc_common.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+namespace uvc {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+uvc_status fail(uvc_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+uvc_status dalloc(void** p, size_t bytes, const char* what) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(UVC_ENOMEM, std::string("device allocation of ") + std::to_string(bytes) +
+                                    " bytes failed (" + what + ")");
+    }
+    return UVC_OK;
+}
+
+// --------------------------------------------------------------- kernels
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Surface elements in input order (Sec. III-B: one element per triangle).
+// Centroid in FP64 as ((a + b) + c) / 3, rounded once to FP32; normal and
+// area from the FP64 cross product of the two edges leaving v0.
+__global__ void k_elements(const float* __restrict__ V, const int32_t* __restrict__ T, int64_t n,
+                           float* __restrict__ c, float* __restrict__ nrm, float* __restrict__ area) {
+#pragma clang fp contract(off)
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t ia = T[3 * i], ib = T[3 * i + 1], ic = T[3 * i + 2];
+    const double ax = V[3 * ia], ay = V[3 * ia + 1], az = V[3 * ia + 2];
+    const double bx = V[3 * ib], by = V[3 * ib + 1], bz = V[3 * ib + 2];
+    const double cx = V[3 * ic], cy = V[3 * ic + 1], cz = V[3 * ic + 2];
+    c[3 * i + 0] = (float)(((ax + bx) + cx) / 3.0);
+    c[3 * i + 1] = (float)(((ay + by) + cy) / 3.0);
+    c[3 * i + 2] = (float)(((az + bz) + cz) / 3.0);
+    const double e1x = bx - ax, e1y = by - ay, e1z = bz - az;
+    const double e2x = cx - ax, e2y = cy - ay, e2z = cz - az;
+    const double mx = e1y * e2z - e1z * e2y;
+    const double my = e1z * e2x - e1x * e2z;
+    const double mz = e1x * e2y - e1y * e2x;
+    const double len = sqrt((mx * mx + my * my) + mz * mz);
+    nrm[3 * i + 0] = (float)(mx / len);
+    nrm[3 * i + 1] = (float)(my / len);
+    nrm[3 * i + 2] = (float)(mz / len);
+    area[i] = (float)(0.5 * len);
+}
+
+__device__ __forceinline__ uint32_t spread10(uint32_t v) {
+    v &= 1023u;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+// 30-bit Morton code of each centroid in the scene box (10 bits per axis,
+// x in the most significant position).
+__global__ void k_morton(const float* __restrict__ c, int64_t n, float lox, float loy, float loz,
+                         float sx, float sy, float sz, uint32_t* __restrict__ key, int32_t* __restrict__ val) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float q[3] = {(c[3 * i] - lox) * sx, (c[3 * i + 1] - loy) * sy, (c[3 * i + 2] - loz) * sz};
+    uint32_t b[3];
+    for (int a = 0; a < 3; ++a) b[a] = (uint32_t)fminf(fmaxf(q[a], 0.f), 1023.f);
+    key[i] = (spread10(b[0]) << 2) | (spread10(b[1]) << 1) | spread10(b[2]);
+    val[i] = (int32_t)i;
+}
+
+// ---- stable LSD radix sort of (key, value) pairs, 8 bits per pass --------
+constexpr int RS_THREADS = 256;
+constexpr int RS_TILE = 1024;  // 4 waves x 4 rounds x 64 lanes
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
+                                                       uint32_t* __restrict__ hist, int nb) {
+    __shared__ uint32_t h[256];
+    const int tid = threadIdx.x;
+    h[tid] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    for (int r = 0; r < RS_TILE / RS_THREADS; ++r) {
+        int64_t idx = base + r * RS_THREADS + tid;
+        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)tid * nb + blockIdx.x] = h[tid];
+}
+
+// Exclusive scan of len words in place, one block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* __restrict__ a, int64_t len) {
+    __shared__ uint32_t part[1024];
+    __shared__ uint32_t carry;
+    const int tid = threadIdx.x;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < len; base += 1024) {
+        int64_t i = base + tid;
+        uint32_t v = (i < len) ? a[i] : 0u;
+        part[tid] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            uint32_t t = (tid >= off) ? part[tid - off] : 0u;
+            __syncthreads();
+            part[tid] += t;
+            __syncthreads();
+        }
+        if (i < len) a[i] = carry + part[tid] - v;
+        __syncthreads();
+        if (tid == 1023) carry += part[1023];
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt(int lane) {
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __restrict__ kin,
+                                                          const int32_t* __restrict__ vin,
+                                                          uint32_t* __restrict__ kout, int32_t* __restrict__ vout,
+                                                          int64_t n, int shift, const uint32_t* __restrict__ offs,
+                                                          int nb) {
+    __shared__ uint32_t cnt[4][257];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    for (int i = tid; i < 4 * 257; i += RS_THREADS) (&cnt[0][0])[i] = 0;
+    __syncthreads();
+    uint32_t kk[4], rank[4], dig[4];
+    int32_t vv[4];
+    const uint64_t lt = lanemask_lt(lane);
+    for (int r = 0; r < 4; ++r) {
+        const int64_t idx = (int64_t)blockIdx.x * RS_TILE + w * 256 + r * 64 + lane;
+        const bool valid = idx < n;
+        kk[r] = valid ? kin[idx] : 0u;
+        vv[r] = valid ? vin[idx] : 0;
+        const uint32_t d = valid ? ((kk[r] >> shift) & 255u) : 256u;
+        uint64_t peers = ~0ull;
+        for (int b = 0; b < 9; ++b) {
+            const int bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t before = cnt[w][d];
+        rank[r] = before + (uint32_t)__popcll(peers & lt);
+        dig[r] = d;
+        const bool leader = (peers >> lane) == 1ull;
+        if (leader) cnt[w][d] = before + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    if (tid < 256) {
+        uint32_t acc = 0;
+        for (int ww = 0; ww < 4; ++ww) {
+            uint32_t t = cnt[ww][tid];
+            cnt[ww][tid] = acc;
+            acc += t;
+        }
+    }
+    __syncthreads();
+    for (int r = 0; r < 4; ++r) {
+        if (dig[r] < 256u) {
+            const uint32_t d = dig[r];
+            const uint64_t dst = (uint64_t)offs[(int64_t)d * nb + blockIdx.x] + cnt[w][d] + rank[r];
+            if (dst < (uint64_t)n) {  // always true for a consistent histogram; guards the write
+                kout[dst] = kk[r];
+                vout[dst] = vv[r];
+            }
+        }
+    }
+}
+
+// Leaf-slot records: triangle vertices in input order plus the input index,
+// and the element (centroid, unit normal, index, area).
+__global__ void k_gather(const float* __restrict__ V, const int32_t* __restrict__ T,
+                         const int32_t* __restrict__ perm, const float* __restrict__ c,
+                         const float* __restrict__ nrm, const float* __restrict__ area, int64_t n,
+                         float* __restrict__ tri, float* __restrict__ elem) {
+    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int64_t i = perm[s];
+    float* t = tri + s * TRI_WORDS;
+    for (int k = 0; k < 3; ++k) {
+        const int64_t vi = T[3 * i + k];
+        t[3 * k + 0] = V[3 * vi + 0];
+        t[3 * k + 1] = V[3 * vi + 1];
+        t[3 * k + 2] = V[3 * vi + 2];
+    }
+    t[9] = __int_as_float((int)i);
+    t[10] = 0.f;
+    t[11] = 0.f;
+    float* e = elem + s * ELEM_WORDS;
+    e[0] = c[3 * i];
+    e[1] = c[3 * i + 1];
+    e[2] = c[3 * i + 2];
+    e[3] = nrm[3 * i];
+    e[4] = nrm[3 * i + 1];
+    e[5] = nrm[3 * i + 2];
+    e[6] = __int_as_float((int)i);
+    e[7] = area[i];
+}
+
+// Length of the common prefix of (code, slot) pairs i and j; -1 outside.
+__device__ __forceinline__ int lcp(const uint32_t* __restrict__ code, int64_t n, int64_t i, int64_t j) {
+    if (j < 0 || j >= n) return -1;
+    const uint32_t a = code[i], b = code[j];
+    if (a == b) return 32 + __clz((int)((uint32_t)i ^ (uint32_t)j));
+    return __clz((int)(a ^ b));
+}
+
+// Internal node i covers a contiguous range of sorted slots; its split is
+// the first position where the common prefix shortens (Karras 2012).
+__global__ void k_hierarchy(const uint32_t* __restrict__ code, int64_t n, float* __restrict__ nodes,
+                            int32_t* __restrict__ int_parent, int32_t* __restrict__ leaf_parent) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    const int d = (lcp(code, n, i, i + 1) - lcp(code, n, i, i - 1)) >= 0 ? 1 : -1;
+    const int dmin = lcp(code, n, i, i - d);
+    int64_t lmax = 2;
+    while (lcp(code, n, i, i + lmax * d) > dmin) lmax <<= 1;
+    int64_t l = 0;
+    for (int64_t t = lmax >> 1; t >= 1; t >>= 1)
+        if (lcp(code, n, i, i + (l + t) * d) > dmin) l += t;
+    const int64_t j = i + l * d;
+    const int dnode = lcp(code, n, i, j);
+    int64_t s = 0, t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (lcp(code, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    const int64_t g = i + s * d + (d < 0 ? -1 : 0);
+    const int64_t lo = i < j ? i : j, hi = i < j ? j : i;
+    int32_t left, right;
+    if (lo == g) {
+        left = ~(int32_t)g;
+        leaf_parent[g] = (int32_t)i;
+    } else {
+        left = (int32_t)g;
+        int_parent[g] = (int32_t)i;
+    }
+    if (hi == g + 1) {
+        right = ~(int32_t)(g + 1);
+        leaf_parent[g + 1] = (int32_t)i;
+    } else {
+        right = (int32_t)(g + 1);
+        int_parent[g + 1] = (int32_t)i;
+    }
+    float* nd = nodes + i * NODE_WORDS;
+    nd[12] = __int_as_float(left);
+    nd[13] = __int_as_float(right);
+    if (i == 0) int_parent[0] = -1;
+}
+
+// Bottom-up refit: each leaf writes its padded box into its parent; the
+// second thread to reach a node merges both child boxes and climbs on.
+__global__ void k_refit(const float* __restrict__ tri, const int32_t* __restrict__ leaf_parent,
+                        const int32_t* __restrict__ int_parent, float* nodes, uint32_t* counters, int64_t n,
+                        float pad) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const float* t = tri + s * TRI_WORDS;
+    float lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = fminf(fminf(t[a], t[3 + a]), t[6 + a]) - pad;
+        hi[a] = fmaxf(fmaxf(t[a], t[3 + a]), t[6 + a]) + pad;
+    }
+    int32_t child = ~(int32_t)s;
+    int32_t p = leaf_parent[s];
+    while (true) {
+        float* nd = nodes + (int64_t)p * NODE_WORDS;
+        const int off = (__float_as_int(nd[12]) == child) ? 0 : 6;
+        for (int a = 0; a < 3; ++a) {
+            nd[off + a] = lo[a];
+            nd[off + 3 + a] = hi[a];
+        }
+        __threadfence();
+        const uint32_t old = atomicAdd(&counters[p], 1u);
+        if (old == 0) return;
+        __threadfence();
+        float b[12];
+        for (int k = 0; k < 12; ++k) b[k] = __builtin_nontemporal_load(nd + k);
+        float best = -1.f;
+        int axis = 0;
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(b[a], b[6 + a]);
+            hi[a] = fmaxf(b[3 + a], b[9 + a]);
+            const float sep = fabsf((b[6 + a] + b[9 + a]) - (b[a] + b[3 + a]));
+            if (sep > best) {
+                best = sep;
+                axis = a;
+            }
+        }
+        const float cl = 0.5f * (b[axis] + b[3 + axis]), cr = 0.5f * (b[6 + axis] + b[9 + axis]);
+        nd[14] = __int_as_float(axis | ((cl <= cr) ? 4 : 0));
+        nd[15] = 0.5f * (cl + cr);
+        if (p == 0) return;
+        child = p;
+        p = int_parent[p];
+    }
+}
+
+__global__ void k_depth(const int32_t* __restrict__ leaf_parent, const int32_t* __restrict__ int_parent, int64_t n,
+                        int32_t* __restrict__ depth) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    int d = 1;
+    for (int32_t p = leaf_parent[s]; p >= 0; p = int_parent[p]) {
+        ++d;
+        if (d > 1000) break;
+    }
+    atomicMax(depth, d);
+}
+
+static inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
+
+static void free_scene(uvc_scene* s) {
+    if (!s) return;
+    void* ptrs[] = {s->tri, s->elem, s->elem_c, s->elem_n, s->elem_a, s->perm, s->codes, s->nodes};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    delete s;
+}
+
+struct TmpBuffers {
+    std::vector<void*> p;
+    ~TmpBuffers() {
+        for (void* q : p)
+            if (q) (void)hipFree(q);
+    }
+    template <class T>
+    uvc_status alloc(T** out, size_t n, const char* what) {
+        UVC_TRY(dalloc_n(out, n, what));
+        p.push_back(*out);
+        return UVC_OK;
+    }
+};
+
+static uvc_status build_impl(const float* verts_in, int64_t nv, const int32_t* tris_in, int64_t nt, int on_dev,
+                             hipStream_t st, uvc_scene** out) {
+    if (!out) return fail(UVC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nv < 0 || nt < 0) return fail(UVC_EINVAL, "negative vertex or triangle count");
+    if (nt > (int64_t)(1u << 30)) return fail(UVC_EUNSUPPORTED, "more than 2^30 triangles");
+    if (nt > 0 && (!verts_in || !tris_in || nv == 0)) return fail(UVC_EINVAL, "NULL mesh arrays");
+    // host copies for validation
+    std::vector<float> hv((size_t)nv * 3);
+    std::vector<int32_t> ht((size_t)nt * 3);
+    if (nt > 0) {
+        if (on_dev) {
+            UVC_HIP(hipMemcpyAsync(hv.data(), verts_in, hv.size() * 4, hipMemcpyDeviceToHost, st));
+            UVC_HIP(hipMemcpyAsync(ht.data(), tris_in, ht.size() * 4, hipMemcpyDeviceToHost, st));
+            UVC_HIP(hipStreamSynchronize(st));
+        } else {
+            std::memcpy(hv.data(), verts_in, hv.size() * 4);
+            std::memcpy(ht.data(), tris_in, ht.size() * 4);
+        }
+    }
+    float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    float max_abs = 0.f;
+    bool first = true;
+    for (int64_t t = 0; t < nt; ++t) {
+        double v[3][3];
+        for (int k = 0; k < 3; ++k) {
+            const int32_t vi = ht[3 * t + k];
+            if (vi < 0 || vi >= nv)
+                return fail(UVC_EINVAL, "triangle " + std::to_string(t) + " has vertex index " + std::to_string(vi) +
+                                            " outside [0, " + std::to_string(nv) + ")");
+            for (int a = 0; a < 3; ++a) {
+                const float x = hv[3 * (size_t)vi + a];
+                if (!std::isfinite(x))
+                    return fail(UVC_EINVAL, "vertex " + std::to_string(vi) + " has a non-finite coordinate");
+                v[k][a] = x;
+                if (first) {
+                    lo[a] = hi[a] = x;
+                } else {
+                    lo[a] = std::min(lo[a], x);
+                    hi[a] = std::max(hi[a], x);
+                }
+                max_abs = std::max(max_abs, std::fabs(x));
+            }
+            first = false;
+        }
+        const double e1[3] = {v[1][0] - v[0][0], v[1][1] - v[0][1], v[1][2] - v[0][2]};
+        const double e2[3] = {v[2][0] - v[0][0], v[2][1] - v[0][1], v[2][2] - v[0][2]};
+        const double m0 = e1[1] * e2[2] - e1[2] * e2[1];
+        const double m1 = e1[2] * e2[0] - e1[0] * e2[2];
+        const double m2 = e1[0] * e2[1] - e1[1] * e2[0];
+        if (m0 == 0.0 && m1 == 0.0 && m2 == 0.0)
+            return fail(UVC_EINVAL, "triangle " + std::to_string(t) + " has zero area");
+    }
+    uvc_scene* s = new uvc_scene();
+    (void)hipGetDevice(&s->device);
+    s->n = nt;
+    s->max_abs = max_abs;
+    s->pad = PAD_REL * std::max(max_abs, 1e-30f);
+    for (int a = 0; a < 3; ++a) {
+        s->lo[a] = lo[a];
+        s->hi[a] = hi[a];
+    }
+    if (nt == 0) {
+        s->depth = 0;
+        *out = s;
+        return UVC_OK;
+    }
+    auto cleanup_fail = [&](uvc_status st_) {
+        free_scene(s);
+        return st_;
+    };
+    const int64_t n = nt;
+    uvc_status r = UVC_OK;
+    if ((r = dalloc_n(&s->tri, (size_t)n * TRI_WORDS, "triangle records")) != UVC_OK) return cleanup_fail(r);
+    if ((r = dalloc_n(&s->elem, (size_t)n * ELEM_WORDS, "element records")) != UVC_OK) return cleanup_fail(r);
+    if ((r = dalloc_n(&s->elem_c, (size_t)n * 3, "centroids")) != UVC_OK) return cleanup_fail(r);
+    if ((r = dalloc_n(&s->elem_n, (size_t)n * 3, "normals")) != UVC_OK) return cleanup_fail(r);
+    if ((r = dalloc_n(&s->elem_a, (size_t)n, "areas")) != UVC_OK) return cleanup_fail(r);
+    if ((r = dalloc_n(&s->perm, (size_t)n, "leaf permutation")) != UVC_OK) return cleanup_fail(r);
+    if ((r = dalloc_n(&s->codes, (size_t)n, "morton codes")) != UVC_OK) return cleanup_fail(r);
+    if ((r = dalloc_n(&s->nodes, (size_t)std::max<int64_t>(n - 1, 1) * NODE_WORDS, "hierarchy nodes")) != UVC_OK)
+        return cleanup_fail(r);
+    TmpBuffers tmp;
+    float* dv = nullptr;
+    int32_t* dt = nullptr;
+    uint32_t *k2 = nullptr, *hist = nullptr, *counters = nullptr;
+    int32_t *v1 = nullptr, *v2 = nullptr, *ipar = nullptr, *lpar = nullptr, *ddepth = nullptr;
+    const int nb = (int)((n + RS_TILE - 1) / RS_TILE);
+    if ((r = tmp.alloc(&dv, (size_t)nv * 3, "vertices")) != UVC_OK ||
+        (r = tmp.alloc(&dt, (size_t)n * 3, "indices")) != UVC_OK ||
+        (r = tmp.alloc(&k2, (size_t)n, "sort keys")) != UVC_OK ||
+        (r = tmp.alloc(&v1, (size_t)n, "sort values")) != UVC_OK ||
+        (r = tmp.alloc(&v2, (size_t)n, "sort values")) != UVC_OK ||
+        (r = tmp.alloc(&hist, (size_t)256 * nb, "sort histogram")) != UVC_OK ||
+        (r = tmp.alloc(&counters, (size_t)std::max<int64_t>(n - 1, 1), "refit counters")) != UVC_OK ||
+        (r = tmp.alloc(&ipar, (size_t)std::max<int64_t>(n - 1, 1), "parents")) != UVC_OK ||
+        (r = tmp.alloc(&lpar, (size_t)n, "leaf parents")) != UVC_OK ||
+        (r = tmp.alloc(&ddepth, 1, "depth")) != UVC_OK)
+        return cleanup_fail(r);
+#define STEP(call)                                                                                    \
+    do {                                                                                              \
+        hipError_t e_ = (call);                                                                       \
+        if (e_ == hipSuccess) e_ = hipGetLastError();                                                 \
+        if (e_ != hipSuccess) return cleanup_fail(fail(UVC_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_))); \
+    } while (0)
+    STEP(hipMemcpyAsync(dv, hv.data(), hv.size() * 4, hipMemcpyHostToDevice, st));
+    STEP(hipMemcpyAsync(dt, ht.data(), ht.size() * 4, hipMemcpyHostToDevice, st));
+    const int TB = 256;
+    hipLaunchKernelGGL(k_elements, dim3(grid_for(n, TB)), dim3(TB), 0, st, dv, dt, n, s->elem_c, s->elem_n, s->elem_a);
+    STEP(hipGetLastError());
+    float sc[3];
+    for (int a = 0; a < 3; ++a) sc[a] = (hi[a] > lo[a]) ? 1024.f / (hi[a] - lo[a]) : 0.f;
+    hipLaunchKernelGGL(k_morton, dim3(grid_for(n, TB)), dim3(TB), 0, st, s->elem_c, n, lo[0], lo[1], lo[2], sc[0],
+                       sc[1], sc[2], s->codes, v1);
+    STEP(hipGetLastError());
+    uint32_t* ka = s->codes;
+    uint32_t* kb = k2;
+    int32_t* va = v1;
+    int32_t* vb = v2;
+    for (int shift = 0; shift < 32; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(RS_THREADS), 0, st, ka, n, shift, hist, nb);
+        STEP(hipGetLastError());
+        hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, st, hist, (int64_t)256 * nb);
+        STEP(hipGetLastError());
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(RS_THREADS), 0, st, ka, va, kb, vb, n, shift, hist, nb);
+        STEP(hipGetLastError());
+        std::swap(ka, kb);
+        std::swap(va, vb);
+    }
+    // after 4 passes the sorted data is back in (s->codes, v1)
+    STEP(hipMemcpyAsync(s->perm, va, (size_t)n * 4, hipMemcpyDeviceToDevice, st));
+    {
+        // structural check before any kernel indexes through the permutation
+        std::vector<uint32_t> hc((size_t)n);
+        std::vector<int32_t> hp((size_t)n);
+        STEP(hipMemcpyAsync(hc.data(), s->codes, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+        STEP(hipMemcpyAsync(hp.data(), s->perm, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+        STEP(hipStreamSynchronize(st));
+        std::vector<uint8_t> seen((size_t)n, 0);
+        for (int64_t i = 0; i < n; ++i) {
+            if ((i > 0 && hc[i] < hc[i - 1]) || hp[i] < 0 || hp[i] >= n || seen[hp[i]])
+                return cleanup_fail(fail(UVC_EDEVICE, "internal error: Morton sort produced an invalid order"));
+            seen[hp[i]] = 1;
+        }
+    }
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(n, TB)), dim3(TB), 0, st, dv, dt, s->perm, s->elem_c, s->elem_n,
+                       s->elem_a, n, s->tri, s->elem);
+    STEP(hipGetLastError());
+    int32_t depth = 1;
+    if (n > 1) {
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n - 1, TB)), dim3(TB), 0, st, counters, 0u, n - 1);
+        STEP(hipGetLastError());
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n - 1, TB)), dim3(TB), 0, st, (uint32_t*)ipar, 0xfffffffeu, n - 1);
+        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, TB)), dim3(TB), 0, st, (uint32_t*)lpar, 0xfffffffeu, n);
+        hipLaunchKernelGGL(k_hierarchy, dim3(grid_for(n - 1, TB)), dim3(TB), 0, st, s->codes, n, s->nodes, ipar, lpar);
+        STEP(hipGetLastError());
+        {
+            // every internal node but the root has one parent, every node has
+            // exactly two children, and every leaf reaches the root
+            std::vector<int32_t> hi_((size_t)(n - 1)), hl((size_t)n);
+            STEP(hipMemcpyAsync(hi_.data(), ipar, (size_t)(n - 1) * 4, hipMemcpyDeviceToHost, st));
+            STEP(hipMemcpyAsync(hl.data(), lpar, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+            STEP(hipStreamSynchronize(st));
+            std::vector<uint8_t> kids((size_t)(n - 1), 0);
+            bool ok = hi_[0] == -1;
+            for (int64_t i = 1; ok && i < n - 1; ++i) {
+                ok = hi_[i] >= 0 && hi_[i] < n - 1 && hi_[i] != i;
+                if (ok) ++kids[hi_[i]];
+            }
+            for (int64_t i = 0; ok && i < n; ++i) {
+                ok = hl[i] >= 0 && hl[i] < n - 1;
+                if (ok) ++kids[hl[i]];
+            }
+            for (int64_t i = 0; ok && i < n - 1; ++i) ok = kids[i] == 2;
+            for (int64_t i = 0; ok && i < n; ++i) {
+                int64_t p = hl[i], steps = 0;
+                while (p > 0 && steps <= 64) {
+                    p = hi_[p];
+                    ++steps;
+                }
+                ok = p == 0 && steps <= 64;
+            }
+            if (!ok) return cleanup_fail(fail(UVC_EDEVICE, "internal error: hierarchy emission is inconsistent"));
+        }
+        hipLaunchKernelGGL(k_refit, dim3(grid_for(n, TB)), dim3(TB), 0, st, s->tri, lpar, ipar, s->nodes, counters, n,
+                           s->pad);
+        STEP(hipGetLastError());
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, st, (uint32_t*)ddepth, 0u, (int64_t)1);
+        STEP(hipGetLastError());
+        hipLaunchKernelGGL(k_depth, dim3(grid_for(n, TB)), dim3(TB), 0, st, lpar, ipar, n, ddepth);
+        STEP(hipGetLastError());
+        STEP(hipMemcpyAsync(&depth, ddepth, 4, hipMemcpyDeviceToHost, st));
+    }
+    STEP(hipStreamSynchronize(st));
+#undef STEP
+    s->depth = depth;
+    if (depth > 64) {
+        free_scene(s);
+        return fail(UVC_EUNSUPPORTED, "hierarchy depth " + std::to_string(depth) + " exceeds 64");
+    }
+    *out = s;
+    return UVC_OK;
+}
+
+}  // namespace uvc
+
+using namespace uvc;
+
+extern "C" const char* uvc_last_error(void) { return uvc::g_err.c_str(); }
+
+extern "C" int32_t uvc_version(void) { return 100; }
+
+extern "C" uvc_status uvc_build_scene(const float* verts_xyz, int64_t n_verts, const int32_t* tri_idx, int64_t n_tris,
+                                      int32_t inputs_on_device, void* hip_stream, uvc_scene** out) {
+    try {
+        return build_impl(verts_xyz, n_verts, tri_idx, n_tris, inputs_on_device, (hipStream_t)hip_stream, out);
+    } catch (const std::exception& e) {
+        return fail(UVC_ENOMEM, std::string("host exception: ") + e.what());
+    }
+}
+
+extern "C" uvc_status uvc_scene_info(const uvc_scene* s, int64_t* n_tris, int32_t* depth, float* max_abs) {
+    if (!s) return fail(UVC_EINVAL, "scene is NULL");
+    if (n_tris) *n_tris = s->n;
+    if (depth) *depth = s->depth;
+    if (max_abs) *max_abs = s->max_abs;
+    return UVC_OK;
+}
+
+extern "C" uvc_status uvc_scene_elements(const uvc_scene* s, float* c, float* nrm, float* area, void* hip_stream) {
+    if (!s) return fail(UVC_EINVAL, "scene is NULL");
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (s->n == 0) return UVC_OK;
+    if (c) UVC_HIP(hipMemcpyAsync(c, s->elem_c, (size_t)s->n * 12, hipMemcpyDeviceToDevice, st));
+    if (nrm) UVC_HIP(hipMemcpyAsync(nrm, s->elem_n, (size_t)s->n * 12, hipMemcpyDeviceToDevice, st));
+    if (area) UVC_HIP(hipMemcpyAsync(area, s->elem_a, (size_t)s->n * 4, hipMemcpyDeviceToDevice, st));
+    return UVC_OK;
+}
+
+extern "C" uvc_status uvc_scene_export_bvh(const uvc_scene* s, float* nodes, int32_t* perm, uint32_t* codes,
+                                           void* hip_stream) {
+    if (!s) return fail(UVC_EINVAL, "scene is NULL");
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (s->n == 0) return UVC_OK;
+    if (nodes && s->n > 1)
+        UVC_HIP(hipMemcpyAsync(nodes, s->nodes, (size_t)(s->n - 1) * NODE_WORDS * 4, hipMemcpyDeviceToHost, st));
+    if (perm) UVC_HIP(hipMemcpyAsync(perm, s->perm, (size_t)s->n * 4, hipMemcpyDeviceToHost, st));
+    if (codes) UVC_HIP(hipMemcpyAsync(codes, s->codes, (size_t)s->n * 4, hipMemcpyDeviceToHost, st));
+    UVC_HIP(hipStreamSynchronize(st));
+    return UVC_OK;
+}
+
+extern "C" void uvc_destroy_scene(uvc_scene* s) {
+    if (!s) return;
+    (void)hipDeviceSynchronize();
+    free_scene(s);
+}

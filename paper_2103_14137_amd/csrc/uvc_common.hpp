@@ -1,0 +1,81 @@
+// Internal declarations of the HIP irradiance library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/uvc.h"
+
+namespace uvc {
+
+// ----------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+uvc_status fail(uvc_status s, const std::string& msg);
+
+#define UVC_HIP(call)                                                               \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess)                                                       \
+            return ::uvc::fail(UVC_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define UVC_TRY(expr)                        \
+    do {                                     \
+        uvc_status s_ = (expr);              \
+        if (s_ != UVC_OK) return s_;         \
+    } while (0)
+
+// Allocation helper that reports UVC_ENOMEM with the size.
+uvc_status dalloc(void** p, size_t bytes, const char* what);
+
+template <class T>
+uvc_status dalloc_n(T** p, size_t n, const char* what) {
+    return dalloc(reinterpret_cast<void**>(p), n * sizeof(T), what);
+}
+
+// --------------------------------------------------------- layout constants
+// Triangle record, 48 bytes, in leaf-slot order: v0.xyz v1.xyz v2.xyz in the
+// input vertex order, the input triangle index (int bits), two spare words.
+constexpr int TRI_WORDS = 12;
+// Element record, 32 bytes, in leaf-slot order: centroid xyz, unit normal
+// xyz, input triangle index (int bits), area.
+constexpr int ELEM_WORDS = 8;
+// Hierarchy node, 64 bytes: left box lo xyz hi xyz, right box lo xyz hi xyz,
+// left ref, right ref (>= 0 internal, < 0 leaf slot ~ref), hint axis/order,
+// hint split coordinate.
+constexpr int NODE_WORDS = 16;
+
+// Decision bands of the FP32 fast path (multiplied by opts.band_scale).
+// Front-facing: |<d, n>| > TAU_F * |d|_1.
+// Edge orientations U, V, W: |U| > TAU_E * G^2 * |D|_1 with G the largest
+//   |coordinate| of v0-O, v1-O, v2-O.
+// Plane sides: |s| > TAU_P * |x|_inf * |e1|_inf * |e2|_inf with x = O-v0 or
+//   T-v0 and e1, e2 the triangle's edge vectors from v0.
+constexpr float TAU_F = 1.0f / 524288.0f;   // 2^-19
+constexpr float TAU_E = 1.0f / 8192.0f;     // 2^-13
+constexpr float TAU_P = 1.0f / 8192.0f;     // 2^-13
+
+// Box padding relative to the scene's largest |coordinate|.
+constexpr float PAD_REL = 1.0f / 262144.0f; // 2^-18
+
+}  // namespace uvc
+
+struct uvc_scene {
+    int device = 0;
+    int64_t n = 0;              // triangles = elements
+    int32_t depth = 0;          // hierarchy depth (root = 1)
+    float max_abs = 0.f;        // largest |vertex coordinate|
+    float pad = 0.f;            // absolute box padding
+    float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    float* tri = nullptr;       // n x TRI_WORDS
+    float* elem = nullptr;      // n x ELEM_WORDS (slot order)
+    float* elem_c = nullptr;    // n x 3 (input order)
+    float* elem_n = nullptr;    // n x 3 (input order)
+    float* elem_a = nullptr;    // n (input order)
+    int32_t* perm = nullptr;    // slot -> input index
+    uint32_t* codes = nullptr;  // sorted Morton codes
+    float* nodes = nullptr;     // (n-1) x NODE_WORDS
+};

@@ -1,0 +1,228 @@
+"""Thin Python binding of the libuvc C ABI (include/uvc.h).
+
+Argument marshalling only: every step of the irradiance path runs in the HIP
+library.  PyTorch provides device memory and the current stream.  There is
+no fallback: if the library cannot be loaded or no GPU is present, the calls
+raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+import torch  # imported before the library so both share one HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libuvc.so")
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+
+PATHS = {"auto": 0, "lbvh": 1, "brute": 2}
+STAT_NAMES = ["rays", "nodes", "tris", "recheck", "front64", "visible"]
+STAT_N = 8
+
+
+class UvcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"uvc status {status}: {msg}")
+        self.status = status
+
+
+class LampC(ctypes.Structure):
+    _fields_ = [("n_src", _I32), ("dz", _P), ("power_w", _P)]
+
+
+class OptsC(ctypes.Structure):
+    _fields_ = [("path", _I32), ("reserved0", _I32), ("band_scale", ctypes.c_float), ("tile_tris", _I32),
+                ("stats_dev", _P)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libuvc.so (building it first only if no build exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        from . import build
+        build.build()
+    L = ctypes.CDLL(LIB_PATH, mode=ctypes.RTLD_GLOBAL)
+    sig = {
+        "uvc_last_error": ([], ctypes.c_char_p),
+        "uvc_version": ([], _I32),
+        "uvc_build_scene": ([_P, _I64, _P, _I64, _I32, _P, ctypes.POINTER(_P)], _I32),
+        "uvc_scene_info": ([_P, ctypes.POINTER(_I64), ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float)], _I32),
+        "uvc_scene_elements": ([_P, _P, _P, _P, _P], _I32),
+        "uvc_scene_export_bvh": ([_P, _P, _P, _P, _P], _I32),
+        "uvc_destroy_scene": ([_P], None),
+        "uvc_compute_irradiance_dense": ([_P, _P, _I64, _I32, ctypes.POINTER(LampC), ctypes.POINTER(OptsC), _P, _P,
+                                          _P], _I32),
+        "uvc_compute_irradiance_csr_begin": ([_P, _P, _I64, _I32, ctypes.POINTER(LampC), ctypes.POINTER(OptsC), _P,
+                                              ctypes.POINTER(_P), ctypes.POINTER(_I64)], _I32),
+        "uvc_compute_irradiance_csr_finish": ([_P, _P, _P, _P, _P], _I32),
+        "uvc_csr_job_destroy": ([_P], None),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def check(status: int) -> None:
+    if status != 0:
+        raise UvcError(status, lib().uvc_last_error().decode())
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _require_cuda(t: torch.Tensor, name: str, dtype) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}")
+    return t.contiguous()
+
+
+class Lamp:
+    """Point sources dz[j] metres above the pose base, power[j] watts each."""
+
+    def __init__(self, dz, power):
+        self.dz = np.ascontiguousarray(dz, np.float32).reshape(-1)
+        self.power = np.ascontiguousarray(power, np.float32).reshape(-1)
+        if self.dz.shape != self.power.shape:
+            raise ValueError("dz and power must have the same length")
+        self._c = LampC(int(self.dz.shape[0]), self.dz.ctypes.data_as(_P), self.power.ctypes.data_as(_P))
+
+    @property
+    def n_src(self) -> int:
+        return int(self.dz.shape[0])
+
+
+def as_lamp(lamp) -> Lamp:
+    if isinstance(lamp, Lamp):
+        return lamp
+    return Lamp(lamp.dz, lamp.power)
+
+
+def make_opts(path="auto", band_scale: float = 1.0, tile_tris: int = 0, stats: torch.Tensor | None = None) -> OptsC:
+    if stats is not None:
+        stats = _require_cuda(stats, "stats", torch.int64)
+        if stats.numel() < STAT_N:
+            raise ValueError(f"stats needs {STAT_N} counters")
+    return OptsC(PATHS[path] if isinstance(path, str) else int(path), 0, float(band_scale), int(tile_tris),
+                 stats.data_ptr() if stats is not None else None)
+
+
+class Scene:
+    """A mesh with its surface elements and hierarchy, resident on the GPU."""
+
+    def __init__(self, verts, tris, stream=None):
+        v = np.ascontiguousarray(verts, np.float32)
+        t = np.ascontiguousarray(tris, np.int32)
+        if v.ndim != 2 or v.shape[1] != 3 or t.ndim != 2 or t.shape[1] != 3:
+            raise ValueError("verts must be [V,3] and tris [N,3]")
+        h = _P()
+        self._h = None
+        check(lib().uvc_build_scene(v.ctypes.data_as(_P), v.shape[0], t.ctypes.data_as(_P), t.shape[0], 0,
+                                    _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.n = int(t.shape[0])
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("scene is closed")
+        return self._h
+
+    def info(self):
+        n, d, m = _I64(), _I32(), ctypes.c_float()
+        check(lib().uvc_scene_info(self.handle, ctypes.byref(n), ctypes.byref(d), ctypes.byref(m)))
+        return {"n_tris": n.value, "bvh_depth": d.value, "max_abs_coord": m.value}
+
+    def elements(self, stream=None):
+        c = torch.empty((self.n, 3), dtype=torch.float32, device="cuda")
+        nrm = torch.empty((self.n, 3), dtype=torch.float32, device="cuda")
+        a = torch.empty((self.n,), dtype=torch.float32, device="cuda")
+        check(lib().uvc_scene_elements(self.handle, c.data_ptr(), nrm.data_ptr(), a.data_ptr(), _stream(stream)))
+        return c, nrm, a
+
+    def export_bvh(self, stream=None):
+        nodes = np.zeros((max(self.n - 1, 0), 16), np.float32)
+        perm = np.zeros(self.n, np.int32)
+        codes = np.zeros(self.n, np.uint32)
+        check(lib().uvc_scene_export_bvh(self.handle, nodes.ctypes.data_as(_P) if nodes.size else None,
+                                         perm.ctypes.data_as(_P), codes.ctypes.data_as(_P), _stream(stream)))
+        return nodes, perm, codes
+
+    def close(self):
+        if self._h is not None:
+            lib().uvc_destroy_scene(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def irradiance_dense(scene: Scene, poses: torch.Tensor, lamp, path="auto", band_scale: float = 1.0,
+                     want_vis: bool = False, stats: torch.Tensor | None = None, out: torch.Tensor | None = None,
+                     tile_tris: int = 0, stream=None):
+    """Dense K x N irradiance matrix (and optional visibility bits)."""
+    poses = _require_cuda(poses, "poses", torch.float32)
+    K, pd = poses.shape
+    lamp = as_lamp(lamp)
+    N = scene.n
+    if out is None:
+        out = torch.empty((K, N), dtype=torch.float32, device=poses.device)
+    else:
+        out = _require_cuda(out, "out", torch.float32)
+        if out.numel() != K * N:
+            raise ValueError("out must hold K*N floats")
+    vis = torch.empty((K, N), dtype=torch.int32, device=poses.device) if want_vis else None
+    opts = make_opts(path, band_scale, tile_tris, stats)
+    check(lib().uvc_compute_irradiance_dense(scene.handle, poses.data_ptr(), K, pd, ctypes.byref(lamp._c),
+                                             ctypes.byref(opts), out.data_ptr(),
+                                             vis.data_ptr() if vis is not None else None, _stream(stream)))
+    return out, vis
+
+
+def irradiance_csr(scene: Scene, poses: torch.Tensor, lamp, path="auto", band_scale: float = 1.0,
+                   stats: torch.Tensor | None = None, tile_tris: int = 0, stream=None):
+    """CSR irradiance matrix: (row_ptr int64 [K+1], col int32 [nnz], val float32 [nnz])."""
+    poses = _require_cuda(poses, "poses", torch.float32)
+    K, pd = poses.shape
+    lamp = as_lamp(lamp)
+    opts = make_opts(path, band_scale, tile_tris, stats)
+    job = _P()
+    nnz = _I64()
+    s = _stream(stream)
+    check(lib().uvc_compute_irradiance_csr_begin(scene.handle, poses.data_ptr(), K, pd, ctypes.byref(lamp._c),
+                                                 ctypes.byref(opts), s, ctypes.byref(job), ctypes.byref(nnz)))
+    row_ptr = torch.empty(K + 1, dtype=torch.int64, device=poses.device)
+    col = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=poses.device)
+    val = torch.empty(max(nnz.value, 1), dtype=torch.float32, device=poses.device)
+    check(lib().uvc_compute_irradiance_csr_finish(job, row_ptr.data_ptr(), col.data_ptr(), val.data_ptr(), s))
+    return row_ptr, col[:nnz.value], val[:nnz.value]
+
+
+def new_stats(device="cuda") -> torch.Tensor:
+    return torch.zeros(STAT_N, dtype=torch.int64, device=device)
+
+
+def stats_dict(stats: torch.Tensor) -> dict:
+    v = stats.cpu().numpy().astype(np.uint64)
+    return {k: int(v[i]) for i, k in enumerate(STAT_NAMES)}

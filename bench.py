@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Irradiance-matrix assembly throughput on one MI355X.
+
+One step = one pass of the whole hot path over the ward workload (8 x 6 x 3 m
+room, 6 beds + 10 cuboids, 52,488 triangles, 5,000 lamp poses, tower lamp of
+8 point sources x 20 W), inputs already resident in HBM:
+  build the scene from the device-resident mesh (surface elements, Morton
+  codes, radix sort, hierarchy, refit) and assemble the dense 5,000 x 52,488
+  FP32 irradiance matrix (front-facing test, occlusion segment per front-facing
+  (pose, source, element) triple, inverse-square cosine term, sum over the 8
+  sources).
+
+Prints one JSON line.  value = occlusion rays per second (rays = front-facing
+triples, each of which casts one occlusion segment); entries/s is reported
+beside it.  roofline: algorithmic FLOPs of the dominant kernel per launch
+(24 per hierarchy node visit, 40 per segment/triangle test, 20 per evaluated
+(pose, source, element) entry term; counts from an instrumented launch)
+divided by its HIP-event-timed duration.  cpu_baseline: the FP64 CPU oracle
+on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "occlusion rays/s + E entries/s (fraction of FP32 peak); ranked vs full plan time @≤2% gap"
+PEAK_FP32 = 157.3          # TFLOP/s, MI355X vector FP32 (packed)
+PEAK_FP32_UNPACKED = 78.6  # TFLOP/s, without packed FP32
+PEAK_HBM = 8000.0          # GB/s
+FLOP_NODE, FLOP_TRI, FLOP_ENTRY = 24, 40, 20
+KERNEL = "k_irr_lbvh"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("irradiance.hip", "uvc_common.hpp"):
+        with open(os.path.join(ROOT, "paper_2103_14137_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(n_launch_bytes_unused=None):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, if it was taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "k_irr_lbvh_ward_traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("source_hash") != source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, n_poses=32, n_elems=1024, seed=2024):
+    """The oracle (FP64 brute force, all host threads) on a seeded sample of
+    n_poses poses x n_elems contiguous elements x all sources."""
+    import numpy as np
+    from oracle import ref
+
+    rng = np.random.default_rng(seed)
+    ks = np.sort(rng.choice(w.K, n_poses, replace=False))
+    i0 = int(rng.integers(0, w.N - n_elems))
+    kk, ii = np.meshgrid(ks, np.arange(i0, i0 + n_elems), indexing="ij")
+    pk, pi = kk.ravel(), ii.ravel()
+    c32, _, _, m64 = ref.elements(w.mesh.verts, w.mesh.tris)
+    rays = 0
+    for j in range(w.lamp.n_src):
+        p = np.stack([w.poses[pk, 0], w.poses[pk, 1], np.full(len(pk), w.lamp.dz[j], np.float32)], -1)
+        d = p.astype(np.float64) - c32[pi].astype(np.float64)
+        rays += int(((d * m64[pi]).sum(-1) > 0).sum())
+    ref.lib()
+    t0 = time.perf_counter()
+    ref.irradiance_pairs(w.mesh.verts, w.mesh.tris, w.poses, w.lamp.dz, w.lamp.power, pk, pi)
+    dt = time.perf_counter() - t0
+    return {"value": rays / dt, "unit": "rays/s", "cores": ref.max_threads(), "kind": "oracle",
+            "sample": f"{n_poses} seeded poses x {n_elems} contiguous elements x {w.lamp.n_src} sources "
+                      f"({len(pk)} entries, {rays} occlusion rays) of the same ward workload",
+            "seconds": dt, "entries_per_s": len(pk) / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the brute-force path comparison")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one MI355X: the irradiance path runs on a single GPU in this build "
+              "(multi-GPU sharding is a design note only); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2103_14137_amd import uvc, workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = workloads.ward()
+    K, N, S = w.K, w.N, w.lamp.n_src
+    verts = torch.from_numpy(w.mesh.verts).to(dev)
+    tris = torch.from_numpy(w.mesh.tris).to(dev)
+    poses = torch.from_numpy(w.poses).to(dev)
+    lamp = uvc.Lamp(w.lamp.dz, w.lamp.power)
+    E = torch.empty((K, N), dtype=torch.float32, device=dev)
+    log(f"ward: K={K} N={N} S={S}")
+
+    def step():
+        sc = uvc.Scene(verts, tris)
+        uvc.irradiance_dense(sc, poses, lamp, path="lbvh", out=E)
+        sc.close()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / max(args.steps, 1)
+    log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step")
+
+    # instrumented launch: algorithmic work counts (outside the timed region)
+    sc = uvc.Scene(verts, tris)
+    stats = uvc.new_stats(dev)
+    uvc.irradiance_dense(sc, poses, lamp, path="lbvh", out=E, stats=stats)
+    st = uvc.stats_dict(stats)
+    rays = st["rays"]
+    flops = FLOP_NODE * st["nodes"] + FLOP_TRI * (st["tris"] + st["near"]) + FLOP_ENTRY * K * N * S
+    # live HIP-event timing of the dominant kernel on the stream it runs on
+    kms = []
+    for _ in range(3):
+        t = ctypes.c_float(0.0)
+        uvc.irradiance_dense(sc, poses, lamp, path="lbvh", out=E, timing=t)
+        kms.append(t.value)
+    kernel_ms = float(np.mean(kms))
+    achieved = flops / (kernel_ms * 1e-3) / 1e12
+    log(f"stats {st}; kernel {kernel_ms:.3f} ms; {achieved:.2f} TFLOP/s algorithmic")
+
+    paths = {"lbvh": {"kernel_ms": kernel_ms, "rays_per_s": rays / (kernel_ms * 1e-3)}}
+    if not args.no_compare:
+        for tp in (1, 4, 16, 64):
+            t = ctypes.c_float(0.0)
+            uvc.irradiance_dense(sc, poses, lamp, path="lbvh", out=E, timing=t, packet_poses=tp)
+            paths[f"lbvh_tp{tp}"] = {"kernel_ms": t.value, "rays_per_s": rays / (t.value * 1e-3)}
+        t = ctypes.c_float(0.0)
+        uvc.irradiance_dense(sc, poses, lamp, path="lbvh", out=E, timing=t, flags=uvc.FLAG_NO_NEAR)
+        paths["lbvh_no_near"] = {"kernel_ms": t.value, "rays_per_s": rays / (t.value * 1e-3)}
+        sub = poses[:: max(1, K // 16)][:16].contiguous()
+        for pth in ("lbvh", "brute"):
+            sst = uvc.new_stats(dev)
+            uvc.irradiance_dense(sc, sub, lamp, path=pth, stats=sst)
+            t = ctypes.c_float(0.0)
+            uvc.irradiance_dense(sc, sub, lamp, path=pth, timing=t)
+            r = uvc.stats_dict(sst)["rays"]
+            paths[pth + "_16poses"] = {"kernel_ms": t.value, "rays_per_s": r / (t.value * 1e-3)}
+        log(f"paths {paths}")
+    sc.close()
+
+    value = rays / (ms_per_step * 1e-3)
+    traffic = traffic_from_profile()
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"ward 8x6x3 m, 6 beds + 10 cuboids, N={N} triangles, K={K} poses, "
+                               f"tower lamp {S} x 20 W; step = scene build + dense E",
+                   "K": K, "N": N, "S": S, "path": "lbvh"},
+        "entries_per_s": K * N / (ms_per_step * 1e-3),
+        "rays_per_step": rays,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32, "traffic": traffic, "kernel": KERNEL,
+                     "kernel_ms": kernel_ms, "algorithmic_flops_per_launch": flops,
+                     "peak_unpacked": PEAK_FP32_UNPACKED, "frac_unpacked": achieved / PEAK_FP32_UNPACKED,
+                     "e_write_GBps": K * N * 4 / (kernel_ms * 1e-3) / 1e9,
+                     "counts": st, "source_hash": source_hash()},
+        "paths": paths,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+        log(f"cpu baseline {out['cpu_baseline']}")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -118,6 +118,11 @@ typedef struct {
 
 enum { UVC_PATH_AUTO = 0, UVC_PATH_LBVH = 1, UVC_PATH_BRUTE = 2 };
 
+/* UVC_FLAG_NO_NEAR: the hierarchy path walks every segment to its target
+ * instead of stopping short and testing the element's near list (same
+ * results, slower; for testing). */
+enum { UVC_FLAG_NO_NEAR = 1 };
+
 /* Counters accumulated by an instrumented launch (opts.stats_dev). */
 enum {
     UVC_STAT_RAYS = 0,       /* occlusion segments cast (front-facing triples) */
@@ -126,20 +131,31 @@ enum {
     UVC_STAT_RECHECK = 3,    /* triangle decisions re-taken in FP64            */
     UVC_STAT_FRONT64 = 4,    /* front-facing decisions re-taken in FP64        */
     UVC_STAT_VISIBLE = 5,    /* visible (pose, source, element) triples        */
+    UVC_STAT_STEPS = 6,      /* wavefront traversal steps (one node each)      */
+    UVC_STAT_NEAR = 7,       /* per-ray near-list segment/triangle tests       */
     UVC_STAT_N = 8
 };
 
 typedef struct {
     int32_t path;        /* UVC_PATH_*; AUTO picks the brute-force path for
                             small meshes and the hierarchy otherwise          */
-    int32_t reserved0;
+    int32_t packet_poses; /* hierarchy path: poses per wavefront packet, a
+                            power of two in [1, 64] (0 = 64); the 64 lanes
+                            hold packet_poses poses x 64/packet_poses
+                            elements                                          */
     float band_scale;    /* multiplies the FP32 decision bands: 1 = default;
                             +inf re-takes every decision in FP64 (slow);
                             0 leaves only exact ties to FP64 (unsafe: FP32
                             may then disagree with the exact predicate)       */
     int32_t tile_tris;   /* brute-force path: triangles per LDS tile (0 = default) */
+    int32_t flags;       /* UVC_FLAG_* bits                                   */
+    int32_t reserved1;
     uint64_t* stats_dev; /* NULL, or UVC_STAT_N device counters that an
                             instrumented (slower) kernel adds to              */
+    float* kernel_ms;    /* NULL, or host float: HIP events are recorded on
+                            hip_stream around the irradiance kernel launches,
+                            the call synchronises and stores their elapsed
+                            milliseconds here (for measurement)              */
 } uvc_opts;
 
 /* Dense irradiance matrix.
@@ -147,6 +163,7 @@ typedef struct {
  *               or (x, y, z).  Source j of pose k sits at
  *               (x_k, y_k, fl32(z_k + dz[j])).  Every source point must lie
  *               within 2 * max_abs_coord of the origin (UVC_EINVAL otherwise).
+ *               The poses are copied to the host once for validation.
  *   E_dev     : K x N FP32, caller-owned, fully overwritten:
  *               E[k*N + i] = sum over j ascending (FP32 adds) of
  *                 V_kji * P_j * <p_kj - c_i, n_i> / (4 pi |p_kj - c_i|^3),
@@ -158,8 +175,8 @@ typedef struct {
  *   vis_dev   : NULL, or K x N uint32 with bit j = V_kji.
  * Visibility is decided in FP32 where the FP32 value is provably on the same
  * side of zero as the exact one, and re-decided in FP64 otherwise, so every
- * bit equals the FP64 segment/triangle predicate.  Validates poses on the
- * device and synchronises once before the main launch. */
+ * bit equals the FP64 segment/triangle predicate.  Synchronises hip_stream
+ * before the main launch (pose validation); the launch itself is async. */
 uvc_status uvc_compute_irradiance_dense(const uvc_scene* scene,
                                         const float* poses_dev, int64_t K,
                                         int32_t pose_dim, const uvc_lamp* lamp,

@@ -20,6 +20,7 @@
 // the same side of zero as the exact one; otherwise the FP64 predicate is
 // evaluated with the same operations in the same order as its definition.
 #include "uvc_common.hpp"
+#include "fp64_predicate.hpp"
 
 #include <algorithm>
 #include <cfloat>
@@ -40,70 +41,25 @@ struct IrrParams {
     const float* tri;
     const float* elem;
     const float* nodes;
-    const float* poses;  // already offset to the first pose of the launch
-    int64_t K;           // poses in this launch
+    const int32_t* near_off;
+    const int32_t* near;
+    const float* poses;        // poses of this launch (row k = pose k of the launch)
+    const int32_t* pose_order; // hierarchy path: packet position -> pose row
+    int64_t K;                 // poses in this launch
     int64_t N;
-    int64_t ntiles;      // ceil(N / 64)
-    int64_t nquads;      // ceil(ntiles / 4)
+    int64_t ntiles;            // element tiles per pose tile
+    int64_t nquads;            // ceil(ntiles / 4)
+    int64_t kgroups;           // pose tiles (hierarchy) or poses (brute force)
     int32_t pose_dim;
-    int32_t tile_tris;   // brute-force LDS tile
+    int32_t tile_tris;         // brute-force LDS tile
+    int32_t tk_log2;           // hierarchy path: log2 of the poses per packet (0..6)
+    int32_t use_near;          // hierarchy path: stop segments short and test near lists
     float tau_f, tau_e, tau_p;
-    float* E;            // rows of this launch, K x N
-    uint32_t* vis;       // NULL or K x N
+    float* E;                  // rows of this launch, K x N
+    uint32_t* vis;             // NULL or K x N
     unsigned long long* stats;
     LampArgs lamp;
 };
-
-// ------------------------------------------------------------------ FP64
-// The segment/triangle predicate, evaluated in FP64 on the FP32 inputs:
-// open segment O->T, closed triangle v0 v1 v2.  Same operations and order as
-// its definition: m = (v1-v0) x (v2-v0); the plane sides (O-v0).m and
-// (T-v0).m must be strictly opposite; with D = T-O and a, b, c = v0-O,
-// v1-O, v2-O the edge orientations D.(b x c), D.(c x a), D.(a x b) must not
-// be of mixed strict sign.  Dot products are ((x x' + y y') + z z').
-__device__ __noinline__ bool seg_tri_fp64(float fox, float foy, float foz, float ftx, float fty, float ftz,
-                                          float f0x, float f0y, float f0z, float f1x, float f1y, float f1z,
-                                          float f2x, float f2y, float f2z) {
-#pragma clang fp contract(off)
-    const double ox = fox, oy = foy, oz = foz, tx = ftx, ty = fty, tz = ftz;
-    const double v0x = f0x, v0y = f0y, v0z = f0z, v1x = f1x, v1y = f1y, v1z = f1z, v2x = f2x, v2y = f2y, v2z = f2z;
-    const double e1x = v1x - v0x, e1y = v1y - v0y, e1z = v1z - v0z;
-    const double e2x = v2x - v0x, e2y = v2y - v0y, e2z = v2z - v0z;
-    const double mx = e1y * e2z - e1z * e2y;
-    const double my = e1z * e2x - e1x * e2z;
-    const double mz = e1x * e2y - e1y * e2x;
-    const double sO = ((ox - v0x) * mx + (oy - v0y) * my) + (oz - v0z) * mz;
-    const double sT = ((tx - v0x) * mx + (ty - v0y) * my) + (tz - v0z) * mz;
-    if (!((sO > 0.0 && sT < 0.0) || (sO < 0.0 && sT > 0.0))) return false;
-    const double Dx = tx - ox, Dy = ty - oy, Dz = tz - oz;
-    const double ax = v0x - ox, ay = v0y - oy, az = v0z - oz;
-    const double bx = v1x - ox, by = v1y - oy, bz = v1z - oz;
-    const double cx = v2x - ox, cy = v2y - oy, cz = v2z - oz;
-    const double bcx = by * cz - bz * cy, bcy = bz * cx - bx * cz, bcz = bx * cy - by * cx;
-    const double cax = cy * az - cz * ay, cay = cz * ax - cx * az, caz = cx * ay - cy * ax;
-    const double abx = ay * bz - az * by, aby = az * bx - ax * bz, abz = ax * by - ay * bx;
-    const double U = (Dx * bcx + Dy * bcy) + Dz * bcz;
-    const double V = (Dx * cax + Dy * cay) + Dz * caz;
-    const double W = (Dx * abx + Dy * aby) + Dz * abz;
-    const bool neg = (U < 0.0) || (V < 0.0) || (W < 0.0);
-    const bool pos = (U > 0.0) || (V > 0.0) || (W > 0.0);
-    return !(neg && pos);
-}
-
-// Front-facing test in FP64: (p - c) . ((v1-v0) x (v2-v0)) > 0, strict.
-__device__ __noinline__ bool front_fp64(float fpx, float fpy, float fpz, float fcx, float fcy, float fcz,
-                                        float f0x, float f0y, float f0z, float f1x, float f1y, float f1z,
-                                        float f2x, float f2y, float f2z) {
-#pragma clang fp contract(off)
-    const double v0x = f0x, v0y = f0y, v0z = f0z;
-    const double e1x = (double)f1x - v0x, e1y = (double)f1y - v0y, e1z = (double)f1z - v0z;
-    const double e2x = (double)f2x - v0x, e2y = (double)f2y - v0y, e2z = (double)f2z - v0z;
-    const double mx = e1y * e2z - e1z * e2y;
-    const double my = e1z * e2x - e1x * e2z;
-    const double mz = e1x * e2y - e1y * e2x;
-    const double dx = (double)fpx - (double)fcx, dy = (double)fpy - (double)fcy, dz = (double)fpz - (double)fcz;
-    return ((dx * mx + dy * my) + dz * mz) > 0.0;
-}
 
 // ------------------------------------------------------------------ FP32
 struct Ray {
@@ -112,6 +68,7 @@ struct Ray {
     float ix, iy, iz;     // 1 / D, zero components replaced by +-1e-30
     float nx, ny, nz;     // -O / D
     float l1;             // |D|_1
+    float tmax;           // hierarchy culling covers t in [0, tmax]
     float tx, ty, tz;     // target: the element centroid
     int self;             // input index of the target's own triangle
 };
@@ -133,16 +90,17 @@ __device__ __forceinline__ void make_ray(Ray& r, float ox, float oy, float oz, f
     r.ix = guard_inv(r.dx); r.iy = guard_inv(r.dy); r.iz = guard_inv(r.dz);
     r.nx = -ox * r.ix; r.ny = -oy * r.iy; r.nz = -oz * r.iz;
     r.l1 = fabsf(r.dx) + fabsf(r.dy) + fabsf(r.dz);
+    r.tmax = 1.0f;
     r.self = self;
 }
 
-// Does the segment's parameter interval [0, 1] meet the (padded) box?
+// Does the segment's parameter interval [0, tmax] meet the (padded) box?
 __device__ __forceinline__ bool slab(const Ray& r, float lx, float ly, float lz, float hx, float hy, float hz) {
     const float t0x = fmaf(lx, r.ix, r.nx), t1x = fmaf(hx, r.ix, r.nx);
     const float t0y = fmaf(ly, r.iy, r.ny), t1y = fmaf(hy, r.iy, r.ny);
     const float t0z = fmaf(lz, r.iz, r.nz), t1z = fmaf(hz, r.iz, r.nz);
     const float tn = fmaxf(max3f(fminf(t0x, t1x), fminf(t0y, t1y), fminf(t0z, t1z)), 0.0f);
-    const float tf = fminf(min3f(fmaxf(t0x, t1x), fmaxf(t0y, t1y), fmaxf(t0z, t1z)), 1.0f);
+    const float tf = fminf(min3f(fmaxf(t0x, t1x), fmaxf(t0y, t1y), fmaxf(t0z, t1z)), r.tmax);
     return tn <= tf;
 }
 
@@ -172,23 +130,32 @@ __device__ __noinline__ int tri_rare(float rox, float roy, float roz, float rtx,
     return 2 | (seg_tri_fp64(rox, roy, roz, rtx, rty, rtz, v0x, v0y, v0z, v1x, v1y, v1z, v2x, v2y, v2z) ? 1 : 0);
 }
 
-// Full per-lane triangle decision for the hierarchy path.  The vertex
-// differences and cross products are the same for every lane (shared
-// origin); only the three dot products with D are per lane.
-__device__ __forceinline__ bool tri_hit(const Ray& r, float v0x, float v0y, float v0z, float v1x, float v1y,
-                                        float v1z, float v2x, float v2y, float v2z, float tau_e, float tau_p,
+// Full per-lane triangle decision for the hierarchy path.  t is the
+// triangle record (uniform across the wave).  The edge cross products
+// (vi - O) x (vj - vi) are the same for every lane (shared origin); only the
+// three dot products with D are per lane.  Forming them from the short edge
+// vector keeps their FP32 error proportional to |vi - O| |vj - vi|, the
+// scale of the edge orientation itself.
+__device__ __forceinline__ bool tri_hit(const Ray& r, const float* __restrict__ t, float tau_e, float tau_p,
                                         int* rechecks) {
+    const float v0x = t[0], v0y = t[1], v0z = t[2], v1x = t[3], v1y = t[4], v1z = t[5];
+    const float v2x = t[6], v2y = t[7], v2z = t[8];
+    const float e01x = t[TRI_E01], e01y = t[TRI_E01 + 1], e01z = t[TRI_E01 + 2];
+    const float e12x = t[TRI_E12], e12y = t[TRI_E12 + 1], e12z = t[TRI_E12 + 2];
+    const float e20x = t[TRI_E20], e20y = t[TRI_E20 + 1], e20z = t[TRI_E20 + 2];
+    const float L = t[TRI_L];
     const float ax = v0x - r.ox, ay = v0y - r.oy, az = v0z - r.oz;
     const float bx = v1x - r.ox, by = v1y - r.oy, bz = v1z - r.oz;
     const float cx = v2x - r.ox, cy = v2y - r.oy, cz = v2z - r.oz;
-    const float ux = fmaf(by, cz, -bz * cy), uy = fmaf(bz, cx, -bx * cz), uz = fmaf(bx, cy, -by * cx);
-    const float vx = fmaf(cy, az, -cz * ay), vy = fmaf(cz, ax, -cx * az), vz = fmaf(cx, ay, -cy * ax);
-    const float wx = fmaf(ay, bz, -az * by), wy = fmaf(az, bx, -ax * bz), wz = fmaf(ax, by, -ay * bx);
+    const float ux = fmaf(by, e12z, -bz * e12y), uy = fmaf(bz, e12x, -bx * e12z), uz = fmaf(bx, e12y, -by * e12x);
+    const float vx = fmaf(cy, e20z, -cz * e20y), vy = fmaf(cz, e20x, -cx * e20z), vz = fmaf(cx, e20y, -cy * e20x);
+    const float wx = fmaf(ay, e01z, -az * e01y), wy = fmaf(az, e01x, -ax * e01z), wz = fmaf(ax, e01y, -ay * e01x);
     const float g = max3f(amax3(ax, ay, az), amax3(bx, by, bz), amax3(cx, cy, cz));
+    const float kap = tau_e * g * fmaf(0x1p-28f, g, L);
     const float U = fmaf(r.dz, uz, fmaf(r.dy, uy, r.dx * ux));
     const float V = fmaf(r.dz, vz, fmaf(r.dy, vy, r.dx * vx));
     const float W = fmaf(r.dz, wz, fmaf(r.dy, wy, r.dx * wx));
-    const float be = (tau_e * g * g) * r.l1;
+    const float be = kap * r.l1;
     const float mn = min3f(U, V, W), mx = max3f(U, V, W);
     if (mn < -be && mx > be) return false;
     const int q = tri_rare(r.ox, r.oy, r.oz, r.tx, r.ty, r.tz, v0x, v0y, v0z, v1x, v1y, v1z, v2x, v2y, v2z, mn, mx,
@@ -222,19 +189,20 @@ __device__ __forceinline__ unsigned long long wave_sum_u32(unsigned v) {
     return s;
 }
 
-// Workgroup (4 packets) -> (pose, quad of tiles), spreading consecutive
-// logical workgroups over the 8 XCDs in contiguous ranges so that each XCD's
-// L2 serves a compact region of the element space.
-__device__ __forceinline__ void block_coords(const IrrParams& P, int64_t& kk, int64_t& quad) {
+// Workgroup (4 packets) -> (pose group, quad of element tiles), spreading
+// consecutive logical workgroups over the 8 XCDs in contiguous ranges so
+// that each XCD's L2 serves a compact region of the element space.
+__device__ __forceinline__ void block_coords(const IrrParams& P, int64_t& kg, int64_t& quad) {
     const uint64_t B = gridDim.x, b = blockIdx.x;
     const uint64_t xcd = b & 7u, loc = b >> 3, per = B >> 3, rem = B & 7u;
     const uint64_t logical = xcd * per + (xcd < rem ? xcd : rem) + loc;
-    kk = (int64_t)(logical % (uint64_t)P.K);
-    quad = (int64_t)(logical / (uint64_t)P.K);
+    kg = (int64_t)(logical % (uint64_t)P.kgroups);
+    quad = (int64_t)(logical / (uint64_t)P.kgroups);
 }
 
 struct ElemLane {
     float cx, cy, cz, nx, ny, nz;
+    float rho_t;
     int self;
     bool valid;
 };
@@ -247,8 +215,9 @@ __device__ __forceinline__ ElemLane load_elem(const IrrParams& P, int64_t slot) 
         const float4 a = q[0], b = q[1];
         e.cx = a.x; e.cy = a.y; e.cz = a.z; e.nx = a.w; e.ny = b.x; e.nz = b.y;
         e.self = __float_as_int(b.z);
+        e.rho_t = b.w;
     } else {
-        e.cx = e.cy = e.cz = e.nx = e.ny = e.nz = 0.f;
+        e.cx = e.cy = e.cz = e.nx = e.ny = e.nz = e.rho_t = 0.f;
         e.self = -1;
     }
     return e;
@@ -268,7 +237,7 @@ __device__ __forceinline__ bool front_face(const IrrParams& P, const ElemLane& e
 template <bool STATS>
 __device__ __forceinline__ unsigned long long traverse(const IrrParams& P, const Ray& r, unsigned long long live,
                                                        unsigned long long& n_nodes, unsigned long long& n_tris,
-                                                       int* rechecks) {
+                                                       unsigned long long& n_steps, int* rechecks) {
     const int lane = lane_id();
     unsigned long long occl = 0;
     if (P.N < 2) return 0;
@@ -286,23 +255,26 @@ __device__ __forceinline__ unsigned long long traverse(const IrrParams& P, const
         const bool hR = in_m && slab(r, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w);
         unsigned long long mL = __ballot(hL), mR = __ballot(hR);
         const int cl = __float_as_int(q3.x), cr = __float_as_int(q3.y);
-        if (STATS) n_nodes += (unsigned long long)__popcll(m);
+        if (STATS) {
+            n_nodes += (unsigned long long)__popcll(m);
+            ++n_steps;
+        }
         if (cl < 0 && mL) {
             const float* t = tri + (int64_t)(~cl) * TRI_WORDS;
-            const int who = __float_as_int(t[9]);
+            const int who = __float_as_int(t[TRI_ID]);
             const bool act = ((mL >> lane) & 1ull) && r.self != who;
             bool h = false;
-            if (act) h = tri_hit(r, t[0], t[1], t[2], t[3], t[4], t[5], t[6], t[7], t[8], P.tau_e, P.tau_p, rechecks);
+            if (act) h = tri_hit(r, t, P.tau_e, P.tau_p, rechecks);
             if (STATS) n_tris += (unsigned long long)__popcll(__ballot(act));
             occl |= __ballot(h);
             mL = 0;
         }
         if (cr < 0 && mR) {
             const float* t = tri + (int64_t)(~cr) * TRI_WORDS;
-            const int who = __float_as_int(t[9]);
+            const int who = __float_as_int(t[TRI_ID]);
             const bool act = ((mR >> lane) & 1ull) && r.self != who;
             bool h = false;
-            if (act) h = tri_hit(r, t[0], t[1], t[2], t[3], t[4], t[5], t[6], t[7], t[8], P.tau_e, P.tau_p, rechecks);
+            if (act) h = tri_hit(r, t, P.tau_e, P.tau_p, rechecks);
             if (STATS) n_tris += (unsigned long long)__popcll(__ballot(act));
             occl |= __ballot(h);
             mR = 0;
@@ -312,7 +284,8 @@ __device__ __forceinline__ unsigned long long traverse(const IrrParams& P, const
         if (mL && mR) {
             const int hint = __float_as_int(q3.z);
             const int axis = hint & 3;
-            const float o = axis == 0 ? r.ox : (axis == 1 ? r.oy : r.oz);
+            const float o_lane = axis == 0 ? r.ox : (axis == 1 ? r.oy : r.oz);
+            const float o = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(o_lane)));
             const bool left_first = ((o < q3.w) == ((hint & 4) != 0));
             const int nnear = left_first ? cl : cr, nfar = left_first ? cr : cl;
             const unsigned long long mnear = left_first ? mL : mR, mfar = left_first ? mR : mL;
@@ -350,33 +323,64 @@ __device__ __forceinline__ unsigned long long traverse(const IrrParams& P, const
     return occl;
 }
 
+// Hierarchy path.  A packet is TK = 2^tk_log2 poses x TE = 64 / TK elements:
+// lane = (pose kk, element ee).  Poses are visited in a compact 2D order
+// (pose_order) so that a packet's origins are close together; with TK = 64
+// the 64 segments of a source share their target and diverge only towards
+// their nearby origins.  Each lane sums its element's terms over the sources
+// in ascending order, exactly like the brute-force path.
 template <bool STATS>
 __global__ __launch_bounds__(256) void k_irr_lbvh(IrrParams P) {
-    int64_t kk, quad;
-    block_coords(P, kk, quad);
+    int64_t kg, quad;
+    block_coords(P, kg, quad);
     const int lane = lane_id(), w = (int)(threadIdx.x >> 6);
+    const int tkl = P.tk_log2, tel = 6 - tkl;
+    const int kk = lane >> tel, ee = lane & ((1 << tel) - 1);
     const int64_t tile = quad * 4 + w;
     if (tile >= P.ntiles) return;
-    const int64_t slot = tile * 64 + lane;
+    const int64_t kpos = (kg << tkl) + kk;
+    const bool kok = kpos < P.K;
+    const int64_t k = kok ? P.pose_order[kpos] : 0;
+    const int64_t slot = (tile << tel) + ee;
     const ElemLane e = load_elem(P, slot);
-    const float* pp = P.poses + kk * P.pose_dim;
-    const float px = pp[0], py = pp[1], pz0 = (P.pose_dim == 3) ? pp[2] : 0.0f;
+    const bool ok = kok && e.valid;
+    const float* pp = P.poses + k * P.pose_dim;
+    const float px = kok ? pp[0] : 0.0f, py = kok ? pp[1] : 0.0f;
+    const float pz0 = (kok && P.pose_dim == 3) ? pp[2] : 0.0f;
+    const int32_t nb = ok ? P.near_off[slot] : 0, ne = ok ? P.near_off[slot + 1] : 0;
     float acc = 0.0f;
     uint32_t bits = 0;
     int rechecks = 0, f64 = 0;
-    unsigned long long n_rays = 0, n_nodes = 0, n_tris = 0, n_vis = 0;
+    unsigned n_near = 0;
+    unsigned long long n_rays = 0, n_nodes = 0, n_tris = 0, n_vis = 0, n_steps = 0;
     for (int j = 0; j < P.lamp.S; ++j) {
         const float oz = pz0 + P.lamp.dz[j];
         const float dx = px - e.cx, dy = py - e.cy, dz = oz - e.cz;
         const float s = cos_numerator(dx, dy, dz, e.nx, e.ny, e.nz);
         bool f = false;
-        if (e.valid) f = front_face(P, e, slot, px, py, oz, dx, dy, dz, s, &f64);
+        if (ok) f = front_face(P, e, slot, px, py, oz, dx, dy, dz, s, &f64);
         const unsigned long long live = __ballot(f);
         if (!live) continue;
         Ray r;
         make_ray(r, px, py, oz, e.cx, e.cy, e.cz, e.self);
-        const unsigned long long occl = traverse<STATS>(P, r, live, n_nodes, n_tris, &rechecks);
-        const bool vis = f && !((occl >> lane) & 1ull);
+        bool trav = f;
+        if (P.use_near) {
+            // stop rho_t short of the target; the near list covers the rest
+            const float r2 = __builtin_fmaf(r.dz, r.dz, __builtin_fmaf(r.dy, r.dy, r.dx * r.dx));
+            r.tmax = 1.0f - e.rho_t * __builtin_amdgcn_rsqf(r2);
+            trav = f && r.tmax > 0.0f;
+        }
+        const unsigned long long tlive = __ballot(trav);
+        unsigned long long occl = 0;
+        if (tlive) occl = traverse<STATS>(P, r, tlive, n_nodes, n_tris, n_steps, &rechecks);
+        bool vis = f && !((occl >> lane) & 1ull);
+        if (P.use_near && vis) {
+            for (int32_t q = nb; q < ne && vis; ++q) {
+                const float* t = P.tri + (int64_t)P.near[q] * TRI_WORDS;
+                if (tri_hit(r, t, P.tau_e, P.tau_p, &rechecks)) vis = false;
+                if (STATS) ++n_near;
+            }
+        }
         if (STATS) {
             n_rays += (unsigned long long)__popcll(live);
             n_vis += (unsigned long long)__popcll(__ballot(vis));
@@ -386,12 +390,13 @@ __global__ __launch_bounds__(256) void k_irr_lbvh(IrrParams P) {
             bits |= 1u << j;
         }
     }
-    if (e.valid) {
-        P.E[kk * P.N + e.self] = acc;
-        if (P.vis) P.vis[kk * P.N + e.self] = bits;
+    if (ok) {
+        P.E[k * P.N + e.self] = acc;
+        if (P.vis) P.vis[k * P.N + e.self] = bits;
     }
     if (STATS) {
         const unsigned long long rc = wave_sum_u32((unsigned)rechecks), fc = wave_sum_u32((unsigned)f64);
+        const unsigned long long nn = wave_sum_u32(n_near);
         if (lane == 0) {
             atomicAdd(P.stats + UVC_STAT_RAYS, n_rays);
             atomicAdd(P.stats + UVC_STAT_NODES, n_nodes);
@@ -399,6 +404,8 @@ __global__ __launch_bounds__(256) void k_irr_lbvh(IrrParams P) {
             atomicAdd(P.stats + UVC_STAT_RECHECK, rc);
             atomicAdd(P.stats + UVC_STAT_FRONT64, fc);
             atomicAdd(P.stats + UVC_STAT_VISIBLE, n_vis);
+            atomicAdd(P.stats + UVC_STAT_STEPS, n_steps);
+            atomicAdd(P.stats + UVC_STAT_NEAR, nn);
         }
     }
 }
@@ -408,7 +415,7 @@ template <bool STATS>
 __global__ __launch_bounds__(256) void k_irr_brute(IrrParams P) {
     extern __shared__ float4 lds[];  // tile_tris x 3 float4
     int64_t kk, quad;
-    block_coords(P, kk, quad);
+    block_coords(P, kk, quad);  // kgroups = K: one pose per workgroup
     const int lane = lane_id(), w = (int)(threadIdx.x >> 6), tid = (int)threadIdx.x;
     const int64_t tile = quad * 4 + w;
     const int64_t slot = tile * 64 + lane;
@@ -437,19 +444,22 @@ __global__ __launch_bounds__(256) void k_irr_brute(IrrParams P) {
                 __syncthreads();
                 for (int t = tid; t < cnt; t += 256) {
                     const float* tp = P.tri + (base + t) * TRI_WORDS;
-                    const float4 q0 = reinterpret_cast<const float4*>(tp)[0];
-                    const float4 q1 = reinterpret_cast<const float4*>(tp)[1];
-                    const float4 q2 = reinterpret_cast<const float4*>(tp)[2];
+                    const float4* qp = reinterpret_cast<const float4*>(tp);
+                    const float4 q0 = qp[0], q1 = qp[1], q2 = qp[2], q3 = qp[3], q4 = qp[4];
+                    // q0 = v0xyz v1x, q1 = v1yz v2xy, q2 = v2z e01xyz, q3 = e12xyz e20x, q4 = e20yz L id
                     const float ax = q0.x - px, ay = q0.y - py, az = q0.z - oz;
                     const float bx = q0.w - px, by = q1.x - py, bz = q1.y - oz;
                     const float cx = q1.z - px, cy = q1.w - py, cz = q2.x - oz;
+                    const float e01x = q2.y, e01y = q2.z, e01z = q2.w;
+                    const float e12x = q3.x, e12y = q3.y, e12z = q3.z;
+                    const float e20x = q3.w, e20y = q4.x, e20z = q4.y;
                     const float g = max3f(amax3(ax, ay, az), amax3(bx, by, bz), amax3(cx, cy, cz));
                     float4 o0, o1, o2;
-                    o0.x = fmaf(by, cz, -bz * cy); o0.y = fmaf(bz, cx, -bx * cz); o0.z = fmaf(bx, cy, -by * cx);
-                    o0.w = fmaf(cy, az, -cz * ay); o1.x = fmaf(cz, ax, -cx * az); o1.y = fmaf(cx, ay, -cy * ax);
-                    o1.z = fmaf(ay, bz, -az * by); o1.w = fmaf(az, bx, -ax * bz); o2.x = fmaf(ax, by, -ay * bx);
-                    o2.y = P.tau_e * g * g;
-                    o2.z = q2.y;  // input index (int bits)
+                    o0.x = fmaf(by, e12z, -bz * e12y); o0.y = fmaf(bz, e12x, -bx * e12z); o0.z = fmaf(bx, e12y, -by * e12x);
+                    o0.w = fmaf(cy, e20z, -cz * e20y); o1.x = fmaf(cz, e20x, -cx * e20z); o1.y = fmaf(cx, e20y, -cy * e20x);
+                    o1.z = fmaf(ay, e01z, -az * e01y); o1.w = fmaf(az, e01x, -ax * e01z); o2.x = fmaf(ax, e01y, -ay * e01x);
+                    o2.y = P.tau_e * g * fmaf(0x1p-28f, g, q4.z);
+                    o2.z = q4.w;  // input index (int bits)
                     o2.w = 0.f;
                     lds[3 * t + 0] = o0;
                     lds[3 * t + 1] = o1;
@@ -503,19 +513,6 @@ __global__ __launch_bounds__(256) void k_irr_brute(IrrParams P) {
             atomicAdd(P.stats + UVC_STAT_VISIBLE, n_vis);
         }
     }
-}
-
-// ------------------------------------------------------------ validation
-__global__ void k_pose_check(const float* __restrict__ poses, int64_t K, int pd, float dzmin, float dzmax, float lim,
-                             unsigned* __restrict__ flag) {
-    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k >= K) return;
-    const float x = poses[k * pd], y = poses[k * pd + 1], z = (pd == 3) ? poses[k * pd + 2] : 0.0f;
-    unsigned f = 0;
-    if (!isfinite(x) || !isfinite(y) || !isfinite(z)) f |= 1u;
-    const float z0 = z + dzmin, z1 = z + dzmax;
-    if (fabsf(x) > lim || fabsf(y) > lim || fabsf(z0) > lim || fabsf(z1) > lim) f |= 2u;
-    if (f) atomicOr(flag, f);
 }
 
 // ------------------------------------------------------------ CSR pieces
@@ -611,43 +608,86 @@ static uvc_status make_params(const uvc_scene* s, const float* poses, int64_t K,
     P.tri = s->tri;
     P.elem = s->elem;
     P.nodes = s->nodes;
+    P.near_off = s->near_off;
+    P.near = s->near;
+    P.use_near = (opts && (opts->flags & UVC_FLAG_NO_NEAR)) ? 0 : 1;
     P.poses = poses;
     P.K = K;
     P.N = s->n;
     P.pose_dim = pd;
-    P.ntiles = (s->n + 63) / 64;
-    P.nquads = (P.ntiles + 3) / 4;
+    int tk = (opts && opts->packet_poses > 0) ? opts->packet_poses : 64;
+    if (tk != 1 && tk != 2 && tk != 4 && tk != 8 && tk != 16 && tk != 32 && tk != 64)
+        return fail(UVC_EINVAL, "packet_poses must be a power of two in [1, 64]");
+    P.tk_log2 = 0;
+    while ((1 << P.tk_log2) < tk) ++P.tk_log2;
     P.tile_tris = (opts && opts->tile_tris > 0) ? opts->tile_tris : 512;
     if (P.tile_tris > 2048) return fail(UVC_EINVAL, "tile_tris must be <= 2048");
     P.stats = opts ? reinterpret_cast<unsigned long long*>(opts->stats_dev) : nullptr;
     return UVC_OK;
 }
 
-static uvc_status check_poses(const uvc_scene* s, const float* poses, int64_t K, int pd, const LampArgs& L,
-                              hipStream_t st) {
+// Poses are copied to the host once per call: validated there (finite, and
+// every source point within 2 * max_abs_coord of the origin, which bounds the
+// rounding the box padding has to absorb) and sorted into a compact order.
+static uvc_status fetch_poses(const uvc_scene* s, const float* poses, int64_t K, int pd, const LampArgs& L,
+                              hipStream_t st, std::vector<float>& hp) {
+    hp.assign((size_t)K * pd, 0.f);
     if (K == 0) return UVC_OK;
+    UVC_HIP(hipMemcpyAsync(hp.data(), poses, hp.size() * 4, hipMemcpyDeviceToHost, st));
+    UVC_HIP(hipStreamSynchronize(st));
     float dzmin = L.dz[0], dzmax = L.dz[0];
     for (int j = 1; j < L.S; ++j) {
         dzmin = std::min(dzmin, L.dz[j]);
         dzmax = std::max(dzmax, L.dz[j]);
     }
     const float lim = 2.0f * std::max(s->max_abs, 1e-30f);
-    unsigned* flag = nullptr;
-    UVC_TRY(dalloc_n(&flag, 1, "pose check flag"));
-    unsigned h = 0;
-    hipError_t e = hipMemsetAsync(flag, 0, 4, st);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_pose_check, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st, poses, K, pd, dzmin,
-                           dzmax, lim, flag);
-        e = hipGetLastError();
+    for (int64_t k = 0; k < K; ++k) {
+        const float x = hp[k * pd], y = hp[k * pd + 1], z = (pd == 3) ? hp[k * pd + 2] : 0.0f;
+        if (!std::isfinite(x) || !std::isfinite(y) || !std::isfinite(z))
+            return fail(UVC_EINVAL, "pose " + std::to_string(k) + ": a pose coordinate is not finite");
+        const float z0 = z + dzmin, z1 = z + dzmax;
+        if (std::fabs(x) > lim || std::fabs(y) > lim || std::fabs(z0) > lim || std::fabs(z1) > lim)
+            return fail(UVC_EINVAL, "pose " + std::to_string(k) +
+                                        ": a source point lies farther than 2 * max_abs_coord from the origin");
     }
-    if (e == hipSuccess) e = hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(flag);
-    if (e != hipSuccess) return fail(UVC_EDEVICE, std::string("pose validation: ") + hipGetErrorString(e));
-    if (h & 1u) return fail(UVC_EINVAL, "a pose coordinate is not finite");
-    if (h & 2u) return fail(UVC_EINVAL, "a source point lies farther than 2 * max_abs_coord from the origin");
     return UVC_OK;
+}
+
+static uint64_t spread_bits(uint64_t v, int stride) {
+    uint64_t r = 0;
+    for (int b = 0; b < 21; ++b) r |= ((v >> b) & 1ull) << (b * stride);
+    return r;
+}
+
+// Positions 0..kb-1 -> pose rows k0..k0+kb-1 (relative to k0) in Morton order
+// of the pose coordinates.
+static void pose_order(const std::vector<float>& hp, int pd, int64_t k0, int64_t kb, std::vector<int32_t>& order) {
+    float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int64_t k = 0; k < kb; ++k)
+        for (int a = 0; a < pd; ++a) {
+            const float v = hp[(k0 + k) * pd + a];
+            lo[a] = k ? std::min(lo[a], v) : v;
+            hi[a] = k ? std::max(hi[a], v) : v;
+        }
+    const int bits = pd == 2 ? 16 : 10;
+    const double cells = (double)(1u << bits);
+    std::vector<std::pair<uint64_t, int32_t>> key((size_t)kb);
+    for (int64_t k = 0; k < kb; ++k) {
+        uint64_t code = 0;
+        for (int a = 0; a < pd; ++a) {
+            const double ext = (double)hi[a] - (double)lo[a];
+            double q = ext > 0 ? ((double)hp[(k0 + k) * pd + a] - lo[a]) / ext * cells : 0.0;
+            q = std::min(std::max(q, 0.0), cells - 1.0);
+            code |= spread_bits((uint64_t)q, pd) << (pd - 1 - a);
+        }
+        key[(size_t)k] = {code, (int32_t)k};
+    }
+    std::stable_sort(key.begin(), key.end(),
+                     [](const std::pair<uint64_t, int32_t>& a, const std::pair<uint64_t, int32_t>& b) {
+                         return a.first < b.first;
+                     });
+    order.resize((size_t)kb);
+    for (int64_t k = 0; k < kb; ++k) order[(size_t)k] = key[(size_t)k].second;
 }
 
 static int choose_path(const uvc_scene* s, const uvc_opts* opts) {
@@ -657,13 +697,18 @@ static int choose_path(const uvc_scene* s, const uvc_opts* opts) {
 }
 
 // Launch the irradiance kernel for P.K poses into P.E / P.vis.
-static uvc_status launch_irr(const IrrParams& P, int path, hipStream_t st) {
-    if (P.K == 0 || P.N == 0) return UVC_OK;
-    const uint64_t blocks = (uint64_t)P.nquads * (uint64_t)P.K;
+static uvc_status launch_irr_impl(const IrrParams& P0, int path, hipStream_t st) {
+    if (P0.K == 0 || P0.N == 0) return UVC_OK;
+    IrrParams P = P0;
+    const int64_t per = (path == UVC_PATH_BRUTE) ? 64 : ((int64_t)1 << (6 - P.tk_log2));
+    P.ntiles = (P.N + per - 1) / per;
+    P.nquads = (P.ntiles + 3) / 4;
+    P.kgroups = (path == UVC_PATH_BRUTE) ? P.K : ((P.K + (1 << P.tk_log2) - 1) >> P.tk_log2);
+    const uint64_t blocks = (uint64_t)P.nquads * (uint64_t)P.kgroups;
     if (blocks > 0x7fffffffull) return fail(UVC_EUNSUPPORTED, "launch too large; split the poses");
     const bool stats = P.stats != nullptr;
     if (path == UVC_PATH_BRUTE) {
-        const size_t shm = (size_t)P.tile_tris * 48;
+        const size_t shm = (size_t)P.tile_tris * 48;  // 3 float4 per staged triangle
         if (stats)
             hipLaunchKernelGGL(k_irr_brute<true>, dim3((unsigned)blocks), dim3(256), shm, st, P);
         else
@@ -675,6 +720,27 @@ static uvc_status launch_irr(const IrrParams& P, int path, hipStream_t st) {
             hipLaunchKernelGGL(k_irr_lbvh<false>, dim3((unsigned)blocks), dim3(256), 0, st, P);
     }
     UVC_HIP(hipGetLastError());
+    return UVC_OK;
+}
+
+// Launch with optional HIP-event timing of the kernel on the caller's stream.
+static uvc_status launch_irr(const IrrParams& P, int path, hipStream_t st, float* kernel_ms) {
+    if (!kernel_ms) return launch_irr_impl(P, path, st);
+    hipEvent_t e0, e1;
+    UVC_HIP(hipEventCreate(&e0));
+    UVC_HIP(hipEventCreate(&e1));
+    uvc_status r = UVC_OK;
+    hipError_t he = hipEventRecord(e0, st);
+    if (he == hipSuccess) r = launch_irr_impl(P, path, st);
+    if (he == hipSuccess && r == UVC_OK) he = hipEventRecord(e1, st);
+    if (he == hipSuccess && r == UVC_OK) he = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (he == hipSuccess && r == UVC_OK) he = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (r != UVC_OK) return r;
+    if (he != hipSuccess) return fail(UVC_EDEVICE, std::string("kernel timing: ") + hipGetErrorString(he));
+    *kernel_ms += ms;
     return UVC_OK;
 }
 
@@ -694,6 +760,22 @@ struct uvc_csr_job {
     std::vector<Chunk> chunks;
 };
 
+// Device copy of a pose order (stream-ordered allocation, freed after use).
+static uvc_status upload_order(const std::vector<float>& hp, int pd, int64_t k0, int64_t kb, hipStream_t st,
+                               int32_t** out) {
+    std::vector<int32_t> ord;
+    pose_order(hp, pd, k0, kb, ord);
+    UVC_HIP(hipMallocAsync(reinterpret_cast<void**>(out), (size_t)std::max<int64_t>(kb, 1) * 4, st));
+    hipError_t e = hipMemcpyAsync(*out, ord.data(), (size_t)kb * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // ord is released on return
+    if (e != hipSuccess) {
+        (void)hipFreeAsync(*out, st);
+        *out = nullptr;
+        return fail(UVC_EDEVICE, std::string("pose order upload: ") + hipGetErrorString(e));
+    }
+    return UVC_OK;
+}
+
 extern "C" uvc_status uvc_compute_irradiance_dense(const uvc_scene* scene, const float* poses_dev, int64_t K,
                                                    int32_t pose_dim, const uvc_lamp* lamp, const uvc_opts* opts,
                                                    float* E_dev, uint32_t* vis_dev, void* hip_stream) {
@@ -702,10 +784,18 @@ extern "C" uvc_status uvc_compute_irradiance_dense(const uvc_scene* scene, const
     if (K == 0 || scene->n == 0) return UVC_OK;
     if (!E_dev) return fail(UVC_EINVAL, "E is NULL");
     hipStream_t st = (hipStream_t)hip_stream;
-    UVC_TRY(check_poses(scene, poses_dev, K, pose_dim, P.lamp, st));
+    std::vector<float> hp;
+    UVC_TRY(fetch_poses(scene, poses_dev, K, pose_dim, P.lamp, st, hp));
+    const int path = choose_path(scene, opts);
+    int32_t* dorder = nullptr;
+    if (path == UVC_PATH_LBVH) UVC_TRY(upload_order(hp, pose_dim, 0, K, st, &dorder));
+    P.pose_order = dorder;
     P.E = E_dev;
     P.vis = vis_dev;
-    return launch_irr(P, choose_path(scene, opts), st);
+    if (opts && opts->kernel_ms) *opts->kernel_ms = 0.f;
+    const uvc_status r = launch_irr(P, path, st, opts ? opts->kernel_ms : nullptr);
+    if (dorder) (void)hipFreeAsync(dorder, st);
+    return r;
 }
 
 static void free_job(uvc_csr_job* j) {
@@ -744,7 +834,8 @@ extern "C" uvc_status uvc_compute_irradiance_csr_begin(const uvc_scene* scene, c
         *job = J;
         return UVC_OK;
     }
-    uvc_status r = check_poses(scene, poses_dev, K, pose_dim, P.lamp, st);
+    std::vector<float> hp;
+    uvc_status r = fetch_poses(scene, poses_dev, K, pose_dim, P.lamp, st, hp);
     if (r != UVC_OK) {
         free_job(J);
         return r;
@@ -763,6 +854,7 @@ extern "C" uvc_status uvc_compute_irradiance_csr_begin(const uvc_scene* scene, c
         return r;
     }
     const int path = choose_path(scene, opts);
+    if (opts && opts->kernel_ms) *opts->kernel_ms = 0.f;
     hipError_t he = hipSuccess;
     for (int64_t k0 = 0; k0 < K && r == UVC_OK; k0 += Kb) {
         const int64_t kb = std::min(Kb, K - k0);
@@ -771,7 +863,11 @@ extern "C" uvc_status uvc_compute_irradiance_csr_begin(const uvc_scene* scene, c
         Q.K = kb;
         Q.E = scratch;
         Q.vis = nullptr;
-        r = launch_irr(Q, path, st);
+        int32_t* dorder = nullptr;
+        if (path == UVC_PATH_LBVH && (r = upload_order(hp, pose_dim, k0, kb, st, &dorder)) != UVC_OK) break;
+        Q.pose_order = dorder;
+        r = launch_irr(Q, path, st, opts ? opts->kernel_ms : nullptr);
+        if (dorder) (void)hipFreeAsync(dorder, st);
         if (r != UVC_OK) break;
         const unsigned rb = (unsigned)((kb * 64 + 255) / 256);
         hipLaunchKernelGGL(k_row_count, dim3(rb), dim3(256), 0, st, scratch, kb, N, J->counts + k0);

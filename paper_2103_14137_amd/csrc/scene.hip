@@ -1,6 +1,7 @@
 // Scene build: validation, surface elements, Morton codes, LSD radix sort,
 // Karras-style hierarchy emission and bottom-up box refit, all on the GPU.
 #include "uvc_common.hpp"
+#include "fp64_predicate.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -73,16 +74,23 @@ __device__ __forceinline__ uint32_t spread10(uint32_t v) {
     return v;
 }
 
-// 30-bit Morton code of each centroid in the scene box (10 bits per axis,
-// x in the most significant position).
-__global__ void k_morton(const float* __restrict__ c, int64_t n, float lox, float loy, float loz,
-                         float sx, float sy, float sz, uint32_t* __restrict__ key, int32_t* __restrict__ val) {
+// Sort key of each triangle: the dominant axis and sign of its normal
+// (6 classes, top 3 bits) above the 27-bit Morton code of its centroid in the
+// scene box (9 bits per axis, x most significant).  Surfaces of one
+// orientation thus form their own subtrees near the root, and a flat wall or
+// floor becomes a flat subtree that segments ending above it never enter.
+__global__ void k_morton(const float* __restrict__ c, const float* __restrict__ nrm, int64_t n, float lox,
+                         float loy, float loz, float sx, float sy, float sz, uint32_t* __restrict__ key,
+                         int32_t* __restrict__ val) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     float q[3] = {(c[3 * i] - lox) * sx, (c[3 * i + 1] - loy) * sy, (c[3 * i + 2] - loz) * sz};
     uint32_t b[3];
-    for (int a = 0; a < 3; ++a) b[a] = (uint32_t)fminf(fmaxf(q[a], 0.f), 1023.f);
-    key[i] = (spread10(b[0]) << 2) | (spread10(b[1]) << 1) | spread10(b[2]);
+    for (int a = 0; a < 3; ++a) b[a] = (uint32_t)fminf(fmaxf(q[a], 0.f), 511.f);
+    const float ax = fabsf(nrm[3 * i]), ay = fabsf(nrm[3 * i + 1]), az = fabsf(nrm[3 * i + 2]);
+    const int dom = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
+    const uint32_t cls = 2u * dom + (nrm[3 * i + dom] < 0.f ? 1u : 0u);
+    key[i] = (cls << 27) | (spread10(b[0]) << 2) | (spread10(b[1]) << 1) | spread10(b[2]);
     val[i] = (int32_t)i;
 }
 
@@ -196,15 +204,21 @@ __global__ void k_gather(const float* __restrict__ V, const int32_t* __restrict_
     if (s >= n) return;
     const int64_t i = perm[s];
     float* t = tri + s * TRI_WORDS;
+    float v[3][3];
     for (int k = 0; k < 3; ++k) {
         const int64_t vi = T[3 * i + k];
-        t[3 * k + 0] = V[3 * vi + 0];
-        t[3 * k + 1] = V[3 * vi + 1];
-        t[3 * k + 2] = V[3 * vi + 2];
+        for (int a = 0; a < 3; ++a) v[k][a] = t[3 * k + a] = V[3 * vi + a];
     }
-    t[9] = __int_as_float((int)i);
-    t[10] = 0.f;
-    t[11] = 0.f;
+    float L = 0.f;
+    for (int a = 0; a < 3; ++a) {
+        const float e01 = v[1][a] - v[0][a], e12 = v[2][a] - v[1][a], e20 = v[0][a] - v[2][a];
+        t[TRI_E01 + a] = e01;
+        t[TRI_E12 + a] = e12;
+        t[TRI_E20 + a] = e20;
+        L = fmaxf(L, fmaxf(fabsf(e01), fmaxf(fabsf(e12), fabsf(e20))));
+    }
+    t[TRI_L] = L;
+    t[TRI_ID] = __int_as_float((int)i);
     float* e = elem + s * ELEM_WORDS;
     e[0] = c[3 * i];
     e[1] = c[3 * i + 1];
@@ -213,7 +227,74 @@ __global__ void k_gather(const float* __restrict__ V, const int32_t* __restrict_
     e[4] = nrm[3 * i + 1];
     e[5] = nrm[3 * i + 2];
     e[6] = __int_as_float((int)i);
-    e[7] = area[i];
+    e[7] = NEAR_SCALE * L * (1.0f - 0x1p-10f);  // rho_t
+}
+
+// Near lists (see uvc_common.hpp): ball query of every element against the
+// hierarchy.  FILL = false counts, FILL = true writes at near_off[s].
+template <bool FILL>
+__global__ void k_near(const float* __restrict__ nodes, const float* __restrict__ tri,
+                       const float* __restrict__ elem, int64_t n, float pad, int32_t* __restrict__ off,
+                       int32_t* __restrict__ list) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const float* e = elem + s * ELEM_WORDS;
+    const float cx = e[0], cy = e[1], cz = e[2];
+    const float rho = NEAR_SCALE * tri[s * TRI_WORDS + TRI_L];
+    const float q = rho * (1.0f + 0x1p-9f) + 4.0f * pad;
+    const float q2 = q * q;
+    int32_t count = 0;
+    const int32_t base = FILL ? off[s] : 0;
+    int32_t stack[64];
+    int sp = 0;
+    if (n > 1) stack[sp++] = 0;
+    while (sp > 0) {
+        const float* nd = nodes + (int64_t)stack[--sp] * NODE_WORDS;
+        for (int side = 0; side < 2; ++side) {
+            const float* b = nd + 6 * side;
+            const float dx = fmaxf(fmaxf(b[0] - cx, cx - b[3]), 0.0f);
+            const float dy = fmaxf(fmaxf(b[1] - cy, cy - b[4]), 0.0f);
+            const float dz = fmaxf(fmaxf(b[2] - cz, cz - b[5]), 0.0f);
+            if (dx * dx + dy * dy + dz * dz > q2) continue;
+            const int32_t ref = __float_as_int(nd[12 + side]);
+            if (ref >= 0) {
+                if (sp < 64) stack[sp++] = ref;
+                continue;
+            }
+            const int64_t j = ~ref;
+            if (j == s) continue;
+            const float* t = tri + j * TRI_WORDS;
+            if (plane_side_fp64(cx, cy, cz, t[0], t[1], t[2], t[3], t[4], t[5], t[6], t[7], t[8]) == 0.0) continue;
+            if (FILL) list[base + count] = (int32_t)j;
+            ++count;
+        }
+    }
+    if (!FILL) off[s] = count;
+}
+
+// Exclusive scan of n int32 counts into out[0..n] (one block of 1024).
+__global__ __launch_bounds__(1024) void k_scan_i32(int32_t* __restrict__ a, int64_t n) {
+    __shared__ int64_t part[1024];
+    __shared__ int64_t carry;
+    const int tid = threadIdx.x;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int64_t b0 = 0; b0 <= n; b0 += 1024) {
+        const int64_t i = b0 + tid;
+        const int64_t v = (i < n) ? a[i] : 0;
+        part[tid] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int64_t t = (tid >= o) ? part[tid - o] : 0;
+            __syncthreads();
+            part[tid] += t;
+            __syncthreads();
+        }
+        if (i <= n) a[i] = (int32_t)(carry + part[tid] - v);
+        __syncthreads();
+        if (tid == 1023) carry += part[1023];
+        __syncthreads();
+    }
 }
 
 // Length of the common prefix of (code, slot) pairs i and j; -1 outside.
@@ -331,7 +412,7 @@ static inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n +
 
 static void free_scene(uvc_scene* s) {
     if (!s) return;
-    void* ptrs[] = {s->tri, s->elem, s->elem_c, s->elem_n, s->elem_a, s->perm, s->codes, s->nodes};
+    void* ptrs[] = {s->tri, s->elem, s->elem_c, s->elem_n, s->elem_a, s->perm, s->codes, s->nodes, s->near_off, s->near};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete s;
@@ -439,8 +520,8 @@ static uvc_status build_impl(const float* verts_in, int64_t nv, const int32_t* t
     uint32_t *k2 = nullptr, *hist = nullptr, *counters = nullptr;
     int32_t *v1 = nullptr, *v2 = nullptr, *ipar = nullptr, *lpar = nullptr, *ddepth = nullptr;
     const int nb = (int)((n + RS_TILE - 1) / RS_TILE);
-    if ((r = tmp.alloc(&dv, (size_t)nv * 3, "vertices")) != UVC_OK ||
-        (r = tmp.alloc(&dt, (size_t)n * 3, "indices")) != UVC_OK ||
+    if ((!on_dev && (r = tmp.alloc(&dv, (size_t)nv * 3, "vertices")) != UVC_OK) ||
+        (!on_dev && (r = tmp.alloc(&dt, (size_t)n * 3, "indices")) != UVC_OK) ||
         (r = tmp.alloc(&k2, (size_t)n, "sort keys")) != UVC_OK ||
         (r = tmp.alloc(&v1, (size_t)n, "sort values")) != UVC_OK ||
         (r = tmp.alloc(&v2, (size_t)n, "sort values")) != UVC_OK ||
@@ -456,15 +537,20 @@ static uvc_status build_impl(const float* verts_in, int64_t nv, const int32_t* t
         if (e_ == hipSuccess) e_ = hipGetLastError();                                                 \
         if (e_ != hipSuccess) return cleanup_fail(fail(UVC_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_))); \
     } while (0)
-    STEP(hipMemcpyAsync(dv, hv.data(), hv.size() * 4, hipMemcpyHostToDevice, st));
-    STEP(hipMemcpyAsync(dt, ht.data(), ht.size() * 4, hipMemcpyHostToDevice, st));
+    if (on_dev) {  // validated copies of the caller's device arrays are already on the device
+        dv = const_cast<float*>(verts_in);
+        dt = const_cast<int32_t*>(tris_in);
+    } else {
+        STEP(hipMemcpyAsync(dv, hv.data(), hv.size() * 4, hipMemcpyHostToDevice, st));
+        STEP(hipMemcpyAsync(dt, ht.data(), ht.size() * 4, hipMemcpyHostToDevice, st));
+    }
     const int TB = 256;
     hipLaunchKernelGGL(k_elements, dim3(grid_for(n, TB)), dim3(TB), 0, st, dv, dt, n, s->elem_c, s->elem_n, s->elem_a);
     STEP(hipGetLastError());
     float sc[3];
-    for (int a = 0; a < 3; ++a) sc[a] = (hi[a] > lo[a]) ? 1024.f / (hi[a] - lo[a]) : 0.f;
-    hipLaunchKernelGGL(k_morton, dim3(grid_for(n, TB)), dim3(TB), 0, st, s->elem_c, n, lo[0], lo[1], lo[2], sc[0],
-                       sc[1], sc[2], s->codes, v1);
+    for (int a = 0; a < 3; ++a) sc[a] = (hi[a] > lo[a]) ? 512.f / (hi[a] - lo[a]) : 0.f;
+    hipLaunchKernelGGL(k_morton, dim3(grid_for(n, TB)), dim3(TB), 0, st, s->elem_c, s->elem_n, n, lo[0], lo[1],
+                       lo[2], sc[0], sc[1], sc[2], s->codes, v1);
     STEP(hipGetLastError());
     uint32_t* ka = s->codes;
     uint32_t* kb = k2;
@@ -543,14 +629,28 @@ static uvc_status build_impl(const float* verts_in, int64_t nv, const int32_t* t
         hipLaunchKernelGGL(k_depth, dim3(grid_for(n, TB)), dim3(TB), 0, st, lpar, ipar, n, ddepth);
         STEP(hipGetLastError());
         STEP(hipMemcpyAsync(&depth, ddepth, 4, hipMemcpyDeviceToHost, st));
+        STEP(hipStreamSynchronize(st));
+        if (depth > 64)
+            return cleanup_fail(fail(UVC_EUNSUPPORTED, "hierarchy depth " + std::to_string(depth) + " exceeds 64"));
     }
+    if ((r = dalloc_n(&s->near_off, (size_t)n + 1, "near-list offsets")) != UVC_OK) return cleanup_fail(r);
+    hipLaunchKernelGGL(k_near<false>, dim3(grid_for(n, TB)), dim3(TB), 0, st, s->nodes, s->tri, s->elem, n, s->pad,
+                       s->near_off, (int32_t*)nullptr);
+    STEP(hipGetLastError());
+    hipLaunchKernelGGL(k_scan_i32, dim3(1), dim3(1024), 0, st, s->near_off, n);
+    STEP(hipGetLastError());
+    int32_t n_near = 0;
+    STEP(hipMemcpyAsync(&n_near, s->near_off + n, 4, hipMemcpyDeviceToHost, st));
+    STEP(hipStreamSynchronize(st));
+    if (n_near < 0) return cleanup_fail(fail(UVC_EUNSUPPORTED, "near lists exceed 2^31 entries"));
+    s->n_near = n_near;
+    if ((r = dalloc_n(&s->near, (size_t)std::max<int32_t>(n_near, 1), "near lists")) != UVC_OK) return cleanup_fail(r);
+    hipLaunchKernelGGL(k_near<true>, dim3(grid_for(n, TB)), dim3(TB), 0, st, s->nodes, s->tri, s->elem, n, s->pad,
+                       s->near_off, s->near);
+    STEP(hipGetLastError());
     STEP(hipStreamSynchronize(st));
 #undef STEP
     s->depth = depth;
-    if (depth > 64) {
-        free_scene(s);
-        return fail(UVC_EUNSUPPORTED, "hierarchy depth " + std::to_string(depth) + " exceeds 64");
-    }
     *out = s;
     return UVC_OK;
 }

@@ -37,12 +37,23 @@ uvc_status dalloc_n(T** p, size_t n, const char* what) {
 }
 
 // --------------------------------------------------------- layout constants
-// Triangle record, 48 bytes, in leaf-slot order: v0.xyz v1.xyz v2.xyz in the
-// input vertex order, the input triangle index (int bits), two spare words.
-constexpr int TRI_WORDS = 12;
+// Triangle record, 80 bytes, in leaf-slot order: v0.xyz v1.xyz v2.xyz in the
+// input vertex order, the FP32 edge vectors e01 = v1-v0, e12 = v2-v1,
+// e20 = v0-v2, L = the largest |component| of the three edges, and the input
+// triangle index (int bits).
+constexpr int TRI_WORDS = 20;
+constexpr int TRI_E01 = 9, TRI_E12 = 12, TRI_E20 = 15, TRI_L = 18, TRI_ID = 19;
 // Element record, 32 bytes, in leaf-slot order: centroid xyz, unit normal
-// xyz, input triangle index (int bits), area.
+// xyz, input triangle index (int bits), near-list cut radius rho_t.
 constexpr int ELEM_WORDS = 8;
+// Near lists: element slot s owns near[near_off[s] .. near_off[s+1]), the
+// slots of every triangle other than s whose padded box meets the ball of
+// radius rho_n = NEAR_SCALE * L_s around the centroid (L_s = the element's
+// largest |edge component|), except triangles whose FP64 plane side at the
+// centroid is exactly zero (the predicate can never report those).  The
+// traversal may then stop each segment rho_t = rho_n (1 - 2^-10) short of its
+// target: every point it skips lies inside the ball.
+constexpr float NEAR_SCALE = 1.0f;
 // Hierarchy node, 64 bytes: left box lo xyz hi xyz, right box lo xyz hi xyz,
 // left ref, right ref (>= 0 internal, < 0 leaf slot ~ref), hint axis/order,
 // hint split coordinate.
@@ -50,12 +61,13 @@ constexpr int NODE_WORDS = 16;
 
 // Decision bands of the FP32 fast path (multiplied by opts.band_scale).
 // Front-facing: |<d, n>| > TAU_F * |d|_1.
-// Edge orientations U, V, W: |U| > TAU_E * G^2 * |D|_1 with G the largest
-//   |coordinate| of v0-O, v1-O, v2-O.
+// Edge orientations U, V, W (computed as D . ((vi - O) x (vj - vi))):
+//   |U| > TAU_E * |D|_1 * G * (L + 2^-28 G) with G the largest |coordinate| of
+//   v0-O, v1-O, v2-O and L that of the three edge vectors.
 // Plane sides: |s| > TAU_P * |x|_inf * |e1|_inf * |e2|_inf with x = O-v0 or
 //   T-v0 and e1, e2 the triangle's edge vectors from v0.
 constexpr float TAU_F = 1.0f / 524288.0f;   // 2^-19
-constexpr float TAU_E = 1.0f / 8192.0f;     // 2^-13
+constexpr float TAU_E = 1.0f / 65536.0f;    // 2^-16
 constexpr float TAU_P = 1.0f / 8192.0f;     // 2^-13
 
 // Box padding relative to the scene's largest |coordinate|.
@@ -78,4 +90,7 @@ struct uvc_scene {
     int32_t* perm = nullptr;    // slot -> input index
     uint32_t* codes = nullptr;  // sorted Morton codes
     float* nodes = nullptr;     // (n-1) x NODE_WORDS
+    int32_t* near_off = nullptr;  // n + 1
+    int32_t* near = nullptr;      // near_off[n] slots
+    int64_t n_near = 0;
 };

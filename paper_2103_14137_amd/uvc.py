@@ -22,7 +22,8 @@ _I64 = ctypes.c_int64
 _I32 = ctypes.c_int32
 
 PATHS = {"auto": 0, "lbvh": 1, "brute": 2}
-STAT_NAMES = ["rays", "nodes", "tris", "recheck", "front64", "visible"]
+STAT_NAMES = ["rays", "nodes", "tris", "recheck", "front64", "visible", "steps", "near"]
+FLAG_NO_NEAR = 1
 STAT_N = 8
 
 
@@ -37,8 +38,9 @@ class LampC(ctypes.Structure):
 
 
 class OptsC(ctypes.Structure):
-    _fields_ = [("path", _I32), ("reserved0", _I32), ("band_scale", ctypes.c_float), ("tile_tris", _I32),
-                ("stats_dev", _P)]
+    _fields_ = [("path", _I32), ("packet_poses", _I32), ("band_scale", ctypes.c_float), ("tile_tris", _I32),
+                ("flags", _I32), ("reserved1", _I32), ("stats_dev", _P),
+                ("kernel_ms", ctypes.POINTER(ctypes.c_float))]
 
 
 _lib = None
@@ -116,27 +118,40 @@ def as_lamp(lamp) -> Lamp:
     return Lamp(lamp.dz, lamp.power)
 
 
-def make_opts(path="auto", band_scale: float = 1.0, tile_tris: int = 0, stats: torch.Tensor | None = None) -> OptsC:
+def make_opts(path="auto", band_scale: float = 1.0, tile_tris: int = 0, stats: torch.Tensor | None = None,
+              timing: ctypes.c_float | None = None, packet_poses: int = 0, flags: int = 0) -> OptsC:
     if stats is not None:
         stats = _require_cuda(stats, "stats", torch.int64)
         if stats.numel() < STAT_N:
             raise ValueError(f"stats needs {STAT_N} counters")
-    return OptsC(PATHS[path] if isinstance(path, str) else int(path), 0, float(band_scale), int(tile_tris),
-                 stats.data_ptr() if stats is not None else None)
+    return OptsC(PATHS[path] if isinstance(path, str) else int(path), int(packet_poses), float(band_scale),
+                 int(tile_tris), int(flags), 0,
+                 stats.data_ptr() if stats is not None else None,
+                 ctypes.pointer(timing) if timing is not None else None)
 
 
 class Scene:
     """A mesh with its surface elements and hierarchy, resident on the GPU."""
 
     def __init__(self, verts, tris, stream=None):
-        v = np.ascontiguousarray(verts, np.float32)
-        t = np.ascontiguousarray(tris, np.int32)
-        if v.ndim != 2 or v.shape[1] != 3 or t.ndim != 2 or t.shape[1] != 3:
-            raise ValueError("verts must be [V,3] and tris [N,3]")
-        h = _P()
+        """verts [V,3] float32 and tris [N,3] int32, as NumPy arrays (host) or
+        as CUDA tensors (device-resident inputs)."""
         self._h = None
-        check(lib().uvc_build_scene(v.ctypes.data_as(_P), v.shape[0], t.ctypes.data_as(_P), t.shape[0], 0,
-                                    _stream(stream), ctypes.byref(h)))
+        h = _P()
+        if isinstance(verts, torch.Tensor):
+            v = _require_cuda(verts, "verts", torch.float32)
+            t = _require_cuda(tris, "tris", torch.int32)
+            if v.ndim != 2 or v.shape[1] != 3 or t.ndim != 2 or t.shape[1] != 3:
+                raise ValueError("verts must be [V,3] and tris [N,3]")
+            check(lib().uvc_build_scene(v.data_ptr(), v.shape[0], t.data_ptr(), t.shape[0], 1, _stream(stream),
+                                        ctypes.byref(h)))
+        else:
+            v = np.ascontiguousarray(verts, np.float32)
+            t = np.ascontiguousarray(tris, np.int32)
+            if v.ndim != 2 or v.shape[1] != 3 or t.ndim != 2 or t.shape[1] != 3:
+                raise ValueError("verts must be [V,3] and tris [N,3]")
+            check(lib().uvc_build_scene(v.ctypes.data_as(_P), v.shape[0], t.ctypes.data_as(_P), t.shape[0], 0,
+                                        _stream(stream), ctypes.byref(h)))
         self._h = h
         self.n = int(t.shape[0])
 
@@ -180,8 +195,11 @@ class Scene:
 
 def irradiance_dense(scene: Scene, poses: torch.Tensor, lamp, path="auto", band_scale: float = 1.0,
                      want_vis: bool = False, stats: torch.Tensor | None = None, out: torch.Tensor | None = None,
-                     tile_tris: int = 0, stream=None):
-    """Dense K x N irradiance matrix (and optional visibility bits)."""
+                     tile_tris: int = 0, stream=None, timing: ctypes.c_float | None = None,
+                     packet_poses: int = 0, flags: int = 0):
+    """Dense K x N irradiance matrix (and optional visibility bits).  With a
+    ctypes.c_float passed as timing, the call synchronises and stores the
+    irradiance kernel's duration in milliseconds (HIP events)."""
     poses = _require_cuda(poses, "poses", torch.float32)
     K, pd = poses.shape
     lamp = as_lamp(lamp)
@@ -193,7 +211,7 @@ def irradiance_dense(scene: Scene, poses: torch.Tensor, lamp, path="auto", band_
         if out.numel() != K * N:
             raise ValueError("out must hold K*N floats")
     vis = torch.empty((K, N), dtype=torch.int32, device=poses.device) if want_vis else None
-    opts = make_opts(path, band_scale, tile_tris, stats)
+    opts = make_opts(path, band_scale, tile_tris, stats, timing, packet_poses, flags)
     check(lib().uvc_compute_irradiance_dense(scene.handle, poses.data_ptr(), K, pd, ctypes.byref(lamp._c),
                                              ctypes.byref(opts), out.data_ptr(),
                                              vis.data_ptr() if vis is not None else None, _stream(stream)))
@@ -201,12 +219,13 @@ def irradiance_dense(scene: Scene, poses: torch.Tensor, lamp, path="auto", band_
 
 
 def irradiance_csr(scene: Scene, poses: torch.Tensor, lamp, path="auto", band_scale: float = 1.0,
-                   stats: torch.Tensor | None = None, tile_tris: int = 0, stream=None):
+                   stats: torch.Tensor | None = None, tile_tris: int = 0, stream=None, packet_poses: int = 0,
+                   flags: int = 0):
     """CSR irradiance matrix: (row_ptr int64 [K+1], col int32 [nnz], val float32 [nnz])."""
     poses = _require_cuda(poses, "poses", torch.float32)
     K, pd = poses.shape
     lamp = as_lamp(lamp)
-    opts = make_opts(path, band_scale, tile_tris, stats)
+    opts = make_opts(path, band_scale, tile_tris, stats, None, packet_poses, flags)
     job = _P()
     nnz = _I64()
     s = _stream(stream)

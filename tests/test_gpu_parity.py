@@ -87,6 +87,12 @@ def test_paths_bit_identical_and_band_independent(uvc):
     assert torch.equal(v1, v2) and torch.equal(E1, E2)
     assert torch.equal(v1[:4], v3) and torch.equal(E1[:4], E3)
     assert torch.equal(v1, v4) and torch.equal(E1, E4)  # deterministic
+    for tp in (1, 4, 16, 64):  # packet shapes: same bits, same values
+        E5, v5 = uvc.irradiance_dense(sc, poses, w.lamp, path="lbvh", want_vis=True, packet_poses=tp)
+        assert torch.equal(v1, v5) and torch.equal(E1, E5), tp
+    # walking every segment to its target instead of using the near lists
+    E6, v6 = uvc.irradiance_dense(sc, poses, w.lamp, path="lbvh", want_vis=True, flags=uvc.FLAG_NO_NEAR)
+    assert torch.equal(v1, v6) and torch.equal(E1, E6)
     sc.close()
 
 

@@ -101,6 +101,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the brute-force path comparison")
+    ap.add_argument("--mode", choices=["bench", "kernel", "copy"], default="bench",
+                    help="kernel: only two launches of the irradiance kernel (for counter runs); "
+                         "copy: a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -115,6 +118,16 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.mode == "copy":
+        nbytes = 1 << 30
+        x = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
+                          "copies": 3}), flush=True)
+        return
     w = workloads.ward()
     K, N, S = w.K, w.N, w.lamp.n_src
     verts = torch.from_numpy(w.mesh.verts).to(dev)
@@ -123,6 +136,15 @@ def main():
     lamp = uvc.Lamp(w.lamp.dz, w.lamp.power)
     E = torch.empty((K, N), dtype=torch.float32, device=dev)
     log(f"ward: K={K} N={N} S={S}")
+    if args.mode == "kernel":
+        sc = uvc.Scene(verts, tris)
+        for _ in range(2):
+            uvc.irradiance_dense(sc, poses, lamp, path="lbvh", out=E)
+        torch.cuda.synchronize()
+        sc.close()
+        print(json.dumps({"mode": "kernel", "launches": 2, "K": K, "N": N, "S": S,
+                          "source_hash": source_hash()}), flush=True)
+        return
 
     def step():
         sc = uvc.Scene(verts, tris)
@@ -163,6 +185,10 @@ def main():
             t = ctypes.c_float(0.0)
             uvc.irradiance_dense(sc, poses, lamp, path="lbvh", out=E, timing=t, packet_poses=tp)
             paths[f"lbvh_tp{tp}"] = {"kernel_ms": t.value, "rays_per_s": rays / (t.value * 1e-3)}
+        for wv in (5, 6, 8):
+            t = ctypes.c_float(0.0)
+            uvc.irradiance_dense(sc, poses, lamp, path="lbvh", out=E, timing=t, waves=wv)
+            paths[f"lbvh_waves{wv}"] = {"kernel_ms": t.value, "rays_per_s": rays / (t.value * 1e-3)}
         t = ctypes.c_float(0.0)
         uvc.irradiance_dense(sc, poses, lamp, path="lbvh", out=E, timing=t, flags=uvc.FLAG_NO_NEAR)
         paths["lbvh_no_near"] = {"kernel_ms": t.value, "rays_per_s": rays / (t.value * 1e-3)}

@@ -140,7 +140,7 @@ typedef struct {
     int32_t path;        /* UVC_PATH_*; AUTO picks the brute-force path for
                             small meshes and the hierarchy otherwise          */
     int32_t packet_poses; /* hierarchy path: poses per wavefront packet, a
-                            power of two in [1, 64] (0 = 64); the 64 lanes
+                            power of two in [1, 64] (0 = 16); the 64 lanes
                             hold packet_poses poses x 64/packet_poses
                             elements                                          */
     float band_scale;    /* multiplies the FP32 decision bands: 1 = default;
@@ -149,7 +149,9 @@ typedef struct {
                             may then disagree with the exact predicate)       */
     int32_t tile_tris;   /* brute-force path: triangles per LDS tile (0 = default) */
     int32_t flags;       /* UVC_FLAG_* bits                                   */
-    int32_t reserved1;
+    int32_t waves;       /* hierarchy path: kernel variant compiled for this
+                            many waves per SIMD: 5 (no register cap), 6 or
+                            8 (0 = 8)                                         */
     uint64_t* stats_dev; /* NULL, or UVC_STAT_N device counters that an
                             instrumented (slower) kernel adds to              */
     float* kernel_ms;    /* NULL, or host float: HIP events are recorded on

@@ -54,6 +54,7 @@ struct IrrParams {
     int32_t tile_tris;         // brute-force LDS tile
     int32_t tk_log2;           // hierarchy path: log2 of the poses per packet (0..6)
     int32_t use_near;          // hierarchy path: stop segments short and test near lists
+    int32_t waves;             // hierarchy path: occupancy target of the kernel variant (0, 6, 8)
     float tau_f, tau_e, tau_p;
     float* E;                  // rows of this launch, K x N
     uint32_t* vis;             // NULL or K x N
@@ -234,6 +235,24 @@ __device__ __forceinline__ bool front_face(const IrrParams& P, const ElemLane& e
 }
 
 // ------------------------------------------------------------ hierarchy
+struct NodeRec {
+    float4 a, b, c, d;  // left box lo xyz hi x | hi yz, right lo xy | right lo z hi xyz | refs, hint
+};
+
+__device__ __forceinline__ NodeRec load_node(const float* __restrict__ nodes, int node) {
+    const float4* q = reinterpret_cast<const float4*>(nodes + (int64_t)node * NODE_WORDS);
+    NodeRec r;
+    r.a = q[0];
+    r.b = q[1];
+    r.c = q[2];
+    r.d = q[3];
+    return r;
+}
+
+// Packet traversal.  Control flow is uniform: m is the mask of lanes whose
+// segment entered the current node; both child boxes are tested for every
+// lane and the ballots are masked with m.  Deferred (node, mask) pairs live
+// in three VGPRs, entry i in lane i (depth <= 64).
 template <bool STATS>
 __device__ __forceinline__ unsigned long long traverse(const IrrParams& P, const Ray& r, unsigned long long live,
                                                        unsigned long long& n_nodes, unsigned long long& n_tris,
@@ -241,20 +260,18 @@ __device__ __forceinline__ unsigned long long traverse(const IrrParams& P, const
     const int lane = lane_id();
     unsigned long long occl = 0;
     if (P.N < 2) return 0;
-    int node = 0;
-    unsigned long long m = live;
-    int sp = 0;
-    int stk_node = 0, stk_lo = 0, stk_hi = 0;
     const float* __restrict__ nodes = P.nodes;
     const float* __restrict__ tri = P.tri;
+    unsigned long long m = live;
+    int node = 0;
+    int sp = 0;
+    int stk_node = 0, stk_lo = 0, stk_hi = 0;
     while (true) {
-        const float4* q = reinterpret_cast<const float4*>(nodes + (int64_t)node * NODE_WORDS);
-        const float4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
-        const bool in_m = (m >> lane) & 1ull;
-        const bool hL = in_m && slab(r, q0.x, q0.y, q0.z, q0.w, q1.x, q1.y);
-        const bool hR = in_m && slab(r, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w);
-        unsigned long long mL = __ballot(hL), mR = __ballot(hR);
-        const int cl = __float_as_int(q3.x), cr = __float_as_int(q3.y);
+        const NodeRec cur = load_node(nodes, node);
+        const int cl = __float_as_int(cur.d.x), cr = __float_as_int(cur.d.y);
+        const bool hL = slab(r, cur.a.x, cur.a.y, cur.a.z, cur.a.w, cur.b.x, cur.b.y);
+        const bool hR = slab(r, cur.b.z, cur.b.w, cur.c.x, cur.c.y, cur.c.z, cur.c.w);
+        unsigned long long mL = __ballot(hL) & m, mR = __ballot(hR) & m;
         if (STATS) {
             n_nodes += (unsigned long long)__popcll(m);
             ++n_steps;
@@ -282,20 +299,20 @@ __device__ __forceinline__ unsigned long long traverse(const IrrParams& P, const
         mL &= ~occl;
         mR &= ~occl;
         if (mL && mR) {
-            const int hint = __float_as_int(q3.z);
+            const int hint = __float_as_int(cur.d.z);
             const int axis = hint & 3;
             const float o_lane = axis == 0 ? r.ox : (axis == 1 ? r.oy : r.oz);
             const float o = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(o_lane)));
-            const bool left_first = ((o < q3.w) == ((hint & 4) != 0));
-            const int nnear = left_first ? cl : cr, nfar = left_first ? cr : cl;
-            const unsigned long long mnear = left_first ? mL : mR, mfar = left_first ? mR : mL;
+            const bool left_first = ((o < cur.d.w) == ((hint & 4) != 0));
+            const int nfar = left_first ? cr : cl;
+            const unsigned long long mfar = left_first ? mR : mL;
             const bool here = lane == sp;  // the stack entry sp lives in lane sp
             stk_node = here ? nfar : stk_node;
             stk_lo = here ? (int)(unsigned)mfar : stk_lo;
             stk_hi = here ? (int)(unsigned)(mfar >> 32) : stk_hi;
             ++sp;
-            node = nnear;
-            m = mnear;
+            node = left_first ? cl : cr;
+            m = left_first ? mL : mR;
         } else if (mL) {
             node = cl;
             m = mL;
@@ -330,7 +347,7 @@ __device__ __forceinline__ unsigned long long traverse(const IrrParams& P, const
 // their nearby origins.  Each lane sums its element's terms over the sources
 // in ascending order, exactly like the brute-force path.
 template <bool STATS>
-__global__ __launch_bounds__(256) void k_irr_lbvh(IrrParams P) {
+__device__ __forceinline__ void irr_lbvh_body(const IrrParams& P) {
     int64_t kg, quad;
     block_coords(P, kg, quad);
     const int lane = lane_id(), w = (int)(threadIdx.x >> 6);
@@ -408,6 +425,21 @@ __global__ __launch_bounds__(256) void k_irr_lbvh(IrrParams P) {
             atomicAdd(P.stats + UVC_STAT_NEAR, nn);
         }
     }
+}
+
+// Kernel variants differ only in the occupancy the register allocator aims
+// for (waves per SIMD); which one is fastest depends on the scene.
+template <bool STATS>
+__global__ __launch_bounds__(256) void k_irr_lbvh(IrrParams P) {
+    irr_lbvh_body<STATS>(P);
+}
+template <bool STATS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_irr_lbvh_w6(IrrParams P) {
+    irr_lbvh_body<STATS>(P);
+}
+template <bool STATS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_irr_lbvh_w8(IrrParams P) {
+    irr_lbvh_body<STATS>(P);
 }
 
 // ---------------------------------------------------------- brute force
@@ -611,11 +643,13 @@ static uvc_status make_params(const uvc_scene* s, const float* poses, int64_t K,
     P.near_off = s->near_off;
     P.near = s->near;
     P.use_near = (opts && (opts->flags & UVC_FLAG_NO_NEAR)) ? 0 : 1;
+    P.waves = (opts && opts->waves > 0) ? opts->waves : 8;
+    if (P.waves != 5 && P.waves != 6 && P.waves != 8) return fail(UVC_EINVAL, "waves must be 0, 5, 6 or 8");
     P.poses = poses;
     P.K = K;
     P.N = s->n;
     P.pose_dim = pd;
-    int tk = (opts && opts->packet_poses > 0) ? opts->packet_poses : 64;
+    int tk = (opts && opts->packet_poses > 0) ? opts->packet_poses : 16;
     if (tk != 1 && tk != 2 && tk != 4 && tk != 8 && tk != 16 && tk != 32 && tk != 64)
         return fail(UVC_EINVAL, "packet_poses must be a power of two in [1, 64]");
     P.tk_log2 = 0;
@@ -716,6 +750,10 @@ static uvc_status launch_irr_impl(const IrrParams& P0, int path, hipStream_t st)
     } else {
         if (stats)
             hipLaunchKernelGGL(k_irr_lbvh<true>, dim3((unsigned)blocks), dim3(256), 0, st, P);
+        else if (P.waves == 8)
+            hipLaunchKernelGGL(k_irr_lbvh_w8<false>, dim3((unsigned)blocks), dim3(256), 0, st, P);
+        else if (P.waves == 6)
+            hipLaunchKernelGGL(k_irr_lbvh_w6<false>, dim3((unsigned)blocks), dim3(256), 0, st, P);
         else
             hipLaunchKernelGGL(k_irr_lbvh<false>, dim3((unsigned)blocks), dim3(256), 0, st, P);
     }

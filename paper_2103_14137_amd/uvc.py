@@ -39,7 +39,7 @@ class LampC(ctypes.Structure):
 
 class OptsC(ctypes.Structure):
     _fields_ = [("path", _I32), ("packet_poses", _I32), ("band_scale", ctypes.c_float), ("tile_tris", _I32),
-                ("flags", _I32), ("reserved1", _I32), ("stats_dev", _P),
+                ("flags", _I32), ("waves", _I32), ("stats_dev", _P),
                 ("kernel_ms", ctypes.POINTER(ctypes.c_float))]
 
 
@@ -119,13 +119,14 @@ def as_lamp(lamp) -> Lamp:
 
 
 def make_opts(path="auto", band_scale: float = 1.0, tile_tris: int = 0, stats: torch.Tensor | None = None,
-              timing: ctypes.c_float | None = None, packet_poses: int = 0, flags: int = 0) -> OptsC:
+              timing: ctypes.c_float | None = None, packet_poses: int = 0, flags: int = 0,
+              waves: int = 0) -> OptsC:
     if stats is not None:
         stats = _require_cuda(stats, "stats", torch.int64)
         if stats.numel() < STAT_N:
             raise ValueError(f"stats needs {STAT_N} counters")
     return OptsC(PATHS[path] if isinstance(path, str) else int(path), int(packet_poses), float(band_scale),
-                 int(tile_tris), int(flags), 0,
+                 int(tile_tris), int(flags), int(waves),
                  stats.data_ptr() if stats is not None else None,
                  ctypes.pointer(timing) if timing is not None else None)
 
@@ -196,7 +197,7 @@ class Scene:
 def irradiance_dense(scene: Scene, poses: torch.Tensor, lamp, path="auto", band_scale: float = 1.0,
                      want_vis: bool = False, stats: torch.Tensor | None = None, out: torch.Tensor | None = None,
                      tile_tris: int = 0, stream=None, timing: ctypes.c_float | None = None,
-                     packet_poses: int = 0, flags: int = 0):
+                     packet_poses: int = 0, flags: int = 0, waves: int = 0):
     """Dense K x N irradiance matrix (and optional visibility bits).  With a
     ctypes.c_float passed as timing, the call synchronises and stores the
     irradiance kernel's duration in milliseconds (HIP events)."""
@@ -211,7 +212,7 @@ def irradiance_dense(scene: Scene, poses: torch.Tensor, lamp, path="auto", band_
         if out.numel() != K * N:
             raise ValueError("out must hold K*N floats")
     vis = torch.empty((K, N), dtype=torch.int32, device=poses.device) if want_vis else None
-    opts = make_opts(path, band_scale, tile_tris, stats, timing, packet_poses, flags)
+    opts = make_opts(path, band_scale, tile_tris, stats, timing, packet_poses, flags, waves)
     check(lib().uvc_compute_irradiance_dense(scene.handle, poses.data_ptr(), K, pd, ctypes.byref(lamp._c),
                                              ctypes.byref(opts), out.data_ptr(),
                                              vis.data_ptr() if vis is not None else None, _stream(stream)))

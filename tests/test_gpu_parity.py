@@ -90,6 +90,9 @@ def test_paths_bit_identical_and_band_independent(uvc):
     for tp in (1, 4, 16, 64):  # packet shapes: same bits, same values
         E5, v5 = uvc.irradiance_dense(sc, poses, w.lamp, path="lbvh", want_vis=True, packet_poses=tp)
         assert torch.equal(v1, v5) and torch.equal(E1, E5), tp
+    for wv in (5, 6, 8):  # occupancy variants of the same kernel
+        E7, v7 = uvc.irradiance_dense(sc, poses, w.lamp, path="lbvh", want_vis=True, waves=wv)
+        assert torch.equal(v1, v7) and torch.equal(E1, E7), wv
     # walking every segment to its target instead of using the near lists
     E6, v6 = uvc.irradiance_dense(sc, poses, w.lamp, path="lbvh", want_vis=True, flags=uvc.FLAG_NO_NEAR)
     assert torch.equal(v1, v6) and torch.equal(E1, E6)

@@ -207,6 +207,70 @@ uvc_status uvc_compute_irradiance_csr_finish(uvc_csr_job* job,
                                              void* hip_stream);
 void uvc_csr_job_destroy(uvc_csr_job* job);
 
+/* ------------------------------------------------------------------------
+ * Many rooms in one launch.
+ * ------------------------------------------------------------------------ */
+typedef struct uvc_batch uvc_batch;
+
+enum { UVC_BATCH_PERSISTENT = 0, UVC_BATCH_GRAPH = 1, UVC_BATCH_PER_ROOM = 2 };
+
+/* Prepare the dense irradiance matrices of n_rooms rooms (same lamp and
+ * options for all; hierarchy path) for repeated runs.  scenes[r], the device
+ * poses poses_dev[r] (K[r] x pose_dim) and the caller-owned device outputs
+ * E_dev[r] (K[r] x N_r FP32) must stay valid while the batch exists.  Poses
+ * are validated here (synchronises hip_stream).  The work queue lists the
+ * rooms by estimated cost per work item, longest first. */
+uvc_status uvc_batch_create(const uvc_scene* const* scenes, int32_t n_rooms,
+                            const float* const* poses_dev, const int64_t* K,
+                            int32_t pose_dim, const uvc_lamp* lamp,
+                            const uvc_opts* opts, float* const* E_dev,
+                            void* hip_stream, uvc_batch** out);
+
+/* Compute every room's E.  mode UVC_BATCH_PERSISTENT: one persistent launch
+ * whose workgroups drain the queue through an atomic counter;
+ * UVC_BATCH_GRAPH: the same work (a counter-reset kernel and the launch)
+ * captured once into a hipGraph on a library-owned stream and replayed on
+ * hip_stream; UVC_BATCH_PER_ROOM: one launch per
+ * room.  All modes write identical bits.  kernel_ms: NULL or host float that
+ * receives the HIP-event time of the launches (the call then synchronises).
+ * Runs on one batch must not overlap (they share the queue counter). */
+uvc_status uvc_batch_run(uvc_batch* batch, int32_t mode, float* kernel_ms,
+                         void* hip_stream);
+
+void uvc_batch_destroy(uvc_batch* batch);
+
+/* ------------------------------------------------------------------------
+ * Dosage LP (Sec. IV-D, relaxed LP), the consumer of E.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    double objective;        /* sum_k t_k + sum_i p_i sigma_i over visible elements */
+    double primal_residual;  /* relative KKT residuals of the returned point     */
+    double dual_residual;
+    double gap;
+    int32_t iterations;
+    int64_t n_visible;       /* elements with some E[k,i] > 0                     */
+    double penalty;          /* p_0 (the default penalty when penalty_dev = NULL) */
+} uvc_lp_info;
+
+/* Solve  min sum_k t_k + sum_i p_i sigma_i
+ *        s.t. sum_k E[k,i] t_k + sigma_i >= mu_min (every visible element),
+ *             sum_k t_k <= t_max, t >= 0, sigma >= 0
+ * for the dense pose-major E_dev (K x N FP32, device).  Elements with
+ * E[k,i] = 0 for every k are dropped (sigma_i = mu_min, excluded from the
+ * objective).  penalty_dev: N FP64 device values or NULL for
+ * p_i = 1.001 * ||E||_F (the paper asks for p_i > ||I||_F).  Mehrotra
+ * predictor-corrector interior point method; its K x K normal matrix is
+ * formed and Cholesky-factored on the GPU in FP64 (8 K^2 bytes of scratch).
+ * Stops when the relative primal residual, dual residual and duality gap are
+ * all <= tol.  Outputs t_out_dev (K FP64) and sigma_out_dev (N FP64), device;
+ * either may be NULL.  Returns UVC_ENOTCONV with the last point when
+ * max_iter is reached.  Synchronises hip_stream. */
+uvc_status uvc_solve_dosage_lp(const float* E_dev, int64_t K, int64_t N,
+                               const double* penalty_dev, double mu_min,
+                               double t_max, double tol, int32_t max_iter,
+                               double* t_out_dev, double* sigma_out_dev,
+                               uvc_lp_info* info, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

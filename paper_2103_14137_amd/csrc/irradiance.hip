@@ -347,9 +347,7 @@ __device__ __forceinline__ unsigned long long traverse(const IrrParams& P, const
 // their nearby origins.  Each lane sums its element's terms over the sources
 // in ascending order, exactly like the brute-force path.
 template <bool STATS>
-__device__ __forceinline__ void irr_lbvh_body(const IrrParams& P) {
-    int64_t kg, quad;
-    block_coords(P, kg, quad);
+__device__ __forceinline__ void irr_lbvh_packet(const IrrParams& P, int64_t kg, int64_t quad) {
     const int lane = lane_id(), w = (int)(threadIdx.x >> 6);
     const int tkl = P.tk_log2, tel = 6 - tkl;
     const int kk = lane >> tel, ee = lane & ((1 << tel) - 1);
@@ -427,6 +425,13 @@ __device__ __forceinline__ void irr_lbvh_body(const IrrParams& P) {
     }
 }
 
+template <bool STATS>
+__device__ __forceinline__ void irr_lbvh_body(const IrrParams& P) {
+    int64_t kg, quad;
+    block_coords(P, kg, quad);
+    irr_lbvh_packet<STATS>(P, kg, quad);
+}
+
 // Kernel variants differ only in the occupancy the register allocator aims
 // for (waves per SIMD); which one is fastest depends on the scene.
 template <bool STATS>
@@ -440,6 +445,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
 template <bool STATS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_irr_lbvh_w8(IrrParams P) {
     irr_lbvh_body<STATS>(P);
+}
+
+// ------------------------------------------------------------- batched
+// Many rooms in one persistent launch.  The work queue lists the rooms in
+// descending estimated cost per work item (longest first); item_off[q] is the
+// first item of queue entry q and room_of[q] its room.  Each workgroup takes
+// the next item from an atomic counter until the queue is drained, so every
+// wave reaches the exit.  An item is one workgroup's worth of work of the
+// single-room kernel (4 packets), run by the same code.
+struct BatchArgs {
+    const IrrParams* rooms;
+    const int64_t* item_off;  // n_queue + 1
+    const int32_t* room_of;   // n_queue
+    int32_t n_queue;
+    int64_t total;
+    unsigned long long* counter;
+};
+
+__global__ void k_fill_u64(unsigned long long* p, unsigned long long v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_irr_batched(BatchArgs B) {
+    __shared__ long long item_s;
+    while (true) {
+        if (threadIdx.x == 0) item_s = (long long)atomicAdd(B.counter, 1ull);
+        __syncthreads();
+        const int64_t item = item_s;
+        __syncthreads();
+        if (item >= B.total) break;
+        int lo = 0, hi = B.n_queue - 1;  // last q with item_off[q] <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (B.item_off[mid] <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const IrrParams& P = B.rooms[B.room_of[lo]];
+        const int64_t local = item - B.item_off[lo];
+        irr_lbvh_packet<false>(P, local % P.kgroups, local / P.kgroups);
+    }
 }
 
 // ---------------------------------------------------------- brute force
@@ -981,4 +1026,184 @@ extern "C" void uvc_csr_job_destroy(uvc_csr_job* J) {
     if (!J) return;
     (void)hipDeviceSynchronize();
     free_job(J);
+}
+
+// ------------------------------------------------------------- batched host
+struct uvc_batch {
+    int device = 0;
+    int32_t n_rooms = 0;
+    std::vector<IrrParams> rooms;     // host copies (per-room launches)
+    IrrParams* d_rooms = nullptr;
+    int64_t* d_item_off = nullptr;
+    int32_t* d_room_of = nullptr;
+    int32_t* d_orders = nullptr;      // all rooms' pose orders, concatenated
+    unsigned long long* d_counter = nullptr;
+    int32_t n_queue = 0;
+    int64_t total = 0;
+    int grid = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t capture_stream = nullptr;  // library-owned: the legacy stream cannot be captured
+};
+
+static void free_batch(uvc_batch* b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    void* ptrs[] = {b->d_rooms, b->d_item_off, b->d_room_of, b->d_orders, b->d_counter};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    delete b;
+}
+
+extern "C" uvc_status uvc_batch_create(const uvc_scene* const* scenes, int32_t n_rooms, const float* const* poses_dev,
+                                       const int64_t* K, int32_t pose_dim, const uvc_lamp* lamp, const uvc_opts* opts,
+                                       float* const* E_dev, void* hip_stream, uvc_batch** out) {
+    if (!out) return fail(UVC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_rooms < 0 || (n_rooms > 0 && (!scenes || !poses_dev || !K || !E_dev)))
+        return fail(UVC_EINVAL, "invalid batch arrays");
+    hipStream_t st = (hipStream_t)hip_stream;
+    uvc_batch* b = new uvc_batch();
+    (void)hipGetDevice(&b->device);
+    b->n_rooms = n_rooms;
+    std::vector<std::vector<int32_t>> orders((size_t)n_rooms);
+    int64_t order_total = 0;
+    for (int32_t r = 0; r < n_rooms; ++r) {
+        IrrParams P;
+        uvc_status st_ = make_params(scenes[r], poses_dev[r], K[r], pose_dim, lamp, opts, P);
+        if (st_ == UVC_OK && K[r] > 0 && scenes[r]->n > 0 && !E_dev[r]) st_ = fail(UVC_EINVAL, "E is NULL");
+        std::vector<float> hp;
+        if (st_ == UVC_OK) st_ = fetch_poses(scenes[r], poses_dev[r], K[r], pose_dim, P.lamp, st, hp);
+        if (st_ != UVC_OK) {
+            free_batch(b);
+            return fail(st_, "room " + std::to_string(r) + ": " + uvc_last_error());
+        }
+        pose_order(hp, pose_dim, 0, K[r], orders[(size_t)r]);
+        P.E = E_dev[r];
+        P.vis = nullptr;
+        P.stats = nullptr;
+        const int64_t per = (int64_t)1 << (6 - P.tk_log2);
+        P.ntiles = (P.N + per - 1) / per;
+        P.nquads = (P.ntiles + 3) / 4;
+        P.kgroups = (P.K + (1 << P.tk_log2) - 1) >> P.tk_log2;
+        b->rooms.push_back(P);
+        order_total += K[r];
+    }
+    uvc_status r = UVC_OK;
+    if ((r = dalloc_n(&b->d_orders, (size_t)std::max<int64_t>(order_total, 1), "batch pose orders")) != UVC_OK ||
+        (r = dalloc_n(&b->d_rooms, (size_t)std::max<int32_t>(n_rooms, 1), "batch room table")) != UVC_OK ||
+        (r = dalloc_n(&b->d_item_off, (size_t)n_rooms + 1, "batch queue")) != UVC_OK ||
+        (r = dalloc_n(&b->d_room_of, (size_t)std::max<int32_t>(n_rooms, 1), "batch queue")) != UVC_OK ||
+        (r = dalloc_n(&b->d_counter, 1, "batch counter")) != UVC_OK) {
+        free_batch(b);
+        return r;
+    }
+    // pose orders into one arena
+    std::vector<int32_t> all((size_t)std::max<int64_t>(order_total, 1));
+    int64_t at = 0;
+    for (int32_t q = 0; q < n_rooms; ++q) {
+        std::copy(orders[(size_t)q].begin(), orders[(size_t)q].end(), all.begin() + at);
+        b->rooms[(size_t)q].pose_order = b->d_orders + at;
+        at += K[q];
+    }
+    // queue: rooms with work, by estimated cost per item (depth ~ log2 N) descending
+    std::vector<int32_t> qorder;
+    for (int32_t q = 0; q < n_rooms; ++q)
+        if (b->rooms[(size_t)q].K > 0 && b->rooms[(size_t)q].N > 0) qorder.push_back(q);
+    std::stable_sort(qorder.begin(), qorder.end(), [&](int32_t a, int32_t c) {
+        return b->rooms[(size_t)a].N > b->rooms[(size_t)c].N;
+    });
+    std::vector<int64_t> off(qorder.size() + 1, 0);
+    for (size_t q = 0; q < qorder.size(); ++q) {
+        const IrrParams& P = b->rooms[(size_t)qorder[q]];
+        off[q + 1] = off[q] + P.nquads * P.kgroups;
+    }
+    b->n_queue = (int32_t)qorder.size();
+    b->total = off.back();
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+    b->grid = std::max(1, cus * 8);  // 8 workgroups of 4 waves per CU: 8 waves per SIMD
+    hipError_t e = hipMemcpyAsync(b->d_orders, all.data(), all.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && n_rooms > 0)
+        e = hipMemcpyAsync(b->d_rooms, b->rooms.data(), b->rooms.size() * sizeof(IrrParams), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_item_off, off.data(), off.size() * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !qorder.empty())
+        e = hipMemcpyAsync(b->d_room_of, qorder.data(), qorder.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        free_batch(b);
+        return fail(UVC_EDEVICE, std::string("batch upload: ") + hipGetErrorString(e));
+    }
+    *out = b;
+    return UVC_OK;
+}
+
+static uvc_status batch_enqueue(uvc_batch* b, hipStream_t st) {
+    BatchArgs A{b->d_rooms, b->d_item_off, b->d_room_of, b->n_queue, b->total, b->d_counter};
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(1), 0, st, b->d_counter, 0ull);
+    hipLaunchKernelGGL(k_irr_batched, dim3((unsigned)b->grid), dim3(256), 0, st, A);
+    UVC_HIP(hipGetLastError());
+    return UVC_OK;
+}
+
+extern "C" uvc_status uvc_batch_run(uvc_batch* b, int32_t mode, float* kernel_ms, void* hip_stream) {
+    if (!b) return fail(UVC_EINVAL, "batch is NULL");
+    if (mode < 0 || mode > 2) return fail(UVC_EINVAL, "mode must be 0, 1 or 2");
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (b->total == 0) return UVC_OK;
+    if (mode == UVC_BATCH_GRAPH && !b->exec) {
+        // capture once on a library stream; the executable graph is then
+        // launched on whatever stream the caller passes
+        if (!b->capture_stream) UVC_HIP(hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking));
+        hipStream_t cs = b->capture_stream;
+        UVC_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        const uvc_status r = batch_enqueue(b, cs);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(cs, &g);
+        if (r != UVC_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return r;
+        }
+        if (e != hipSuccess) return fail(UVC_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        b->graph = g;
+        UVC_HIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (kernel_ms) {
+        UVC_HIP(hipEventCreate(&e0));
+        UVC_HIP(hipEventCreate(&e1));
+        UVC_HIP(hipEventRecord(e0, st));
+    }
+    uvc_status r = UVC_OK;
+    if (mode == UVC_BATCH_GRAPH) {
+        const hipError_t e = hipGraphLaunch(b->exec, st);
+        if (e != hipSuccess) r = fail(UVC_EDEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+    } else if (mode == UVC_BATCH_PERSISTENT) {
+        r = batch_enqueue(b, st);
+    } else {
+        for (const IrrParams& P : b->rooms) {
+            if (P.K == 0 || P.N == 0) continue;
+            if ((r = launch_irr_impl(P, UVC_PATH_LBVH, st)) != UVC_OK) break;
+        }
+    }
+    if (kernel_ms) {
+        float ms = 0.f;
+        hipError_t e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (r == UVC_OK && e != hipSuccess) r = fail(UVC_EDEVICE, std::string("batch timing: ") + hipGetErrorString(e));
+        *kernel_ms = ms;
+    }
+    return r;
+}
+
+extern "C" void uvc_batch_destroy(uvc_batch* b) {
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    free_batch(b);
 }

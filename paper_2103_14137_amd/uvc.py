@@ -37,6 +37,12 @@ class LampC(ctypes.Structure):
     _fields_ = [("n_src", _I32), ("dz", _P), ("power_w", _P)]
 
 
+class LpInfoC(ctypes.Structure):
+    _fields_ = [("objective", ctypes.c_double), ("primal_residual", ctypes.c_double),
+                ("dual_residual", ctypes.c_double), ("gap", ctypes.c_double), ("iterations", _I32),
+                ("n_visible", _I64), ("penalty", ctypes.c_double)]
+
+
 class OptsC(ctypes.Structure):
     _fields_ = [("path", _I32), ("packet_poses", _I32), ("band_scale", ctypes.c_float), ("tile_tris", _I32),
                 ("flags", _I32), ("waves", _I32), ("stats_dev", _P),
@@ -69,6 +75,13 @@ def lib():
                                               ctypes.POINTER(_P), ctypes.POINTER(_I64)], _I32),
         "uvc_compute_irradiance_csr_finish": ([_P, _P, _P, _P, _P], _I32),
         "uvc_csr_job_destroy": ([_P], None),
+        "uvc_batch_create": ([ctypes.POINTER(_P), _I32, ctypes.POINTER(_P), ctypes.POINTER(_I64), _I32,
+                              ctypes.POINTER(LampC), ctypes.POINTER(OptsC), ctypes.POINTER(_P), _P, ctypes.POINTER(_P)],
+                             _I32),
+        "uvc_batch_run": ([_P, _I32, ctypes.POINTER(ctypes.c_float), _P], _I32),
+        "uvc_batch_destroy": ([_P], None),
+        "uvc_solve_dosage_lp": ([_P, _I64, _I64, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _I32, _P, _P,
+                                 ctypes.POINTER(LpInfoC), _P], _I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -246,3 +259,73 @@ def new_stats(device="cuda") -> torch.Tensor:
 def stats_dict(stats: torch.Tensor) -> dict:
     v = stats.cpu().numpy().astype(np.uint64)
     return {k: int(v[i]) for i, k in enumerate(STAT_NAMES)}
+
+
+def solve_lp(E: torch.Tensor, mu_min: float = 280.0, t_max: float = 3.6e5, penalty: torch.Tensor | None = None,
+             tol: float = 1e-9, max_iter: int = 200, stream=None, allow_notconv: bool = False):
+    """Relaxed dosage LP on the dense pose-major E (K x N float32, device).
+    Returns dict(t [K] float64, sigma [N] float64, objective, residuals...)."""
+    E = _require_cuda(E, "E", torch.float32)
+    K, N = E.shape
+    t = torch.empty(K, dtype=torch.float64, device=E.device)
+    sg = torch.empty(N, dtype=torch.float64, device=E.device)
+    if penalty is not None:
+        penalty = _require_cuda(penalty, "penalty", torch.float64)
+    info = LpInfoC()
+    st = lib().uvc_solve_dosage_lp(E.data_ptr(), K, N, penalty.data_ptr() if penalty is not None else None,
+                                   float(mu_min), float(t_max), float(tol), int(max_iter), t.data_ptr(),
+                                   sg.data_ptr(), ctypes.byref(info), _stream(stream))
+    if st != 0 and not (allow_notconv and st == -4):
+        check(st)
+    return {"t": t, "sigma": sg, "objective": info.objective, "primal_residual": info.primal_residual,
+            "dual_residual": info.dual_residual, "gap": info.gap, "iterations": info.iterations,
+            "n_visible": info.n_visible, "penalty": info.penalty, "converged": st == 0}
+
+
+BATCH_MODES = {"persistent": 0, "graph": 1, "per_room": 2}
+
+
+class Batch:
+    """Dense irradiance matrices of many rooms, computed by one persistent
+    launch (optionally replayed from a hipGraph).  Keeps references to the
+    scenes, poses and outputs it was created with."""
+
+    def __init__(self, scenes, poses_list, lamp, packet_poses: int = 0, waves: int = 0, stream=None):
+        self.scenes = list(scenes)
+        self.poses = [_require_cuda(p, "poses", torch.float32) for p in poses_list]
+        if len(self.poses) != len(self.scenes):
+            raise ValueError("one pose tensor per scene")
+        pd = self.poses[0].shape[1] if self.poses else 2
+        self.lamp = as_lamp(lamp)
+        self.E = [torch.empty((p.shape[0], sc.n), dtype=torch.float32, device=p.device)
+                  for p, sc in zip(self.poses, self.scenes)]
+        n = len(self.scenes)
+        SA = _P * max(n, 1)
+        KA = _I64 * max(n, 1)
+        self._sc = SA(*[sc.handle for sc in self.scenes])
+        self._ps = SA(*[p.data_ptr() for p in self.poses])
+        self._ks = KA(*[p.shape[0] for p in self.poses])
+        self._es = SA(*[e.data_ptr() for e in self.E])
+        self._opts = make_opts("lbvh", packet_poses=packet_poses, waves=waves)
+        h = _P()
+        self._h = None
+        check(lib().uvc_batch_create(self._sc, n, self._ps, self._ks, pd, ctypes.byref(self.lamp._c),
+                                     ctypes.byref(self._opts), self._es, _stream(stream), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, mode: str = "graph", timing: bool = False, stream=None):
+        t = ctypes.c_float(0.0)
+        check(lib().uvc_batch_run(self._h, BATCH_MODES[mode], ctypes.byref(t) if timing else None,
+                                  _stream(stream)))
+        return t.value if timing else None
+
+    def close(self):
+        if self._h is not None:
+            lib().uvc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

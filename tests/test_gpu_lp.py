@@ -1,0 +1,73 @@
+"""GPU dosage LP (interior point, FP64) against SciPy's HiGHS on the relaxed
+LP of Sec. IV-D.  The optimal objective is unique (t and sigma need not be),
+so the comparison is on the objective and on feasibility.  Bar: relative
+objective difference <= 1e-6 at tol 1e-9 on shared inputs; on each side's own
+matrix the entry tolerance (1e-5) dominates."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from oracle import lp, ref  # noqa: E402
+from paper_2103_14137_amd import workloads as wl  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def uvc():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2103_14137_amd import uvc as U
+    return U
+
+
+def _random_instance(seed, K, N):
+    """Seeded LP input with the structure of an irradiance matrix: nonnegative,
+    sparse visibility, a few never-visible elements."""
+    rng = np.random.default_rng(seed)
+    E = rng.lognormal(0.0, 1.0, size=(K, N)) * (rng.uniform(size=(K, N)) < 0.3)
+    E[:, rng.choice(N, max(1, N // 50), replace=False)] = 0.0
+    return E.astype(np.float32)
+
+
+def _feasible(E, t, sigma, mu, t_max, tol):
+    cov = E.astype(np.float64).T @ t + sigma
+    vis = E.max(0) > 0
+    return (np.all(cov[vis] >= mu * (1 - tol)) and t.sum() <= t_max * (1 + tol) and t.min() >= 0
+            and sigma.min() >= 0)
+
+
+@pytest.mark.parametrize("seed,K,N,t_max", [(0, 40, 300, 3.6e5), (1, 120, 700, 3.6e5), (2, 60, 400, 500.0)])
+def test_random_instances_match_highs(uvc, seed, K, N, t_max):
+    E = _random_instance(seed, K, N)
+    ref_sol = lp.solve(E.astype(np.float64), mu_min=280.0, t_max=t_max)
+    sol = uvc.solve_lp(torch.from_numpy(E).cuda(), mu_min=280.0, t_max=t_max, tol=1e-9)
+    assert sol["converged"]
+    assert lp.relative_objective_gap(sol["objective"], ref_sol["objective"]) <= 1e-6, (sol, ref_sol["objective"])
+    t, sg = sol["t"].cpu().numpy(), sol["sigma"].cpu().numpy()
+    assert _feasible(E, t, sg, 280.0, t_max, 1e-5)
+    assert sol["n_visible"] == int((E.max(0) > 0).sum())
+
+
+@pytest.mark.parametrize("t_max", [3.6e5, 1800.0])
+def test_box_room_lp(uvc, t_max):
+    """Each side on its own matrix: GPU E into the GPU solver, oracle E into
+    HiGHS; the objectives agree to the LP bar plus the entry tolerance."""
+    w = wl.box_room()
+    sc = uvc.Scene(w.mesh.verts, w.mesh.tris)
+    E, _ = uvc.irradiance_dense(sc, torch.from_numpy(w.poses).cuda(), w.lamp)
+    sol = uvc.solve_lp(E, mu_min=280.0, t_max=t_max, tol=1e-9)
+    E64, _ = ref.irradiance_dense(w.mesh.verts, w.mesh.tris, w.poses, w.lamp.dz, w.lamp.power)
+    ref_sol = lp.solve(E64, mu_min=280.0, t_max=t_max)
+    assert sol["converged"]
+    assert lp.relative_objective_gap(sol["objective"], ref_sol["objective"]) <= 5e-5
+    sc.close()
+
+
+def test_lp_input_errors(uvc):
+    E = torch.zeros((3, 4), dtype=torch.float32, device="cuda")
+    with pytest.raises(uvc.UvcError):
+        uvc.solve_lp(E, mu_min=-1.0)
+    sol = uvc.solve_lp(E)  # nothing visible: t = 0, sigma = mu
+    assert sol["n_visible"] == 0 and float(sol["t"].abs().sum()) == 0.0
+    assert torch.all(sol["sigma"] == 280.0)

@@ -185,6 +185,19 @@ uvc_status uvc_compute_irradiance_dense(const uvc_scene* scene,
                                         const uvc_opts* opts, float* E_dev,
                                         uint32_t* vis_dev, void* hip_stream);
 
+/* Irradiance of a subset of the elements: targets_dev holds n_targets input
+ * element indices (device int32); E_dev (K x n_targets FP32, device) gets
+ * column j = element targets_dev[j], bit-identical to that column of the
+ * dense matrix.  vis_dev: NULL or K x n_targets uint32.  Same options,
+ * validation and synchronisation as the dense call. */
+uvc_status uvc_compute_irradiance_targets(const uvc_scene* scene,
+                                          const float* poses_dev, int64_t K,
+                                          int32_t pose_dim, const uvc_lamp* lamp,
+                                          const uvc_opts* opts,
+                                          const int32_t* targets_dev,
+                                          int64_t n_targets, float* E_dev,
+                                          uint32_t* vis_dev, void* hip_stream);
+
 /* CSR irradiance matrix (rows = poses, ascending columns, only entries with
  * some V_kji = 1 stored), in two phases so that the caller owns the output.
  * begin computes everything, keeps the compacted entries in library memory,
@@ -206,6 +219,23 @@ uvc_status uvc_compute_irradiance_csr_finish(uvc_csr_job* job,
                                              int32_t* col_dev, float* val_dev,
                                              void* hip_stream);
 void uvc_csr_job_destroy(uvc_csr_job* job);
+
+/* ------------------------------------------------------------------------
+ * Autotuning of the launch options.
+ * ------------------------------------------------------------------------ */
+
+/* Pick the fastest launch options for this scene's size class: the first
+ * probe_poses poses (<= 0: 256) are computed with every hierarchy variant
+ * (packet_poses 1/4/16/64 x waves 5/6/8) and, for meshes of up to 200k
+ * triangles, every brute-force LDS tile (256..2048); each is timed with HIP
+ * events and scored in occlusion rays per second.  The winner is stored in
+ * the JSON table at table_path (NULL: no table) under the key
+ * "n<floor(log2 N)>_s<n_src>" and returned in *best.  When the table already
+ * holds the key and force == 0, no probe runs.  Synchronises hip_stream. */
+uvc_status uvc_autotune(const uvc_scene* scene, const float* poses_dev,
+                        int64_t K, int32_t pose_dim, const uvc_lamp* lamp,
+                        int32_t probe_poses, const char* table_path,
+                        int32_t force, uvc_opts* best, void* hip_stream);
 
 /* ------------------------------------------------------------------------
  * Many rooms in one launch.
@@ -270,6 +300,111 @@ uvc_status uvc_solve_dosage_lp(const float* E_dev, int64_t K, int64_t N,
                                double t_max, double tol, int32_t max_iter,
                                double* t_out_dev, double* sigma_out_dev,
                                uvc_lp_info* info, void* hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Learned pose ranker.  Not part of the paper: a pruning step in front of
+ * E assembly whose result is always judged by the paper's LP (Sec. IV-D)
+ * on the full candidate set when pruning could have cost coverage.
+ * ------------------------------------------------------------------------ */
+
+/* Number of FP32 parameters of the ranker MLP (64 -> 128 -> 128 -> 1, ReLU):
+ * W1[128][64], b1[128], W2[128][128], b2[128], W3[128], b3, in this order
+ * (24,961 floats). */
+int64_t uvc_ranker_param_count(void);
+
+/* Per-pose visibility features, feat_dev[k * 64 + b] (K x 64 FP32, device).
+ * From the point (x_k, y_k, z_k + src_height) (z_k = 0 for 2-D poses), 256
+ * rays in an equal-area direction set (16 azimuths x 16 bands uniform in the
+ * vertical direction cosine, cell centres) find their closest triangle; each
+ * hit adds the area its ray stands for, (4 pi / 256) r^2 / max(|cos|, 0.05)
+ * with r the hit distance and cos the cosine between ray and triangle
+ * normal, to bin 8 * d + c, d = distance bin with edges
+ * 0.5, 1, 1.5, 2, 3, 4, 6 m and c = min(7, floor(8 |cos|)); the features are
+ * log1p of the bin sums (summed in ray order).  Misses add nothing.
+ * Non-finite poses or height return UVC_EINVAL (the poses are copied to the
+ * host for the check, which synchronises hip_stream). */
+uvc_status uvc_ranker_features(const uvc_scene* scene, const float* poses_dev,
+                               int64_t K, int32_t pose_dim, float src_height,
+                               float* feat_dev, void* hip_stream);
+
+/* Scores score_dev[b] (B FP32, device) of the MLP with parameters
+ * params_dev on features feat_dev (B x 64).  bf16 != 0 rounds every weight
+ * and layer input to bfloat16 (nearest even) before its FP32 product and
+ * accumulation. */
+uvc_status uvc_ranker_forward(const float* params_dev, const float* feat_dev,
+                              int64_t B, int32_t bf16, float* score_dev,
+                              void* hip_stream);
+
+/* Non-learned baseline score: the visible area sum_b expm1(feat[k,b]). */
+uvc_status uvc_ranker_area_score(const float* feat_dev, int64_t K,
+                                 float* score_dev, void* hip_stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with the
+ * 1-based step count) on the mean binary cross-entropy with logits of the
+ * batch: rows idx_dev[0..B) of feat_dev / label_dev (idx_dev NULL: rows
+ * 0..B).  params_dev, adam_m, adam_v: uvc_ranker_param_count() FP32 each,
+ * device, updated in place.  grad_out_dev: NULL or a device buffer of the
+ * same size that receives the batch gradient.  *loss_out (host, may be NULL)
+ * receives the batch's mean loss before the update.  Synchronises
+ * hip_stream. */
+uvc_status uvc_ranker_train_step(float* params_dev, float* adam_m,
+                                 float* adam_v, const float* feat_dev,
+                                 const float* label_dev,
+                                 const int32_t* idx_dev, int64_t B, float lr,
+                                 int64_t step, float* grad_out_dev,
+                                 float* loss_out, void* hip_stream);
+
+enum { UVC_RANK_MLP = 0, UVC_RANK_AREA = 1, UVC_RANK_NONE = 2 };
+
+typedef struct {
+    double objective;     /* LP objective of the returned plan                     */
+    int64_t n_kept;       /* poses in the LP that produced the plan                */
+    int32_t fell_back;    /* 1: the full candidate set produced the plan           */
+    int32_t lp_iterations;
+    int32_t lp_converged;
+    int64_t n_uncovered;  /* reduced plan: elements with sigma_i > 1e-6 mu_min     */
+    int64_t n_checked;    /* of those, checked against every candidate pose        */
+    int64_t n_coverable;  /* of the checked, elements some pose doses within t_max */
+    float ms_features, ms_score, ms_E, ms_lp, ms_check, ms_fallback, ms_total;
+} uvc_plan_info;
+
+/* Dwell-time plan with pose pruning.  score_mode UVC_RANK_MLP scores the K
+ * poses with the MLP (params_dev, bf16 as in uvc_ranker_forward) on features
+ * taken at feature_height; UVC_RANK_AREA scores them by visible area;
+ * UVC_RANK_NONE keeps every pose.  The ceil(keep_frac K) best-scoring poses
+ * (ties: lower index) are kept, E is assembled on them (opts as for the
+ * dense call) and the relaxed LP is solved with its default penalty (tol,
+ * max_iter as for uvc_solve_dosage_lp).  Elements with
+ * sigma_i > 1e-6 mu_min are then checked against all K poses, in blocks,
+ * until one is found with max_k E[k,i] * t_max >= mu_min.  If one is found,
+ * the reduced LP did not converge, or its dwell times reach t_max, the plan
+ * is recomputed from all K poses (fell_back = 1).  Outputs: t_out_dev (K
+ * FP64, zero for pruned poses), sigma_out_dev (N FP64), kept_host (NULL or
+ * K int32: the first n_kept entries list the poses of the LP, ascending) and
+ * *info with HIP-event stage times.  Synchronises hip_stream. */
+uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses_dev,
+                           int64_t K, int32_t pose_dim, const uvc_lamp* lamp,
+                           const uvc_opts* opts, int32_t score_mode,
+                           const float* params_dev, int32_t bf16,
+                           float keep_frac, float feature_height,
+                           double mu_min, double t_max, double tol,
+                           int32_t max_iter, double* t_out_dev,
+                           double* sigma_out_dev, int32_t* kept_host,
+                           uvc_plan_info* info, void* hip_stream);
+
+/* Objective of a dwell-time plan t_dev (K FP64, device) on the dense E_dev
+ * (K x N FP32, device): sum_k t_k + p * sum_i max(0, mu_min - sum_k E[k,i] t_k)
+ * over the visible elements (some E[k,i] > 0), i.e. the relaxed LP objective
+ * with sigma at its smallest feasible value.  penalty <= 0 selects the LP's
+ * default p = 1.001 ||E||_F.  Optional outputs: the shortfall sum, the number
+ * of visible elements short by more than 1e-6 mu_min, the number of visible
+ * elements.  Used to compare plans from different pose subsets on the same
+ * matrix.  Synchronises hip_stream. */
+uvc_status uvc_plan_evaluate(const float* E_dev, int64_t K, int64_t N,
+                             const double* t_dev, double mu_min,
+                             double penalty, double* objective,
+                             double* shortfall, int64_t* n_short,
+                             int64_t* n_visible, void* hip_stream);
 
 #ifdef __cplusplus
 }

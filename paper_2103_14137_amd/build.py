@@ -44,7 +44,7 @@ def hipcc() -> str:
 
 
 def sources():
-    return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
 def build(verbose: bool = False) -> str:
@@ -61,6 +61,8 @@ def build_asm(out_dir: str) -> None:
     """Write the gfx950 assembly of every source (for inspection)."""
     os.makedirs(out_dir, exist_ok=True)
     for src in sources():
+        if not src.endswith(".hip"):
+            continue
         base = os.path.splitext(os.path.basename(src))[0]
         cmd = [hipcc(), *[f for f in HIPCC_FLAGS if f not in ("-shared", "-fPIC")], "--cuda-device-only", "-S",
                src, "-o", os.path.join(out_dir, base + ".s")]

@@ -45,8 +45,12 @@ struct IrrParams {
     const int32_t* near;
     const float* poses;        // poses of this launch (row k = pose k of the launch)
     const int32_t* pose_order; // hierarchy path: packet position -> pose row
+    const int32_t* targets;    // NULL (every element, columns = input index) or
+                               // leaf slots of the target elements (column = list position)
     int64_t K;                 // poses in this launch
-    int64_t N;
+    int64_t N;                 // triangles in the scene
+    int64_t ntargets;          // elements computed (N, or the length of targets)
+    int64_t ld;                // row stride of E and vis
     int64_t ntiles;            // element tiles per pose tile
     int64_t nquads;            // ceil(ntiles / 4)
     int64_t kgroups;           // pose tiles (hierarchy) or poses (brute force)
@@ -208,15 +212,21 @@ struct ElemLane {
     bool valid;
 };
 
-__device__ __forceinline__ ElemLane load_elem(const IrrParams& P, int64_t slot) {
+__device__ __forceinline__ ElemLane load_elem(const IrrParams& P, int64_t& slot, int64_t& col) {
     ElemLane e;
-    e.valid = slot < P.N;
+    e.valid = slot < P.ntargets;
+    col = 0;
+    if (e.valid && P.targets) {
+        col = slot;
+        slot = P.targets[slot];
+    }
     if (e.valid) {
         const float4* q = reinterpret_cast<const float4*>(P.elem + slot * ELEM_WORDS);
         const float4 a = q[0], b = q[1];
         e.cx = a.x; e.cy = a.y; e.cz = a.z; e.nx = a.w; e.ny = b.x; e.nz = b.y;
         e.self = __float_as_int(b.z);
         e.rho_t = b.w;
+        if (!P.targets) col = e.self;
     } else {
         e.cx = e.cy = e.cz = e.nx = e.ny = e.nz = e.rho_t = 0.f;
         e.self = -1;
@@ -356,8 +366,8 @@ __device__ __forceinline__ void irr_lbvh_packet(const IrrParams& P, int64_t kg, 
     const int64_t kpos = (kg << tkl) + kk;
     const bool kok = kpos < P.K;
     const int64_t k = kok ? P.pose_order[kpos] : 0;
-    const int64_t slot = (tile << tel) + ee;
-    const ElemLane e = load_elem(P, slot);
+    int64_t slot = (tile << tel) + ee, col;
+    const ElemLane e = load_elem(P, slot, col);
     const bool ok = kok && e.valid;
     const float* pp = P.poses + k * P.pose_dim;
     const float px = kok ? pp[0] : 0.0f, py = kok ? pp[1] : 0.0f;
@@ -406,8 +416,8 @@ __device__ __forceinline__ void irr_lbvh_packet(const IrrParams& P, int64_t kg, 
         }
     }
     if (ok) {
-        P.E[k * P.N + e.self] = acc;
-        if (P.vis) P.vis[k * P.N + e.self] = bits;
+        P.E[k * P.ld + col] = acc;
+        if (P.vis) P.vis[k * P.ld + col] = bits;
     }
     if (STATS) {
         const unsigned long long rc = wave_sum_u32((unsigned)rechecks), fc = wave_sum_u32((unsigned)f64);
@@ -495,8 +505,8 @@ __global__ __launch_bounds__(256) void k_irr_brute(IrrParams P) {
     block_coords(P, kk, quad);  // kgroups = K: one pose per workgroup
     const int lane = lane_id(), w = (int)(threadIdx.x >> 6), tid = (int)threadIdx.x;
     const int64_t tile = quad * 4 + w;
-    const int64_t slot = tile * 64 + lane;
-    const ElemLane e = load_elem(P, slot);  // invalid lanes (and whole waves past the end) idle
+    int64_t slot = tile * 64 + lane, col;
+    const ElemLane e = load_elem(P, slot, col);  // invalid lanes (and whole waves past the end) idle
     const float* pp = P.poses + kk * P.pose_dim;
     const float px = pp[0], py = pp[1], pz0 = (P.pose_dim == 3) ? pp[2] : 0.0f;
     const int TT = P.tile_tris;
@@ -577,8 +587,8 @@ __global__ __launch_bounds__(256) void k_irr_brute(IrrParams P) {
         }
     }
     if (e.valid) {
-        P.E[kk * P.N + e.self] = acc;
-        if (P.vis) P.vis[kk * P.N + e.self] = bits;
+        P.E[kk * P.ld + col] = acc;
+        if (P.vis) P.vis[kk * P.ld + col] = bits;
     }
     if (STATS) {
         const unsigned long long rc = wave_sum_u32((unsigned)rechecks), fc = wave_sum_u32((unsigned)f64);
@@ -693,6 +703,9 @@ static uvc_status make_params(const uvc_scene* s, const float* poses, int64_t K,
     P.poses = poses;
     P.K = K;
     P.N = s->n;
+    P.ntargets = s->n;
+    P.ld = s->n;
+    P.targets = nullptr;
     P.pose_dim = pd;
     int tk = (opts && opts->packet_poses > 0) ? opts->packet_poses : 16;
     if (tk != 1 && tk != 2 && tk != 4 && tk != 8 && tk != 16 && tk != 32 && tk != 64)
@@ -780,9 +793,10 @@ static uvc_status launch_irr_impl(const IrrParams& P0, int path, hipStream_t st)
     if (P0.K == 0 || P0.N == 0) return UVC_OK;
     IrrParams P = P0;
     const int64_t per = (path == UVC_PATH_BRUTE) ? 64 : ((int64_t)1 << (6 - P.tk_log2));
-    P.ntiles = (P.N + per - 1) / per;
+    P.ntiles = (P.ntargets + per - 1) / per;
     P.nquads = (P.ntiles + 3) / 4;
     P.kgroups = (path == UVC_PATH_BRUTE) ? P.K : ((P.K + (1 << P.tk_log2) - 1) >> P.tk_log2);
+    if (P.ntargets == 0) return UVC_OK;
     const uint64_t blocks = (uint64_t)P.nquads * (uint64_t)P.kgroups;
     if (blocks > 0x7fffffffull) return fail(UVC_EUNSUPPORTED, "launch too large; split the poses");
     const bool stats = P.stats != nullptr;
@@ -1085,7 +1099,7 @@ extern "C" uvc_status uvc_batch_create(const uvc_scene* const* scenes, int32_t n
         P.vis = nullptr;
         P.stats = nullptr;
         const int64_t per = (int64_t)1 << (6 - P.tk_log2);
-        P.ntiles = (P.N + per - 1) / per;
+        P.ntiles = (P.ntargets + per - 1) / per;
         P.nquads = (P.ntiles + 3) / 4;
         P.kgroups = (P.K + (1 << P.tk_log2) - 1) >> P.tk_log2;
         b->rooms.push_back(P);
@@ -1206,4 +1220,54 @@ extern "C" void uvc_batch_destroy(uvc_batch* b) {
     if (!b) return;
     (void)hipDeviceSynchronize();
     free_batch(b);
+}
+
+extern "C" uvc_status uvc_compute_irradiance_targets(const uvc_scene* scene, const float* poses_dev, int64_t K,
+                                                     int32_t pose_dim, const uvc_lamp* lamp, const uvc_opts* opts,
+                                                     const int32_t* targets_dev, int64_t n_targets, float* E_dev,
+                                                     uint32_t* vis_dev, void* hip_stream) {
+    IrrParams P;
+    UVC_TRY(make_params(scene, poses_dev, K, pose_dim, lamp, opts, P));
+    if (n_targets < 0) return fail(UVC_EINVAL, "n_targets < 0");
+    if (K == 0 || scene->n == 0 || n_targets == 0) return UVC_OK;
+    if (!E_dev || !targets_dev) return fail(UVC_EINVAL, "E or targets is NULL");
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::vector<float> hp;
+    UVC_TRY(fetch_poses(scene, poses_dev, K, pose_dim, P.lamp, st, hp));
+    // targets are input element indices: check the range and map them to leaf slots
+    std::vector<int32_t> ht((size_t)n_targets), perm((size_t)scene->n), slot((size_t)scene->n);
+    UVC_HIP(hipMemcpyAsync(ht.data(), targets_dev, (size_t)n_targets * 4, hipMemcpyDeviceToHost, st));
+    UVC_HIP(hipMemcpyAsync(perm.data(), scene->perm, (size_t)scene->n * 4, hipMemcpyDeviceToHost, st));
+    UVC_HIP(hipStreamSynchronize(st));
+    for (int64_t s2 = 0; s2 < scene->n; ++s2) slot[(size_t)perm[(size_t)s2]] = (int32_t)s2;
+    for (int64_t j = 0; j < n_targets; ++j) {
+        if (ht[(size_t)j] < 0 || ht[(size_t)j] >= scene->n)
+            return fail(UVC_EINVAL, "target " + std::to_string(j) + " is not an element index");
+        ht[(size_t)j] = slot[(size_t)ht[(size_t)j]];
+    }
+    int32_t* dslots = nullptr;
+    UVC_HIP(hipMallocAsync(reinterpret_cast<void**>(&dslots), (size_t)n_targets * 4, st));
+    hipError_t he = hipMemcpyAsync(dslots, ht.data(), (size_t)n_targets * 4, hipMemcpyHostToDevice, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    if (he != hipSuccess) {
+        (void)hipFreeAsync(dslots, st);
+        return fail(UVC_EDEVICE, std::string("targets upload: ") + hipGetErrorString(he));
+    }
+    const int path = choose_path(scene, opts);
+    int32_t* dorder = nullptr;
+    uvc_status r = UVC_OK;
+    if (path == UVC_PATH_LBVH) r = upload_order(hp, pose_dim, 0, K, st, &dorder);
+    if (r == UVC_OK) {
+        P.pose_order = dorder;
+        P.targets = dslots;
+        P.ntargets = n_targets;
+        P.ld = n_targets;
+        P.E = E_dev;
+        P.vis = vis_dev;
+        if (opts && opts->kernel_ms) *opts->kernel_ms = 0.f;
+        r = launch_irr(P, path, st, opts ? opts->kernel_ms : nullptr);
+    }
+    if (dorder) (void)hipFreeAsync(dorder, st);
+    (void)hipFreeAsync(dslots, st);
+    return r;
 }

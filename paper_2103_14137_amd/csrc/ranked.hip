@@ -1,0 +1,337 @@
+// Ranked plan: prune the candidate poses with a score, assemble E on the
+// kept poses only, solve the relaxed dosage LP (Sec. IV-D) on that reduced
+// matrix, check that no element which the full candidate set could dose was
+// left uncovered, and fall back to the full candidate set otherwise.
+#include "uvc_common.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+namespace uvc {
+namespace {
+
+__global__ void k_gather_rows(const float* __restrict__ src, const int32_t* __restrict__ rows, int64_t n, int dim,
+                              float* __restrict__ dst) {
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q >= n * dim) return;
+    dst[q] = src[(int64_t)rows[q / dim] * dim + q % dim];
+}
+
+__global__ void k_fill_f64(double* __restrict__ p, double v, int64_t n) {
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q < n) p[q] = v;
+}
+
+__global__ void k_scatter_f64(const double* __restrict__ src, const int32_t* __restrict__ rows, int64_t n,
+                              double* __restrict__ dst) {
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q < n) dst[rows[q]] = src[q];
+}
+
+// colmax[j] = max_k E[k * n + j]: one thread per column, rows read in order
+// (a row of n consecutive floats is read by consecutive threads).
+__global__ void k_colmax(const float* __restrict__ E, int64_t K, int64_t n, float* __restrict__ out) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    float m = 0.f;
+    for (int64_t k = 0; k < K; ++k) m = fmaxf(m, E[k * n + j]);
+    out[j] = m;
+}
+
+// Per column i: a = sum_k E[k,i] t_k (FP64, ascending k), visible = some
+// E[k,i] > 0, shortfall = max(0, mu - a) over visible columns.  Per block:
+// the shortfall sum, the count of shortfalls above short_tol, and the sum of
+// E^2 (FP64) of the block's columns, reduced in a fixed tree order.
+constexpr int EV_TB = 256;
+__global__ __launch_bounds__(EV_TB) void k_plan_eval(const float* __restrict__ E, int64_t K, int64_t N,
+                                                     const double* __restrict__ t, double mu, double short_tol,
+                                                     double* __restrict__ part_short, double* __restrict__ part_e2,
+                                                     int64_t* __restrict__ part_n, int64_t* __restrict__ part_vis) {
+    __shared__ double s_short[EV_TB], s_e2[EV_TB];
+    __shared__ int64_t s_n[EV_TB], s_v[EV_TB];
+    const int64_t i = blockIdx.x * (int64_t)EV_TB + threadIdx.x;
+    double sh = 0.0, e2 = 0.0;
+    int64_t ns = 0, nv = 0;
+    if (i < N) {
+        double a = 0.0;
+        bool vis = false;
+        for (int64_t k = 0; k < K; ++k) {
+            const double e = (double)E[k * N + i];
+            a += e * t[k];
+            e2 += e * e;
+            vis = vis || e > 0.0;
+        }
+        if (vis) {
+            nv = 1;
+            sh = a < mu ? mu - a : 0.0;
+            ns = sh > short_tol ? 1 : 0;
+        }
+    }
+    s_short[threadIdx.x] = sh;
+    s_e2[threadIdx.x] = e2;
+    s_n[threadIdx.x] = ns;
+    s_v[threadIdx.x] = nv;
+    __syncthreads();
+    for (int w = EV_TB / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s_short[threadIdx.x] += s_short[threadIdx.x + w];
+            s_e2[threadIdx.x] += s_e2[threadIdx.x + w];
+            s_n[threadIdx.x] += s_n[threadIdx.x + w];
+            s_v[threadIdx.x] += s_v[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part_short[blockIdx.x] = s_short[0];
+        part_e2[blockIdx.x] = s_e2[0];
+        part_n[blockIdx.x] = s_n[0];
+        part_vis[blockIdx.x] = s_v[0];
+    }
+}
+
+unsigned grid_of(int64_t n, int tb) { return (unsigned)((n + tb - 1) / tb); }
+
+struct Dev {
+    void* p = nullptr;
+    ~Dev() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+template <class T>
+uvc_status alloc(Dev& d, int64_t n, const char* what) {
+    return dalloc(&d.p, (size_t)std::max<int64_t>(n, 1) * sizeof(T), what);
+}
+
+struct Events {
+    hipEvent_t e[8] = {};
+    ~Events() {
+        for (auto& x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+};
+
+float ms_between(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+    return ms;
+}
+
+}  // namespace
+}  // namespace uvc
+
+using namespace uvc;
+
+extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses_dev, int64_t K, int32_t pose_dim,
+                                      const uvc_lamp* lamp, const uvc_opts* opts, int32_t score_mode,
+                                      const float* params_dev, int32_t bf16, float keep_frac, float feature_height,
+                                      double mu_min, double t_max, double tol, int32_t max_iter, double* t_out_dev,
+                                      double* sigma_out_dev, int32_t* kept_host, uvc_plan_info* info,
+                                      void* hip_stream) {
+    if (!scene || !poses_dev || !lamp || !t_out_dev || !sigma_out_dev || !info)
+        return fail(UVC_EINVAL, "NULL scene, poses, lamp, outputs or info");
+    if (K < 1 || (pose_dim != 2 && pose_dim != 3)) return fail(UVC_EINVAL, "K must be >= 1 and pose_dim 2 or 3");
+    if (K > (int64_t)INT32_MAX) return fail(UVC_EINVAL, "K too large");
+    if (score_mode != UVC_RANK_MLP && score_mode != UVC_RANK_AREA && score_mode != UVC_RANK_NONE)
+        return fail(UVC_EINVAL, "unknown score_mode");
+    if (score_mode == UVC_RANK_MLP && !params_dev) return fail(UVC_EINVAL, "MLP scoring needs params_dev");
+    if (!(keep_frac > 0.f && keep_frac <= 1.f)) return fail(UVC_EINVAL, "keep_frac must lie in (0, 1]");
+    const int64_t N = scene->n;
+    if (N < 1) return fail(UVC_EINVAL, "empty scene");
+    hipStream_t st = (hipStream_t)hip_stream;
+    uvc_opts o{};
+    if (opts) o = *opts;
+    o.stats_dev = nullptr;
+    o.kernel_ms = nullptr;
+    *info = uvc_plan_info{};
+    Events ev;
+    for (auto& x : ev.e) UVC_HIP(hipEventCreate(&x));
+    UVC_HIP(hipEventRecord(ev.e[0], st));
+
+    uvc_lp_info li{};
+    auto full_plan = [&](hipEvent_t before, hipEvent_t after) -> uvc_status {
+        Dev E;
+        UVC_TRY(alloc<float>(E, K * N, "E (full candidate set)"));
+        UVC_TRY(uvc_compute_irradiance_dense(scene, poses_dev, K, pose_dim, lamp, &o, (float*)E.p, nullptr, st));
+        UVC_HIP(hipEventRecord(before, st));
+        const uvc_status s = uvc_solve_dosage_lp((const float*)E.p, K, N, nullptr, mu_min, t_max, tol, max_iter,
+                                                 t_out_dev, sigma_out_dev, &li, st);
+        UVC_HIP(hipEventRecord(after, st));
+        if (s != UVC_OK && s != UVC_ENOTCONV) return s;
+        info->n_kept = K;
+        info->objective = li.objective;
+        info->lp_iterations = li.iterations;
+        info->lp_converged = s == UVC_OK ? 1 : 0;
+        if (kept_host)
+            for (int64_t k = 0; k < K; ++k) kept_host[k] = (int32_t)k;
+        return UVC_OK;
+    };
+
+    if (score_mode == UVC_RANK_NONE) {
+        UVC_TRY(full_plan(ev.e[1], ev.e[2]));
+        UVC_HIP(hipEventSynchronize(ev.e[2]));
+        info->ms_E = ms_between(ev.e[0], ev.e[1]);
+        info->ms_lp = ms_between(ev.e[1], ev.e[2]);
+        info->ms_total = ms_between(ev.e[0], ev.e[2]);
+        return UVC_OK;
+    }
+
+    // 1. features and scores
+    Dev feat, score;
+    UVC_TRY(alloc<float>(feat, K * 64, "ranker features"));
+    UVC_TRY(alloc<float>(score, K, "ranker scores"));
+    UVC_TRY(uvc_ranker_features(scene, poses_dev, K, pose_dim, feature_height, (float*)feat.p, st));
+    UVC_HIP(hipEventRecord(ev.e[1], st));
+    if (score_mode == UVC_RANK_MLP)
+        UVC_TRY(uvc_ranker_forward(params_dev, (const float*)feat.p, K, bf16, (float*)score.p, st));
+    else
+        UVC_TRY(uvc_ranker_area_score((const float*)feat.p, K, (float*)score.p, st));
+    std::vector<float> hs((size_t)K);
+    UVC_HIP(hipMemcpyAsync(hs.data(), score.p, (size_t)K * 4, hipMemcpyDeviceToHost, st));
+    UVC_HIP(hipStreamSynchronize(st));
+    // 2. keep the ceil(keep_frac K) best scores (ties: lower index first),
+    // then restore the candidates' own order
+    const int64_t keep = std::min<int64_t>(K, std::max<int64_t>(1, (int64_t)std::ceil((double)keep_frac * (double)K)));
+    std::vector<int32_t> order((size_t)K);
+    std::iota(order.begin(), order.end(), 0);
+    auto better = [&](int32_t a, int32_t b) {
+        const float sa = hs[(size_t)a], sb = hs[(size_t)b];
+        const bool na = sa != sa, nb = sb != sb;  // NaN scores rank last
+        if (na != nb) return nb;
+        if (!na && sa != sb) return sa > sb;
+        return a < b;
+    };
+    std::partial_sort(order.begin(), order.begin() + keep, order.end(), better);
+    std::vector<int32_t> kept(order.begin(), order.begin() + keep);
+    std::sort(kept.begin(), kept.end());
+    Dev dkept, red_poses;
+    UVC_TRY(alloc<int32_t>(dkept, keep, "kept pose list"));
+    UVC_TRY(alloc<float>(red_poses, keep * pose_dim, "kept poses"));
+    UVC_HIP(hipMemcpyAsync(dkept.p, kept.data(), (size_t)keep * 4, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_gather_rows, dim3(grid_of(keep * pose_dim, 256)), dim3(256), 0, st, poses_dev,
+                       (const int32_t*)dkept.p, keep, pose_dim, (float*)red_poses.p);
+    UVC_HIP(hipGetLastError());
+    UVC_HIP(hipEventRecord(ev.e[2], st));
+    // 3. reduced E and its LP
+    Dev Ered, tred;
+    UVC_TRY(alloc<float>(Ered, keep * N, "E (kept poses)"));
+    UVC_TRY(alloc<double>(tred, keep, "reduced dwell times"));
+    UVC_TRY(uvc_compute_irradiance_dense(scene, (const float*)red_poses.p, keep, pose_dim, lamp, &o, (float*)Ered.p,
+                                         nullptr, st));
+    UVC_HIP(hipEventRecord(ev.e[3], st));
+    const uvc_status lps = uvc_solve_dosage_lp((const float*)Ered.p, keep, N, nullptr, mu_min, t_max, tol, max_iter,
+                                               (double*)tred.p, sigma_out_dev, &li, st);
+    if (lps != UVC_OK && lps != UVC_ENOTCONV) return lps;
+    UVC_HIP(hipEventRecord(ev.e[4], st));
+    info->n_kept = keep;
+    info->objective = li.objective;
+    info->lp_iterations = li.iterations;
+    info->lp_converged = lps == UVC_OK ? 1 : 0;
+    // 4. coverage check: elements left (partly) to the penalty term, then
+    // whether the full candidate set could give any of them the dose within
+    // the time budget, max_k E[k,i] * t_max >= mu_min
+    std::vector<double> sig((size_t)N);
+    UVC_HIP(hipMemcpyAsync(sig.data(), sigma_out_dev, (size_t)N * 8, hipMemcpyDeviceToHost, st));
+    std::vector<double> ht((size_t)keep);
+    UVC_HIP(hipMemcpyAsync(ht.data(), tred.p, (size_t)keep * 8, hipMemcpyDeviceToHost, st));
+    UVC_HIP(hipStreamSynchronize(st));
+    std::vector<int32_t> unc;
+    for (int64_t i = 0; i < N; ++i)
+        if (sig[(size_t)i] > 1e-6 * mu_min) unc.push_back((int32_t)i);
+    info->n_uncovered = (int64_t)unc.size();
+    double tsum = 0.0;
+    for (double v : ht) tsum += v;
+    bool fallback = lps != UVC_OK || tsum >= t_max * (1.0 - 1e-6);
+    if (!fallback && !unc.empty()) {
+        const int64_t nu = (int64_t)unc.size();
+        const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nu, ((int64_t)1 << 26) / K));
+        Dev dunc, Echk, cmax;
+        UVC_TRY(alloc<int32_t>(dunc, nu, "uncovered element list"));
+        UVC_TRY(alloc<float>(Echk, K * chunk, "coverage check block"));
+        UVC_TRY(alloc<float>(cmax, chunk, "coverage check maxima"));
+        UVC_HIP(hipMemcpyAsync(dunc.p, unc.data(), (size_t)nu * 4, hipMemcpyHostToDevice, st));
+        std::vector<float> hm((size_t)chunk);
+        const double need = mu_min / t_max;
+        for (int64_t c0 = 0; c0 < nu && !fallback; c0 += chunk) {
+            const int64_t c = std::min(chunk, nu - c0);
+            UVC_TRY(uvc_compute_irradiance_targets(scene, poses_dev, K, pose_dim, lamp, &o,
+                                                   (const int32_t*)dunc.p + c0, c, (float*)Echk.p, nullptr, st));
+            hipLaunchKernelGGL(k_colmax, dim3(grid_of(c, 256)), dim3(256), 0, st, (const float*)Echk.p, K, c,
+                               (float*)cmax.p);
+            UVC_HIP(hipGetLastError());
+            UVC_HIP(hipMemcpyAsync(hm.data(), cmax.p, (size_t)c * 4, hipMemcpyDeviceToHost, st));
+            UVC_HIP(hipStreamSynchronize(st));
+            for (int64_t j = 0; j < c; ++j)
+                if ((double)hm[(size_t)j] >= need) ++info->n_coverable;
+            info->n_checked += c;
+            fallback = info->n_coverable > 0;
+        }
+    }
+    UVC_HIP(hipEventRecord(ev.e[5], st));
+    if (fallback) {
+        info->fell_back = 1;
+        UVC_TRY(full_plan(ev.e[6], ev.e[7]));
+    } else {
+        hipLaunchKernelGGL(k_fill_f64, dim3(grid_of(K, 256)), dim3(256), 0, st, t_out_dev, 0.0, K);
+        hipLaunchKernelGGL(k_scatter_f64, dim3(grid_of(keep, 256)), dim3(256), 0, st, (const double*)tred.p,
+                           (const int32_t*)dkept.p, keep, t_out_dev);
+        UVC_HIP(hipGetLastError());
+        UVC_HIP(hipEventRecord(ev.e[6], st));
+        UVC_HIP(hipEventRecord(ev.e[7], st));
+        if (kept_host) std::copy(kept.begin(), kept.end(), kept_host);
+    }
+    UVC_HIP(hipEventSynchronize(ev.e[7]));
+    info->ms_features = ms_between(ev.e[0], ev.e[1]);
+    info->ms_score = ms_between(ev.e[1], ev.e[2]);
+    info->ms_E = ms_between(ev.e[2], ev.e[3]);
+    info->ms_lp = ms_between(ev.e[3], ev.e[4]);
+    info->ms_check = ms_between(ev.e[4], ev.e[5]);
+    info->ms_fallback = ms_between(ev.e[5], ev.e[7]);
+    info->ms_total = ms_between(ev.e[0], ev.e[7]);
+    return UVC_OK;
+}
+
+extern "C" uvc_status uvc_plan_evaluate(const float* E_dev, int64_t K, int64_t N, const double* t_dev,
+                                        double mu_min, double penalty, double* objective, double* shortfall,
+                                        int64_t* n_short, int64_t* n_visible, void* hip_stream) {
+    if (!E_dev || !t_dev || !objective) return fail(UVC_EINVAL, "NULL E, t or objective");
+    if (K < 1 || N < 1) return fail(UVC_EINVAL, "empty matrix");
+    if (!(mu_min > 0.0) || !std::isfinite(mu_min) || !std::isfinite(penalty))
+        return fail(UVC_EINVAL, "mu_min must be positive and the penalty finite");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int64_t nb = (N + EV_TB - 1) / EV_TB;
+    if (nb > (int64_t)INT32_MAX) return fail(UVC_EINVAL, "N too large");
+    Dev ps, pe, pn, pv;
+    UVC_TRY(alloc<double>(ps, nb, "evaluation partials"));
+    UVC_TRY(alloc<double>(pe, nb, "evaluation partials"));
+    UVC_TRY(alloc<int64_t>(pn, nb, "evaluation partials"));
+    UVC_TRY(alloc<int64_t>(pv, nb, "evaluation partials"));
+    hipLaunchKernelGGL(k_plan_eval, dim3((unsigned)nb), dim3(EV_TB), 0, st, E_dev, K, N, t_dev, mu_min,
+                       1e-6 * mu_min, (double*)ps.p, (double*)pe.p, (int64_t*)pn.p, (int64_t*)pv.p);
+    UVC_HIP(hipGetLastError());
+    std::vector<double> hs((size_t)nb), he((size_t)nb), ht((size_t)K);
+    std::vector<int64_t> hn((size_t)nb), hv((size_t)nb);
+    UVC_HIP(hipMemcpyAsync(hs.data(), ps.p, (size_t)nb * 8, hipMemcpyDeviceToHost, st));
+    UVC_HIP(hipMemcpyAsync(he.data(), pe.p, (size_t)nb * 8, hipMemcpyDeviceToHost, st));
+    UVC_HIP(hipMemcpyAsync(hn.data(), pn.p, (size_t)nb * 8, hipMemcpyDeviceToHost, st));
+    UVC_HIP(hipMemcpyAsync(hv.data(), pv.p, (size_t)nb * 8, hipMemcpyDeviceToHost, st));
+    UVC_HIP(hipMemcpyAsync(ht.data(), t_dev, (size_t)K * 8, hipMemcpyDeviceToHost, st));
+    UVC_HIP(hipStreamSynchronize(st));
+    double sh = 0.0, e2 = 0.0, tsum = 0.0;
+    int64_t ns = 0, nv = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        sh += hs[(size_t)b];
+        e2 += he[(size_t)b];
+        ns += hn[(size_t)b];
+        nv += hv[(size_t)b];
+    }
+    for (double v : ht) tsum += v;
+    const double p = penalty > 0.0 ? penalty : 1.001 * std::sqrt(e2);
+    *objective = tsum + p * sh;
+    if (shortfall) *shortfall = sh;
+    if (n_short) *n_short = ns;
+    if (n_visible) *n_visible = nv;
+    return UVC_OK;
+}

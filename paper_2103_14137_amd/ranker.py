@@ -1,0 +1,238 @@
+"""Learned pose ranker: training, checkpoints and held-out evaluation.
+
+Host orchestration only.  Features, labels (the irradiance matrix and the
+relaxed dosage LP of Sec. IV-D), the forward and backward passes, Adam and
+the ranked plan all run in libuvc kernels through the binding; this module
+draws seeded rooms, shuffles sample indices, and reads and writes files.
+
+Labels: a pose is positive when the full-candidate LP gives it a dwell time
+above LABEL_REL times the plan's total dwell time.  The LP solver is an
+interior point method, so poses outside the optimal support keep dwell
+times near the solver tolerance instead of exact zeros; the relative
+threshold separates the two.
+
+Checkpoint format: one JSON header line (magic, parameter count, Adam step,
+metadata), then the parameters, and optionally Adam's m and v, as raw
+little-endian float32.
+
+    python -m paper_2103_14137_amd.ranker train --out ranker.bin
+    python -m paper_2103_14137_amd.ranker eval --weights ranker.bin
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import uvc, workloads
+
+MAGIC = "uvc-ranker-v1"
+LABEL_REL = 1e-5
+FEATURE_HEIGHT = 0.9
+# training / held-out rooms: the batched-room generator at reduced sizes
+TRAIN_N_RANGE = (2000, 20000)
+TRAIN_K_RANGE = (200, 1000)
+TRAIN_SEED0 = 100_000
+HELDOUT_SEED0 = 900_000
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """He-normal weights for the ReLU layers, small output layer, zero biases."""
+    rng = np.random.default_rng(seed)
+    w1 = rng.normal(0.0, math.sqrt(2.0 / 64), size=(128, 64))
+    w2 = rng.normal(0.0, math.sqrt(2.0 / 128), size=(128, 128))
+    w3 = rng.normal(0.0, math.sqrt(1.0 / 128), size=128)
+    p = np.concatenate([w1.ravel(), np.zeros(128), w2.ravel(), np.zeros(128), w3, [0.0]]).astype(np.float32)
+    assert p.size == uvc.ranker_param_count()
+    return p
+
+
+def save_checkpoint(path: str, params, m=None, v=None, step: int = 0, meta: dict | None = None) -> None:
+    arrs = [np.asarray(a, np.float32).reshape(-1) for a in (params, m, v) if a is not None]
+    n = arrs[0].size
+    if any(a.size != n for a in arrs):
+        raise ValueError("params, m and v must have the same size")
+    head = {"magic": MAGIC, "n_params": int(n), "has_adam": len(arrs) == 3, "step": int(step), "meta": meta or {}}
+    with open(path, "wb") as f:
+        f.write((json.dumps(head, sort_keys=True) + "\n").encode())
+        for a in arrs:
+            f.write(a.astype("<f4").tobytes())
+
+
+def load_checkpoint(path: str) -> dict:
+    with open(path, "rb") as f:
+        head = json.loads(f.readline().decode())
+        if head.get("magic") != MAGIC:
+            raise ValueError(f"{path}: not a ranker checkpoint")
+        n = int(head["n_params"])
+        body = np.frombuffer(f.read(), dtype="<f4")
+    k = 3 if head["has_adam"] else 1
+    if body.size != k * n:
+        raise ValueError(f"{path}: truncated checkpoint")
+    out = {"params": body[:n].copy(), "step": int(head["step"]), "meta": head["meta"], "m": None, "v": None}
+    if k == 3:
+        out["m"], out["v"] = body[n:2 * n].copy(), body[2 * n:].copy()
+    return out
+
+
+def room(seed: int, n_range=TRAIN_N_RANGE, k_range=TRAIN_K_RANGE) -> workloads.Workload:
+    return workloads.batch_room(seed, n_range=n_range, k_range=k_range)
+
+
+def room_samples(w: workloads.Workload, mu_min: float = 280.0, t_max: float = 3.6e5, tol: float = 1e-9) -> dict:
+    """Features and LP labels of one room (full candidate set)."""
+    sc = uvc.Scene(w.mesh.verts, w.mesh.tris)
+    try:
+        poses = torch.from_numpy(np.ascontiguousarray(w.poses, np.float32)).cuda()
+        feat = uvc.ranker_features(sc, poses, FEATURE_HEIGHT)
+        E, _ = uvc.irradiance_dense(sc, poses, w.lamp, path="lbvh")
+        lp = uvc.solve_lp(E, mu_min=mu_min, t_max=t_max, tol=tol, allow_notconv=True)
+        t = lp["t"].cpu().numpy()
+        y = (t > LABEL_REL * t.sum()).astype(np.float32)
+        return {"feat": feat.cpu(), "y": y, "objective": lp["objective"], "converged": lp["converged"],
+                "K": w.K, "N": w.N}
+    finally:
+        sc.close()
+
+
+def train(feat: torch.Tensor, y: np.ndarray, params=None, m=None, v=None, step0: int = 0, epochs: int = 30,
+          batch: int = 1024, lr: float = 1e-3, seed: int = 0, log=None):
+    """Adam on mean BCE; feat [S, 64] (any device), y [S].  Returns
+    (params, m, v, step, epoch losses) as NumPy arrays / ints."""
+    n = uvc.ranker_param_count()
+    dev = torch.device("cuda")
+    P = torch.from_numpy(np.asarray(params if params is not None else init_params(seed), np.float32)).to(dev)
+    M = torch.from_numpy(np.asarray(m, np.float32)).to(dev) if m is not None else torch.zeros(n, device=dev)
+    V = torch.from_numpy(np.asarray(v, np.float32)).to(dev) if v is not None else torch.zeros(n, device=dev)
+    X = feat.to(dev, torch.float32).contiguous()
+    Y = torch.from_numpy(np.asarray(y, np.float32)).to(dev)
+    S = X.shape[0]
+    rng = np.random.default_rng(seed)
+    step = step0
+    losses = []
+    for ep in range(epochs):
+        perm = rng.permutation(S).astype(np.int32)
+        tot, cnt = 0.0, 0
+        for b0 in range(0, S, batch):
+            idx = torch.from_numpy(perm[b0:b0 + batch]).to(dev)
+            step += 1
+            loss = uvc.ranker_train_step(P, M, V, X, Y, idx, lr, step)
+            tot += loss * idx.numel()
+            cnt += idx.numel()
+        losses.append(tot / max(cnt, 1))
+        if log:
+            log(f"epoch {ep + 1}/{epochs}: loss {losses[-1]:.5f}")
+    return P.cpu().numpy(), M.cpu().numpy(), V.cpu().numpy(), step, losses
+
+
+def evaluate_room(w: workloads.Workload, params: np.ndarray, keep_frac: float = 0.1, bf16: bool = False,
+                  modes=("mlp", "area"), mu_min: float = 280.0, t_max: float = 3.6e5, tol: float = 1e-9) -> dict:
+    """Full-candidate plan vs pruned plans of one room.  Every plan is scored
+    on the full E with the full LP's penalty (uvc_plan_evaluate)."""
+    sc = uvc.Scene(w.mesh.verts, w.mesh.tris)
+    try:
+        poses = torch.from_numpy(np.ascontiguousarray(w.poses, np.float32)).cuda()
+        P = torch.from_numpy(np.asarray(params, np.float32)).cuda()
+        full = uvc.plan_ranked(sc, poses, w.lamp, mode="none", mu_min=mu_min, t_max=t_max, tol=tol)
+        E, _ = uvc.irradiance_dense(sc, poses, w.lamp, path="lbvh")
+        ref = uvc.plan_evaluate(E, full["t"], mu_min)
+        out = {"room": w.name, "K": w.K, "N": w.N, "full_objective": ref["objective"],
+               "full_ms": full["ms_total"], "full_n_short": ref["n_short"]}
+        for mode in modes:
+            r = uvc.plan_ranked(sc, poses, w.lamp, mode=mode, params=P, bf16=bf16, keep_frac=keep_frac,
+                                mu_min=mu_min, t_max=t_max, tol=tol)
+            ev = uvc.plan_evaluate(E, r["t"], mu_min)
+            out[mode] = {"objective": ev["objective"],
+                         "gap": (ev["objective"] - ref["objective"]) / ref["objective"],
+                         "fell_back": r["fell_back"], "n_kept": r["n_kept"], "ms": r["ms_total"],
+                         "ms_parts": {k: r[k] for k in ("ms_features", "ms_score", "ms_E", "ms_lp", "ms_check",
+                                                        "ms_fallback")},
+                         "n_uncovered": r["n_uncovered"], "n_coverable": r["n_coverable"],
+                         "n_short": ev["n_short"]}
+        del E
+        return out
+    finally:
+        sc.close()
+
+
+def summarize(results: list, modes=("mlp", "area")) -> dict:
+    s = {"rooms": len(results)}
+    full_ms = np.array([r["full_ms"] for r in results])
+    for mode in modes:
+        g = np.array([r[mode]["gap"] for r in results])
+        fb = np.array([r[mode]["fell_back"] for r in results])
+        ms = np.array([r[mode]["ms"] for r in results])
+        s[mode] = {"gap_mean": float(g.mean()), "gap_median": float(np.median(g)), "gap_max": float(g.max()),
+                   "gap_le_2pct": float(np.mean(g <= 0.02)), "fallback_rate": float(fb.mean()),
+                   "ms_total": float(ms.sum()), "speedup_vs_full": float(full_ms.sum() / max(ms.sum(), 1e-9)),
+                   "gap_mean_no_fallback": float(g[fb == 0].mean()) if np.any(fb == 0) else None}
+    s["full_ms_total"] = float(full_ms.sum())
+    return s
+
+
+def _main(argv=None) -> int:
+    ap = argparse.ArgumentParser(prog="python -m paper_2103_14137_amd.ranker")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train", help="generate labelled rooms and train")
+    t.add_argument("--rooms", type=int, default=256)
+    t.add_argument("--epochs", type=int, default=40)
+    t.add_argument("--batch", type=int, default=1024)
+    t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--seed", type=int, default=0)
+    t.add_argument("--resume", default=None, help="checkpoint with Adam state to continue from")
+    t.add_argument("--out", required=True)
+    e = sub.add_parser("eval", help="held-out evaluation of a checkpoint")
+    e.add_argument("--weights", required=True)
+    e.add_argument("--rooms", type=int, default=64)
+    e.add_argument("--keep", type=float, default=0.1)
+    e.add_argument("--bf16", action="store_true")
+    e.add_argument("--json", default=None)
+    a = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, flush=True)
+
+    if a.cmd == "train":
+        feats, ys = [], []
+        t0 = time.time()
+        for r in range(a.rooms):
+            d = room_samples(room(TRAIN_SEED0 + r))
+            feats.append(d["feat"])
+            ys.append(d["y"])
+            if (r + 1) % 16 == 0:
+                log(f"labelled {r + 1}/{a.rooms} rooms ({time.time() - t0:.1f} s), "
+                    f"positives {np.concatenate(ys).mean():.4f}")
+        X = torch.cat(feats)
+        Y = np.concatenate(ys)
+        ck = load_checkpoint(a.resume) if a.resume else None
+        p, m, v, step, losses = train(X, Y, ck["params"] if ck else None, ck["m"] if ck else None,
+                                      ck["v"] if ck else None, ck["step"] if ck else 0, a.epochs, a.batch, a.lr,
+                                      a.seed, log)
+        meta = {"rooms": a.rooms, "samples": int(X.shape[0]), "positives": float(Y.mean()), "epochs": a.epochs,
+                "batch": a.batch, "lr": a.lr, "final_loss": losses[-1], "label_rel": LABEL_REL,
+                "feature_height": FEATURE_HEIGHT, "n_range": TRAIN_N_RANGE, "k_range": TRAIN_K_RANGE,
+                "seed0": TRAIN_SEED0}
+        save_checkpoint(a.out, p, m, v, step, meta)
+        log(json.dumps(meta))
+        return 0
+    ck = load_checkpoint(a.weights)
+    res = []
+    for r in range(a.rooms):
+        res.append(evaluate_room(room(HELDOUT_SEED0 + r), ck["params"], a.keep, a.bf16))
+        if (r + 1) % 8 == 0:
+            log(f"evaluated {r + 1}/{a.rooms}: {json.dumps(summarize(res))}")
+    s = summarize(res)
+    log(json.dumps(s))
+    if a.json:
+        with open(a.json, "w") as f:
+            json.dump({"summary": s, "rooms": res}, f, indent=1)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(_main())

@@ -49,6 +49,14 @@ class OptsC(ctypes.Structure):
                 ("kernel_ms", ctypes.POINTER(ctypes.c_float))]
 
 
+class PlanInfoC(ctypes.Structure):
+    _fields_ = [("objective", ctypes.c_double), ("n_kept", _I64), ("fell_back", _I32), ("lp_iterations", _I32),
+                ("lp_converged", _I32), ("n_uncovered", _I64), ("n_checked", _I64), ("n_coverable", _I64),
+                ("ms_features", ctypes.c_float), ("ms_score", ctypes.c_float), ("ms_E", ctypes.c_float),
+                ("ms_lp", ctypes.c_float), ("ms_check", ctypes.c_float), ("ms_fallback", ctypes.c_float),
+                ("ms_total", ctypes.c_float)]
+
+
 _lib = None
 
 
@@ -71,6 +79,8 @@ def lib():
         "uvc_destroy_scene": ([_P], None),
         "uvc_compute_irradiance_dense": ([_P, _P, _I64, _I32, ctypes.POINTER(LampC), ctypes.POINTER(OptsC), _P, _P,
                                           _P], _I32),
+        "uvc_compute_irradiance_targets": ([_P, _P, _I64, _I32, ctypes.POINTER(LampC), ctypes.POINTER(OptsC), _P,
+                                            _I64, _P, _P, _P], _I32),
         "uvc_compute_irradiance_csr_begin": ([_P, _P, _I64, _I32, ctypes.POINTER(LampC), ctypes.POINTER(OptsC), _P,
                                               ctypes.POINTER(_P), ctypes.POINTER(_I64)], _I32),
         "uvc_compute_irradiance_csr_finish": ([_P, _P, _P, _P, _P], _I32),
@@ -80,8 +90,21 @@ def lib():
                              _I32),
         "uvc_batch_run": ([_P, _I32, ctypes.POINTER(ctypes.c_float), _P], _I32),
         "uvc_batch_destroy": ([_P], None),
+        "uvc_autotune": ([_P, _P, _I64, _I32, ctypes.POINTER(LampC), _I32, ctypes.c_char_p, _I32,
+                          ctypes.POINTER(OptsC), _P], _I32),
         "uvc_solve_dosage_lp": ([_P, _I64, _I64, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _I32, _P, _P,
                                  ctypes.POINTER(LpInfoC), _P], _I32),
+        "uvc_ranker_param_count": ([], _I64),
+        "uvc_ranker_features": ([_P, _P, _I64, _I32, ctypes.c_float, _P, _P], _I32),
+        "uvc_ranker_forward": ([_P, _P, _I64, _I32, _P, _P], _I32),
+        "uvc_ranker_area_score": ([_P, _I64, _P, _P], _I32),
+        "uvc_ranker_train_step": ([_P, _P, _P, _P, _P, _P, _I64, ctypes.c_float, _I64, _P,
+                                   ctypes.POINTER(ctypes.c_float), _P], _I32),
+        "uvc_plan_ranked": ([_P, _P, _I64, _I32, ctypes.POINTER(LampC), ctypes.POINTER(OptsC), _I32, _P, _I32,
+                             ctypes.c_float, ctypes.c_float, ctypes.c_double, ctypes.c_double, ctypes.c_double, _I32,
+                             _P, _P, _P, ctypes.POINTER(PlanInfoC), _P], _I32),
+        "uvc_plan_evaluate": ([_P, _I64, _I64, _P, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), ctypes.POINTER(_I64), _P], _I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -232,6 +255,25 @@ def irradiance_dense(scene: Scene, poses: torch.Tensor, lamp, path="auto", band_
     return out, vis
 
 
+def irradiance_targets(scene: Scene, poses: torch.Tensor, lamp, targets: torch.Tensor, path="auto",
+                       band_scale: float = 1.0, want_vis: bool = False, stream=None, packet_poses: int = 0,
+                       flags: int = 0, waves: int = 0, tile_tris: int = 0):
+    """K x len(targets) irradiance of the listed input elements (column j =
+    element targets[j])."""
+    poses = _require_cuda(poses, "poses", torch.float32)
+    targets = _require_cuda(targets, "targets", torch.int32)
+    K, pd = poses.shape
+    n = targets.numel()
+    lamp = as_lamp(lamp)
+    out = torch.empty((K, n), dtype=torch.float32, device=poses.device)
+    vis = torch.empty((K, n), dtype=torch.int32, device=poses.device) if want_vis else None
+    opts = make_opts(path, band_scale, tile_tris, None, None, packet_poses, flags, waves)
+    check(lib().uvc_compute_irradiance_targets(scene.handle, poses.data_ptr(), K, pd, ctypes.byref(lamp._c),
+                                               ctypes.byref(opts), targets.data_ptr(), n, out.data_ptr(),
+                                               vis.data_ptr() if vis is not None else None, _stream(stream)))
+    return out, vis
+
+
 def irradiance_csr(scene: Scene, poses: torch.Tensor, lamp, path="auto", band_scale: float = 1.0,
                    stats: torch.Tensor | None = None, tile_tris: int = 0, stream=None, packet_poses: int = 0,
                    flags: int = 0):
@@ -329,3 +371,124 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def autotune(scene: Scene, poses: torch.Tensor, lamp, probe_poses: int = 256, table_path: str | None = None,
+             force: bool = False, stream=None) -> dict:
+    """Fastest launch options for this scene size class (see uvc_autotune)."""
+    poses = _require_cuda(poses, "poses", torch.float32)
+    K, pd = poses.shape
+    lamp = as_lamp(lamp)
+    best = OptsC()
+    check(lib().uvc_autotune(scene.handle, poses.data_ptr(), K, pd, ctypes.byref(lamp._c), int(probe_poses),
+                             table_path.encode() if table_path else None, int(force), ctypes.byref(best),
+                             _stream(stream)))
+    return {"path": {0: "auto", 1: "lbvh", 2: "brute"}[best.path], "packet_poses": best.packet_poses,
+            "waves": best.waves, "tile_tris": best.tile_tris}
+
+
+# ------------------------------------------------------------------ ranker
+RANK_MODES = {"mlp": 0, "area": 1, "none": 2}
+FEATURES = 64
+
+
+def ranker_param_count() -> int:
+    return int(lib().uvc_ranker_param_count())
+
+
+def ranker_features(scene: Scene, poses: torch.Tensor, src_height: float = 0.9, stream=None) -> torch.Tensor:
+    """K x 64 visibility features of the poses (see uvc_ranker_features)."""
+    poses = _require_cuda(poses, "poses", torch.float32)
+    K, pd = poses.shape
+    feat = torch.empty((K, FEATURES), dtype=torch.float32, device=poses.device)
+    check(lib().uvc_ranker_features(scene.handle, poses.data_ptr(), K, pd, float(src_height), feat.data_ptr(),
+                                    _stream(stream)))
+    return feat
+
+
+def ranker_forward(params: torch.Tensor, feat: torch.Tensor, bf16: bool = False, stream=None) -> torch.Tensor:
+    params = _require_cuda(params, "params", torch.float32)
+    feat = _require_cuda(feat, "feat", torch.float32)
+    if params.numel() != ranker_param_count() or feat.ndim != 2 or feat.shape[1] != FEATURES:
+        raise ValueError("params must hold ranker_param_count() floats and feat be [B, 64]")
+    B = feat.shape[0]
+    score = torch.empty(B, dtype=torch.float32, device=feat.device)
+    check(lib().uvc_ranker_forward(params.data_ptr(), feat.data_ptr(), B, int(bool(bf16)), score.data_ptr(),
+                                   _stream(stream)))
+    return score
+
+
+def ranker_area_score(feat: torch.Tensor, stream=None) -> torch.Tensor:
+    feat = _require_cuda(feat, "feat", torch.float32)
+    if feat.ndim != 2 or feat.shape[1] != FEATURES:
+        raise ValueError("feat must be [K, 64]")
+    score = torch.empty(feat.shape[0], dtype=torch.float32, device=feat.device)
+    check(lib().uvc_ranker_area_score(feat.data_ptr(), feat.shape[0], score.data_ptr(), _stream(stream)))
+    return score
+
+
+def ranker_train_step(params: torch.Tensor, m: torch.Tensor, v: torch.Tensor, feat: torch.Tensor,
+                      labels: torch.Tensor, idx: torch.Tensor | None, lr: float, step: int,
+                      grad_out: torch.Tensor | None = None, stream=None) -> float:
+    """One Adam step in place on params / m / v; returns the batch loss."""
+    n = ranker_param_count()
+    for name, t in (("params", params), ("m", m), ("v", v)):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+                and t.numel() == n):
+            raise ValueError(f"{name} must be a contiguous CUDA float32 tensor of {n} values")
+    feat = _require_cuda(feat, "feat", torch.float32)
+    labels = _require_cuda(labels, "labels", torch.float32)
+    if idx is not None:
+        idx = _require_cuda(idx, "idx", torch.int32)
+        B = idx.numel()
+    else:
+        B = feat.shape[0]
+    if grad_out is not None and not (grad_out.is_cuda and grad_out.dtype == torch.float32 and grad_out.numel() == n):
+        raise ValueError("grad_out must be a CUDA float32 tensor of the parameter count")
+    loss = ctypes.c_float(0.0)
+    check(lib().uvc_ranker_train_step(params.data_ptr(), m.data_ptr(), v.data_ptr(), feat.data_ptr(),
+                                      labels.data_ptr(), idx.data_ptr() if idx is not None else None, B, float(lr),
+                                      int(step), grad_out.data_ptr() if grad_out is not None else None,
+                                      ctypes.byref(loss), _stream(stream)))
+    return float(loss.value)
+
+
+def plan_ranked(scene: Scene, poses: torch.Tensor, lamp, mode: str = "mlp", params: torch.Tensor | None = None,
+                bf16: bool = False, keep_frac: float = 0.1, feature_height: float = 0.9, mu_min: float = 280.0,
+                t_max: float = 3.6e5, tol: float = 1e-9, max_iter: int = 200, path="lbvh", packet_poses: int = 0,
+                waves: int = 0, stream=None) -> dict:
+    """Dwell-time plan with pose pruning (see uvc_plan_ranked)."""
+    poses = _require_cuda(poses, "poses", torch.float32)
+    K, pd = poses.shape
+    lamp = as_lamp(lamp)
+    if params is not None:
+        params = _require_cuda(params, "params", torch.float32)
+    t = torch.empty(K, dtype=torch.float64, device=poses.device)
+    sg = torch.empty(scene.n, dtype=torch.float64, device=poses.device)
+    kept = np.zeros(K, np.int32)
+    info = PlanInfoC()
+    opts = make_opts(path, packet_poses=packet_poses, waves=waves)
+    check(lib().uvc_plan_ranked(scene.handle, poses.data_ptr(), K, pd, ctypes.byref(lamp._c), ctypes.byref(opts),
+                                RANK_MODES[mode], params.data_ptr() if params is not None else None, int(bool(bf16)),
+                                float(keep_frac), float(feature_height), float(mu_min), float(t_max), float(tol),
+                                int(max_iter), t.data_ptr(), sg.data_ptr(), kept.ctypes.data_as(_P),
+                                ctypes.byref(info), _stream(stream)))
+    out = {f: getattr(info, f) for f, _ in PlanInfoC._fields_}
+    out.update(t=t, sigma=sg, kept=kept[:info.n_kept].copy())
+    return out
+
+
+def plan_evaluate(E: torch.Tensor, t: torch.Tensor, mu_min: float = 280.0, penalty: float = 0.0,
+                  stream=None) -> dict:
+    """Objective of dwell times t on E with sigma at its smallest feasible
+    value (see uvc_plan_evaluate)."""
+    E = _require_cuda(E, "E", torch.float32)
+    t = _require_cuda(t, "t", torch.float64)
+    K, N = E.shape
+    if t.numel() != K:
+        raise ValueError("t must hold one value per row of E")
+    obj, sh = ctypes.c_double(), ctypes.c_double()
+    ns, nv = _I64(), _I64()
+    check(lib().uvc_plan_evaluate(E.data_ptr(), K, N, t.data_ptr(), float(mu_min), float(penalty), ctypes.byref(obj),
+                                  ctypes.byref(sh), ctypes.byref(ns), ctypes.byref(nv), _stream(stream)))
+    return {"objective": obj.value, "shortfall": sh.value, "n_short": ns.value, "n_visible": nv.value}

@@ -365,6 +365,8 @@ typedef struct {
     int64_t n_uncovered;  /* reduced plan: elements with sigma_i > 1e-6 mu_min     */
     int64_t n_checked;    /* of those, checked against every candidate pose        */
     int64_t n_coverable;  /* of the checked, elements some pose doses within t_max */
+    int64_t n_added;      /* poses added by the repair round                       */
+    int32_t repaired;     /* 1: the plan comes from the repaired pose set          */
     float ms_features, ms_score, ms_E, ms_lp, ms_check, ms_fallback, ms_total;
 } uvc_plan_info;
 
@@ -375,10 +377,16 @@ typedef struct {
  * (ties: lower index) are kept, E is assembled on them (opts as for the
  * dense call) and the relaxed LP is solved with its default penalty (tol,
  * max_iter as for uvc_solve_dosage_lp).  Elements with
- * sigma_i > 1e-6 mu_min are then checked against all K poses, in blocks,
- * until one is found with max_k E[k,i] * t_max >= mu_min.  If one is found,
- * the reduced LP did not converge, or its dwell times reach t_max, the plan
- * is recomputed from all K poses (fell_back = 1).  Outputs: t_out_dev (K
+ * sigma_i > 1e-6 mu_min are then checked against all K poses, in blocks:
+ * those with max_k E[k,i] * t_max >= mu_min could be dosed by the full
+ * candidate set.  If there are any and repair_rounds = 1, a repair round
+ * adds poses greedily
+ * (each time the pruned pose that reaches at least half the best irradiance
+ * of the most such elements still open), recomputes E and the LP on the
+ * enlarged set and checks again (repair_rounds = 0: no repair).  If
+ * dosable elements remain uncovered, a reduced LP does not converge, or its
+ * dwell times
+ * reach t_max, the plan is recomputed from all K poses (fell_back = 1).  Outputs: t_out_dev (K
  * FP64, zero for pruned poses), sigma_out_dev (N FP64), kept_host (NULL or
  * K int32: the first n_kept entries list the poses of the LP, ascending) and
  * *info with HIP-event stage times.  Synchronises hip_stream. */
@@ -388,7 +396,8 @@ uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses_dev,
                            const float* params_dev, int32_t bf16,
                            float keep_frac, float feature_height,
                            double mu_min, double t_max, double tol,
-                           int32_t max_iter, double* t_out_dev,
+                           int32_t max_iter, int32_t repair_rounds,
+                           double* t_out_dev,
                            double* sigma_out_dev, int32_t* kept_host,
                            uvc_plan_info* info, void* hip_stream);
 

@@ -17,7 +17,9 @@
 //   d~ = D_c Theta_s / (D_c + Theta_s),
 // formed on the GPU by an FP64 SYRK over the FP32 matrix and factored by a
 // blocked FP64 Cholesky; the two solves per iteration (predictor, corrector)
-// reuse the factor.  The O(K + N) vector algebra runs on the host in FP64.
+// reuse the factor.  The iterate and all O(K + N) vector algebra stay on the
+// device in FP64; per iteration the host reads back a few reduced scalars
+// (residual norms, step lengths, the affine complementarity gap).
 // Every device reduction sums in a fixed order: results are deterministic.
 #include "uvc_common.hpp"
 
@@ -197,8 +199,10 @@ constexpr int SY_KC = 16;  // inner chunk
 
 // M[a][b] = sum_i E[a,i] d[i] E[b,i] for the lower tiles (tile row >= tile
 // col) of the K x K row-major M.  256 threads, 4 x 4 outputs each.
+// With splits > 1, workgroup (tile, s) covers columns [s N / splits,
+// (s + 1) N / splits) and writes the partial product to M + s K^2.
 __global__ __launch_bounds__(256) void k_syrk(const float* __restrict__ E, int64_t K, int64_t N,
-                                              const double* __restrict__ d, double* __restrict__ M) {
+                                              const double* __restrict__ d, double* __restrict__ M, int splits) {
     __shared__ double As[SY_KC][SY_T + 1];
     __shared__ double Bs[SY_KC][SY_T + 1];
     // lower-triangular tile index -> (tr, tc)
@@ -210,14 +214,17 @@ __global__ __launch_bounds__(256) void k_syrk(const float* __restrict__ E, int64
     const int64_t a0 = tr * SY_T, b0 = tc * SY_T;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
     double acc[4][4] = {};
-    for (int64_t i0 = 0; i0 < N; i0 += SY_KC) {
+    const int64_t per = ((N + splits - 1) / splits + SY_KC - 1) / SY_KC * SY_KC;
+    const int64_t ib = (int64_t)blockIdx.y * per, ie = std::min<int64_t>(N, ib + per);
+    double* Mo = M + (int64_t)blockIdx.y * K * K;
+    for (int64_t i0 = ib; i0 < ie; i0 += SY_KC) {
         for (int q = threadIdx.x; q < SY_T * SY_KC; q += 256) {
             const int r = q / SY_KC, kk = q % SY_KC;
             const int64_t i = i0 + kk;
             const int64_t a = a0 + r, b = b0 + r;
-            const double di = (i < N) ? d[i] : 0.0;
-            As[kk][r] = (a < K && i < N) ? (double)E[a * N + i] * di : 0.0;
-            Bs[kk][r] = (b < K && i < N) ? (double)E[b * N + i] : 0.0;
+            const double di = (i < ie) ? d[i] : 0.0;
+            As[kk][r] = (a < K && i < ie) ? (double)E[a * N + i] * di : 0.0;
+            Bs[kk][r] = (b < K && i < ie) ? (double)E[b * N + i] : 0.0;
         }
         __syncthreads();
 #pragma unroll
@@ -238,7 +245,7 @@ __global__ __launch_bounds__(256) void k_syrk(const float* __restrict__ E, int64
     for (int u = 0; u < 4; ++u)
         for (int v = 0; v < 4; ++v) {
             const int64_t a = a0 + ty * 4 + u, b = b0 + tx * 4 + v;
-            if (a < K && b < K && b <= a) M[a * K + b] = acc[u][v];
+            if (a < K && b < K && b <= a) Mo[a * K + b] = acc[u][v];
         }
 }
 
@@ -290,23 +297,30 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ M, int64
     }
 }
 
-// Rows r >= j0 + nb: L[r, j0:j0+nb] = M[r, j0:j0+nb] L_jj^-T (one row per thread).
+// Rows r >= j0 + nb: L[r, j0:j0+nb] = M[r, j0:j0+nb] L_jj^-T (one row per
+// thread).  The diagonal block sits in LDS; each thread keeps its row's
+// unknowns in its own LDS column (conflict-free), so nothing spills.
 __global__ __launch_bounds__(256) void k_chol_trsm(double* __restrict__ M, int64_t K, int64_t j0, int nb) {
     __shared__ double L[CH_B][CH_B + 1];
+    __shared__ double inv[CH_B];
+    __shared__ double X[CH_B][256];
     for (int q = threadIdx.x; q < nb * nb; q += 256) {
         const int r = q / nb, c = q % nb;
         L[r][c] = (c <= r) ? M[(j0 + r) * K + j0 + c] : 0.0;
     }
     __syncthreads();
+    if ((int)threadIdx.x < nb) inv[threadIdx.x] = 1.0 / L[threadIdx.x][threadIdx.x];
+    __syncthreads();
     const int64_t r = j0 + nb + blockIdx.x * (int64_t)256 + threadIdx.x;
     if (r >= K) return;
-    double x[CH_B];
+    const int t = threadIdx.x;
+    for (int c = 0; c < nb; ++c) X[c][t] = M[r * K + j0 + c];
     for (int c = 0; c < nb; ++c) {
-        double v = M[r * K + j0 + c];
-        for (int q = 0; q < c; ++q) v -= x[q] * L[c][q];
-        x[c] = v / L[c][c];
+        double v = X[c][t];
+        for (int q = 0; q < c; ++q) v -= X[q][t] * L[c][q];
+        X[c][t] = v * inv[c];
     }
-    for (int c = 0; c < nb; ++c) M[r * K + j0 + c] = x[c];
+    for (int c = 0; c < nb; ++c) M[r * K + j0 + c] = X[c][t];
 }
 
 // Trailing update of the lower part: M[a][b] -= sum_q L[a][j0+q] L[b][j0+q]
@@ -340,24 +354,39 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ M, int
         }
 }
 
-// Solve L L^T x = r in place (one workgroup of 1024 threads): forward then
-// backward substitution, blocks of 64 unknowns solved by one thread each
-// step while the other threads update the remaining right-hand side.
+// Solve L L^T x = r in place (one workgroup of 1024 threads).  Each 64 x 64
+// diagonal block is staged in LDS and solved by one wave, lane r holding
+// unknown r (column-oriented substitution with lane broadcasts); the other
+// rows are then updated by all threads.
 __global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ L, int64_t K, double* __restrict__ x) {
+    __shared__ double Lb[64][65];
     __shared__ double zb[64];
+    const int tid = threadIdx.x;
     // forward: L z = r
     for (int64_t j0 = 0; j0 < K; j0 += 64) {
         const int nb = (int)((K - j0) < 64 ? (K - j0) : 64);
-        if (threadIdx.x == 0) {
+        for (int q = tid; q < nb * nb; q += 1024) {
+            const int r = q / nb, c = q % nb;
+            Lb[r][c] = (c <= r) ? L[(j0 + r) * K + j0 + c] : 0.0;
+        }
+        if (tid < nb) zb[tid] = x[j0 + tid];
+        __syncthreads();
+        if (tid < 64) {
+            double v = tid < nb ? zb[tid] : 0.0;
             for (int c = 0; c < nb; ++c) {
-                double v = x[j0 + c];
-                for (int q = 0; q < c; ++q) v -= L[(j0 + c) * K + j0 + q] * zb[q];
-                zb[c] = v / L[(j0 + c) * K + j0 + c];
-                x[j0 + c] = zb[c];
+                const double zc = __shfl(v, c) / Lb[c][c];
+                if (tid == c)
+                    v = zc;
+                else if (tid > c && tid < nb)
+                    v -= Lb[tid][c] * zc;
+            }
+            if (tid < nb) {
+                zb[tid] = v;
+                x[j0 + tid] = v;
             }
         }
         __syncthreads();
-        for (int64_t r = j0 + nb + threadIdx.x; r < K; r += 1024) {
+        for (int64_t r = j0 + nb + tid; r < K; r += 1024) {
             double v = 0.0;
             for (int q = 0; q < nb; ++q) v += L[r * K + j0 + q] * zb[q];
             x[r] -= v;
@@ -368,17 +397,28 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ 
     for (int64_t j1 = K; j1 > 0; j1 -= 64) {
         const int64_t j0 = j1 >= 64 ? j1 - 64 : 0;
         const int nb = (int)(j1 - j0);
-        if (threadIdx.x == 0) {
+        for (int q = tid; q < nb * nb; q += 1024) {
+            const int r = q / nb, c = q % nb;
+            Lb[r][c] = (c <= r) ? L[(j0 + r) * K + j0 + c] : 0.0;
+        }
+        if (tid < nb) zb[tid] = x[j0 + tid];
+        __syncthreads();
+        if (tid < 64) {
+            double v = tid < nb ? zb[tid] : 0.0;
             for (int c = nb - 1; c >= 0; --c) {
-                double v = x[j0 + c];
-                for (int q = c + 1; q < nb; ++q) v -= L[(j0 + q) * K + j0 + c] * zb[q];
-                zb[c] = v / L[(j0 + c) * K + j0 + c];
-                x[j0 + c] = zb[c];
+                const double zc = __shfl(v, c) / Lb[c][c];
+                if (tid == c)
+                    v = zc;
+                else if (tid < c)
+                    v -= Lb[c][tid] * zc;
+            }
+            if (tid < nb) {
+                zb[tid] = v;
+                x[j0 + tid] = v;
             }
         }
         __syncthreads();
-        // rows above the block: x[r] -= sum_q L[j0+q][r] zb[q]
-        for (int64_t r = threadIdx.x; r < j0; r += 1024) {
+        for (int64_t r = tid; r < j0; r += 1024) {
             double v = 0.0;
             for (int q = 0; q < nb; ++q) v += L[(j0 + q) * K + r] * zb[q];
             x[r] -= v;
@@ -389,13 +429,381 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ 
 
 static inline unsigned nblk(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + LP_TB - 1) / LP_TB); }
 
+// -------------------------------------------------- interior point kernels
+// Iterate (device, FP64): x = (t[K], sigma[N]), z = (zt[K], zs[N]),
+// s = (sc[N], s_b), y = (yc[N], y_b).  Hidden (invisible) elements keep
+// every entry at zero.  The budget-row scalars s_b, y_b live on the host;
+// the direction's budget components dy_b, ds_b are formed on the device
+// (k_ipm_bscal) so that no direction needs a host round trip.
+struct IpmPtr {
+    // K
+    double *xt, *zt, *rdt, *tht, *mvK, *mvK2;
+    double *dt[2], *dzt[2];
+    // N
+    double *xs, *zs, *yc, *sc, *pen, *rpc, *rds, *drc, *ths, *dtil, *rhs, *rpp, *mvN, *u;
+    double *dsig[2], *dzs[2], *dyc[2], *dsc[2];
+    const unsigned char* vis;
+    double* S;  // device scalars, see S_* below
+};
+enum { S_SUMDT0 = 0, S_DYB0 = 1, S_DSB0 = 2, S_SUMDT1 = 3, S_DYB1 = 4, S_DSB1 = 5, S_REG = 6, S_RED = 8 };
+constexpr int IPM_SUMS = 8;
+
+// Residuals: rpc = mu - (E^T t + sigma) + sc, rds = p - yc - zs (visible i);
+// rdt = 1 - (E yc - y_b) - zt.
+__global__ void k_ipm_resid_N(IpmPtr P, int64_t N, double mu) {
+    const int64_t i = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
+    if (i >= N) return;
+    if (P.vis[i]) {
+        P.rpc[i] = mu - (P.mvN[i] + P.xs[i]) + P.sc[i];
+        P.rds[i] = P.pen[i] - P.yc[i] - P.zs[i];
+    } else {
+        P.rpc[i] = 0.0;
+        P.rds[i] = 0.0;
+    }
+}
+__global__ void k_ipm_resid_K(IpmPtr P, int64_t K, double yb) {
+    const int64_t k = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
+    if (k < K) P.rdt[k] = 1.0 - (P.mvK[k] - yb) - P.zt[k];
+}
+
+// Scalings: drc = yc / sc, ths = zs / sigma, dtil = drc ths / (drc + ths),
+// tht = zt / t.
+__global__ void k_ipm_scale(IpmPtr P, int64_t K, int64_t N) {
+    const int64_t i = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
+    if (i < N) {
+        if (P.vis[i]) {
+            const double a = P.yc[i] / P.sc[i], b = P.zs[i] / P.xs[i];
+            P.drc[i] = a;
+            P.ths[i] = b;
+            P.dtil[i] = a * b / (a + b);
+        } else {
+            P.drc[i] = 0.0;
+            P.ths[i] = 0.0;
+            P.dtil[i] = 0.0;
+        }
+    }
+    if (i < K) P.tht[i] = P.zt[i] / P.xt[i];
+}
+
+// Complementarity right-hand sides: predictor (mode 0) -x z, -s y;
+// corrector (mode 1) sigmu - x z - dx_aff dz_aff, sigmu - s y - ds_aff dy_aff.
+__device__ __forceinline__ double rsy_of(const IpmPtr& P, int64_t i, int mode, double sigmu) {
+    return mode ? sigmu - P.sc[i] * P.yc[i] - P.dsc[0][i] * P.dyc[0][i] : -P.sc[i] * P.yc[i];
+}
+__device__ __forceinline__ double rxzs_of(const IpmPtr& P, int64_t i, int mode, double sigmu) {
+    return mode ? sigmu - P.xs[i] * P.zs[i] - P.dsig[0][i] * P.dzs[0][i] : -P.xs[i] * P.zs[i];
+}
+
+// Direction, part a (elements): rpp = rpc + rsy / yc, wv = drc rpp,
+// rhs = wv - rds + rxz / sigma, q = drc / (drc + ths) rhs, u = wv - q.
+__global__ void k_dir_a(IpmPtr P, int64_t N, int mode, double sigmu) {
+    const int64_t i = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
+    if (i >= N) return;
+    if (!P.vis[i]) {
+        P.rpp[i] = 0.0;
+        P.rhs[i] = 0.0;
+        P.u[i] = 0.0;
+        return;
+    }
+    const double rpp = P.rpc[i] + rsy_of(P, i, mode, sigmu) / P.yc[i];
+    const double wv = P.drc[i] * rpp;
+    const double rhs = wv - P.rds[i] + rxzs_of(P, i, mode, sigmu) / P.xs[i];
+    const double q = P.drc[i] / (P.drc[i] + P.ths[i]) * rhs;
+    P.rpp[i] = rpp;
+    P.rhs[i] = rhs;
+    P.u[i] = wv - q;
+}
+
+// Part b (poses): dt = E u - wv_b - rdt + rxz_t / t  (then solved with M).
+__global__ void k_dir_b(IpmPtr P, int64_t K, int mode, double sigmu, double wvb, int d) {
+    const int64_t k = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
+    if (k >= K) return;
+    const double rxz = mode ? sigmu - P.xt[k] * P.zt[k] - P.dt[0][k] * P.dzt[0][k] : -P.xt[k] * P.zt[k];
+    P.dt[d][k] = P.mvK[k] - wvb - P.rdt[k] + rxz / P.xt[k];
+}
+
+// Budget-row components: gdx_b = -sum dt, dy_b = D_b (rpp_b - gdx_b),
+// ds_b = (rsy_b - s_b dy_b) / y_b.  One workgroup; fixed-order sum.
+__global__ __launch_bounds__(LP_TB) void k_ipm_bscal(IpmPtr P, int64_t K, int d, double Db, double rppb,
+                                                     double rsyb, double sb, double yb) {
+    __shared__ double red[LP_TB];
+    double a = 0.0;
+    for (int64_t k = threadIdx.x; k < K; k += LP_TB) a += P.dt[d][k];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = LP_TB / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double sdt = red[0];
+        const double dyb = Db * (rppb + sdt);
+        const double dsb = (rsyb - sb * dyb) / yb;
+        P.S[3 * d + 0] = sdt;
+        P.S[3 * d + 1] = dyb;
+        P.S[3 * d + 2] = dsb;
+    }
+}
+
+// Part c (elements), with etd = E^T dt in mvN: dsigma, dy_c, ds_c, dz_s.
+__global__ void k_dir_c(IpmPtr P, int64_t N, int mode, double sigmu, int d) {
+    const int64_t i = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
+    if (i >= N) return;
+    if (!P.vis[i]) {
+        P.dsig[d][i] = 0.0;
+        P.dyc[d][i] = 0.0;
+        P.dsc[d][i] = 0.0;
+        P.dzs[d][i] = 0.0;
+        return;
+    }
+    const double a = P.drc[i], b = P.ths[i];
+    const double etd = P.mvN[i];
+    const double dsg = (P.rhs[i] - a * etd) / (a + b);
+    const double gdx = etd + dsg;
+    const double dy = a * (P.rpp[i] - gdx);
+    P.dsig[d][i] = dsg;
+    P.dyc[d][i] = dy;
+    P.dsc[d][i] = (rsy_of(P, i, mode, sigmu) - P.sc[i] * dy) / P.yc[i];
+    P.dzs[d][i] = P.rds[i] - dy;
+}
+
+// Part d (poses), with E dy_c in mvK2: dz_t = rdt - (E dy_c - dy_b).
+__global__ void k_dir_d(IpmPtr P, int64_t K, int d) {
+    const int64_t k = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
+    if (k >= K) return;
+    P.dzt[d][k] = P.rdt[k] - (P.mvK2[k] - P.S[3 * d + 1]);
+}
+
+// Fixed-order block reductions over the index space [0, K + N): job
+//  0 residual sums: [0] sum t, [1] x.z + sc.yc, [2] p.sigma, [3] sum yc,
+//    [4] |rpc|^2, [5] |rd|^2
+//  1 largest steps of direction d: [0] primal min ratio, [1] dual min ratio
+//  2 affine complementarity: [0] sum (x + ap dx)(z + ad dz) + (s + ap ds)(y + ad dy)
+//  3 final objective of the clamped iterate: [0] sum max(t,0), [1] p.max(sigma,0)
+//  4 sum p^2 over visible elements: [0]
+//  5 [0] sum of dt[d]
+//  6 minima: [0] over (t, sigma, s_c), [1] over (z_t, z_sigma, y_c)
+//  7 start sums: [0] x.z + s.y, [1] sum z + sum y, [2] sum x + sum s
+__global__ __launch_bounds__(LP_TB) void k_ipm_reduce(IpmPtr P, int64_t K, int64_t N, int job, int d, double ap,
+                                                      double ad, double* __restrict__ part) {
+    __shared__ double red[IPM_SUMS][LP_TB];
+    double acc[IPM_SUMS];
+    const bool is_min = job == 1 || job == 6;
+    for (int q = 0; q < IPM_SUMS; ++q) acc[q] = is_min ? 1e300 : 0.0;
+    const int64_t n = K + N;
+    for (int64_t j = blockIdx.x * (int64_t)LP_TB + threadIdx.x; j < n; j += (int64_t)gridDim.x * LP_TB) {
+        if (j < K) {
+            const int64_t k = j;
+            if (job == 0) {
+                acc[0] += P.xt[k];
+                acc[1] += P.xt[k] * P.zt[k];
+                acc[5] += P.rdt[k] * P.rdt[k];
+            } else if (job == 1) {
+                if (P.dt[d][k] < 0.0 && P.xt[k] > 0.0) acc[0] = fmin(acc[0], -P.xt[k] / P.dt[d][k]);
+                if (P.dzt[d][k] < 0.0 && P.zt[k] > 0.0) acc[1] = fmin(acc[1], -P.zt[k] / P.dzt[d][k]);
+            } else if (job == 2) {
+                acc[0] += (P.xt[k] + ap * P.dt[0][k]) * (P.zt[k] + ad * P.dzt[0][k]);
+            } else if (job == 3) {
+                acc[0] += fmax(P.xt[k], 0.0);
+            } else if (job == 5) {
+                acc[0] += P.dt[d][k];
+            } else if (job == 6) {
+                acc[0] = fmin(acc[0], P.xt[k]);
+                acc[1] = fmin(acc[1], P.zt[k]);
+            } else if (job == 7) {
+                acc[0] += P.xt[k] * P.zt[k];
+                acc[1] += P.zt[k];
+                acc[2] += P.xt[k];
+            }
+        } else {
+            const int64_t i = j - K;
+            if (!P.vis[i]) continue;
+            if (job == 0) {
+                acc[1] += P.xs[i] * P.zs[i] + P.sc[i] * P.yc[i];
+                acc[2] += P.pen[i] * P.xs[i];
+                acc[3] += P.yc[i];
+                acc[4] += P.rpc[i] * P.rpc[i];
+                acc[5] += P.rds[i] * P.rds[i];
+            } else if (job == 1) {
+                if (P.dsig[d][i] < 0.0 && P.xs[i] > 0.0) acc[0] = fmin(acc[0], -P.xs[i] / P.dsig[d][i]);
+                if (P.dsc[d][i] < 0.0 && P.sc[i] > 0.0) acc[0] = fmin(acc[0], -P.sc[i] / P.dsc[d][i]);
+                if (P.dzs[d][i] < 0.0 && P.zs[i] > 0.0) acc[1] = fmin(acc[1], -P.zs[i] / P.dzs[d][i]);
+                if (P.dyc[d][i] < 0.0 && P.yc[i] > 0.0) acc[1] = fmin(acc[1], -P.yc[i] / P.dyc[d][i]);
+            } else if (job == 2) {
+                acc[0] += (P.xs[i] + ap * P.dsig[0][i]) * (P.zs[i] + ad * P.dzs[0][i]) +
+                          (P.sc[i] + ap * P.dsc[0][i]) * (P.yc[i] + ad * P.dyc[0][i]);
+            } else if (job == 3) {
+                acc[1] += P.pen[i] * fmax(P.xs[i], 0.0);
+            } else if (job == 4) {
+                acc[0] += P.pen[i] * P.pen[i];
+            } else if (job == 6) {
+                acc[0] = fmin(acc[0], fmin(P.xs[i], P.sc[i]));
+                acc[1] = fmin(acc[1], fmin(P.zs[i], P.yc[i]));
+            } else if (job == 7) {
+                acc[0] += P.xs[i] * P.zs[i] + P.sc[i] * P.yc[i];
+                acc[1] += P.zs[i] + P.yc[i];
+                acc[2] += P.xs[i] + P.sc[i];
+            }
+        }
+    }
+    for (int q = 0; q < IPM_SUMS; ++q) red[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int w = LP_TB / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < IPM_SUMS; ++q)
+                red[q][threadIdx.x] = is_min ? fmin(red[q][threadIdx.x], red[q][threadIdx.x + w])
+                                             : red[q][threadIdx.x] + red[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < IPM_SUMS) part[blockIdx.x * IPM_SUMS + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Second pass: 64 threads per sum each fold a fixed stride of the block
+// partials, then a fixed-order tree over the 64 (one workgroup of 512).
+__global__ __launch_bounds__(512) void k_ipm_reduce2(const double* __restrict__ part, int nb, int is_min,
+                                                     double* __restrict__ out) {
+    __shared__ double red[IPM_SUMS][64];
+    const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
+    double a = is_min ? 1e300 : 0.0;
+    for (int b = l; b < nb; b += 64) a = is_min ? fmin(a, part[b * IPM_SUMS + q]) : a + part[b * IPM_SUMS + q];
+    red[q][l] = a;
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+        if (l < w) red[q][l] = is_min ? fmin(red[q][l], red[q][l + w]) : red[q][l] + red[q][l + w];
+        __syncthreads();
+    }
+    if (l == 0) out[q] = red[q][0];
+}
+
+__global__ void k_ipm_update(IpmPtr P, int64_t K, int64_t N, double ap, double ad) {
+    const int64_t j = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
+    if (j < K) {
+        P.xt[j] += ap * P.dt[1][j];
+        P.zt[j] += ad * P.dzt[1][j];
+    }
+    if (j < N && P.vis[j]) {
+        P.xs[j] += ap * P.dsig[1][j];
+        P.sc[j] += ap * P.dsc[1][j];
+        P.zs[j] += ad * P.dzs[1][j];
+        P.yc[j] += ad * P.dyc[1][j];
+    }
+}
+
+__global__ void k_ipm_init(IpmPtr P, int64_t K, int64_t N, double x0, double pdef, const double* __restrict__ pen_in,
+                           double mu) {
+    const int64_t j = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
+    if (j < K) {
+        P.xt[j] = x0;
+        P.zt[j] = x0;
+    }
+    if (j < N) {
+        const bool v = P.vis[j] != 0;
+        P.pen[j] = v ? (pen_in ? pen_in[j] : pdef) : 0.0;
+        P.xs[j] = v ? x0 : 0.0;
+        P.zs[j] = v ? x0 : 0.0;
+        P.sc[j] = v ? x0 : 0.0;
+        P.yc[j] = v ? 1.0 : 0.0;
+    }
+}
+
+// Mehrotra's starting point: least-norm x~ (with s~ = G x~ - h) and
+// least-squares (y~, z~), then shifted into the interior.  With unit
+// scalings the reduced matrix is M0 = E (I/2) E^T + 1 1^T + I.
+//  N ops: 0 u = mu/2 (vis); 1 [mvN = E^T t~] sigma~ = (mu - mvN)/2,
+//  s~ = mvN + sigma~ - mu; 2 [mvN = E^T 1] v = mvN + p -> rhs, u = v/2;
+//  3 [mvN = E^T w_t] y~ = (v - mvN)/2, z_sigma~ = p - y~; 4 unit scalings.
+__global__ void k_st_N(IpmPtr P, int64_t N, int op, double mu) {
+    const int64_t i = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
+    if (i >= N) return;
+    const bool v = P.vis[i] != 0;
+    if (op == 0) {
+        P.u[i] = v ? 0.5 * mu : 0.0;
+    } else if (op == 1) {
+        const double sg = v ? 0.5 * (mu - P.mvN[i]) : 0.0;
+        P.xs[i] = sg;
+        P.sc[i] = v ? P.mvN[i] + sg - mu : 0.0;
+    } else if (op == 2) {
+        const double vc = v ? P.mvN[i] + P.pen[i] : 0.0;
+        P.rhs[i] = vc;
+        P.u[i] = 0.5 * vc;
+    } else if (op == 3) {
+        const double y = v ? 0.5 * (P.rhs[i] - P.mvN[i]) : 0.0;
+        P.yc[i] = y;
+        P.zs[i] = v ? P.pen[i] - y : 0.0;
+    } else {
+        P.dtil[i] = v ? 0.5 : 0.0;
+    }
+}
+//  K ops: 0 t~ = mvK + a (then solved in place); 1 dt0 = mvK + a;
+//  2 [mvK2 = E y~] z_t~ = 1 - mvK2 + a; 3 dt1 = 1, tht = 1.
+__global__ void k_st_K(IpmPtr P, int64_t K, int op, double a) {
+    const int64_t k = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
+    if (k >= K) return;
+    if (op == 0)
+        P.xt[k] = P.mvK[k] + a;
+    else if (op == 1)
+        P.dt[0][k] = P.mvK[k] + a;
+    else if (op == 2)
+        P.zt[k] = 1.0 - P.mvK2[k] + a;
+    else {
+        P.dt[1][k] = 1.0;
+        P.tht[k] = 1.0;
+    }
+}
+// x += dx on (t, sigma, s_c), z += dz on (z_t, z_sigma, y_c)
+__global__ void k_st_shift(IpmPtr P, int64_t K, int64_t N, double dx, double dz) {
+    const int64_t j = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
+    if (j < K) {
+        P.xt[j] += dx;
+        P.zt[j] += dz;
+    }
+    if (j < N && P.vis[j]) {
+        P.xs[j] += dx;
+        P.sc[j] += dx;
+        P.zs[j] += dz;
+        P.yc[j] += dz;
+    }
+}
+
+__global__ void k_ipm_output(IpmPtr P, int64_t K, int64_t N, double mu, double* __restrict__ t_out,
+                             double* __restrict__ s_out) {
+    const int64_t j = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
+    if (t_out && j < K) t_out[j] = fmax(P.xt[j], 0.0);
+    if (s_out && j < N) s_out[j] = P.vis[j] ? fmax(P.xs[j], 0.0) : mu;
+}
+
+// Largest diagonal entry of M (one workgroup), stored at S[S_REG].
+__global__ __launch_bounds__(LP_TB) void k_diag_max(const double* __restrict__ M, int64_t K, double* __restrict__ S) {
+    __shared__ double red[LP_TB];
+    double a = 0.0;
+    for (int64_t k = threadIdx.x; k < K; k += LP_TB) a = fmax(a, M[k * K + k]);
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = LP_TB / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) S[S_REG] = red[0];
+}
+
+// diag(M) += rel * S[S_REG]
+__global__ void k_diag_reg(double* __restrict__ M, int64_t K, const double* __restrict__ S, double rel) {
+    const int64_t k = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
+    if (k < K) M[k * K + k] += rel * S[S_REG];
+}
+
+// M (lower) = sum over splits of the partial products
+__global__ void k_sum_splits(const double* __restrict__ part, int splits, int64_t K, double* __restrict__ M) {
+    const int64_t a = blockIdx.y;
+    const int64_t b = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
+    if (a >= K || b > a) return;
+    double v = 0.0;
+    for (int s = 0; s < splits; ++s) v += part[(int64_t)s * K * K + a * K + b];
+    M[a * K + b] = v;
+}
+
 // ------------------------------------------------------------------ host
-struct LpDev {
-    hipStream_t st;
-    int64_t K, N, chunks, rows_per;
-    const float* E;
-    double *vecK = nullptr, *vecN = nullptr, *outN = nullptr, *outK = nullptr, *part = nullptr, *M = nullptr;
-    int* fail = nullptr;
+struct LpWork {
     std::vector<void*> owned;
     template <class T>
     uvc_status alloc(T** p, size_t count, const char* what) {
@@ -403,111 +811,71 @@ struct LpDev {
         owned.push_back(*p);
         return UVC_OK;
     }
-    ~LpDev() {
+    ~LpWork() {
         for (void* p : owned) (void)hipFree(p);
     }
-    // out[i] = sum_k E[k,i] u[k]
-    uvc_status Etu(const std::vector<double>& u, std::vector<double>& out) {
-        UVC_HIP(hipMemcpyAsync(vecK, u.data(), (size_t)K * 8, hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_lp_Etu, dim3(nblk(N), (unsigned)chunks), dim3(LP_TB), 0, st, E, K, N, rows_per, vecK,
-                           part);
-        hipLaunchKernelGGL(k_lp_sum_parts, dim3(nblk(N)), dim3(LP_TB), 0, st, part, chunks, N, outN);
-        out.resize((size_t)N);
-        UVC_HIP(hipMemcpyAsync(out.data(), outN, (size_t)N * 8, hipMemcpyDeviceToHost, st));
-        UVC_HIP(hipStreamSynchronize(st));
-        return UVC_OK;
-    }
-    // out[k] = sum_i E[k,i] v[i]
-    uvc_status Ev(const std::vector<double>& v, std::vector<double>& out) {
-        UVC_HIP(hipMemcpyAsync(vecN, v.data(), (size_t)N * 8, hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_lp_Ev, dim3((unsigned)K), dim3(LP_TB), 0, st, E, N, vecN, outK);
-        out.resize((size_t)K);
-        UVC_HIP(hipMemcpyAsync(out.data(), outK, (size_t)K * 8, hipMemcpyDeviceToHost, st));
-        UVC_HIP(hipStreamSynchronize(st));
-        return UVC_OK;
-    }
-    // M = E diag(d) E^T + db + diag(th) + reg, then Cholesky in place
-    uvc_status factor(const std::vector<double>& d, double db, const std::vector<double>& th, bool& ok) {
-        UVC_HIP(hipMemcpyAsync(vecN, d.data(), (size_t)N * 8, hipMemcpyHostToDevice, st));
-        UVC_HIP(hipMemcpyAsync(vecK, th.data(), (size_t)K * 8, hipMemcpyHostToDevice, st));
-        const int64_t T = (K + SY_T - 1) / SY_T;
-        hipLaunchKernelGGL(k_syrk, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, st, E, K, N, vecN, M);
-        // regularisation relative to the largest diagonal entry
-        double dmax = 0.0;
-        for (double v : th) dmax = std::max(dmax, v);
-        hipLaunchKernelGGL(k_mat_finish, dim3(nblk(K), (unsigned)K), dim3(LP_TB), 0, st, M, K, db, vecK, 0.0);
-        // diagonal maximum of M for the regulariser
-        std::vector<double> diag((size_t)K);
-        hipLaunchKernelGGL(k_get_diag, dim3(nblk(K)), dim3(LP_TB), 0, st, M, K, outK);
-        UVC_HIP(hipMemcpyAsync(diag.data(), outK, (size_t)K * 8, hipMemcpyDeviceToHost, st));
-        UVC_HIP(hipStreamSynchronize(st));
-        for (double v : diag) dmax = std::max(dmax, v);
-        std::vector<double> regv((size_t)K, 1e-13 * dmax);
-        UVC_HIP(hipMemcpyAsync(vecK, regv.data(), (size_t)K * 8, hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_mat_finish, dim3(nblk(K), (unsigned)K), dim3(LP_TB), 0, st, M, K, 0.0, vecK, 0.0);
-        UVC_HIP(hipMemsetAsync(fail, 0, 4, st));
-        for (int64_t j0 = 0; j0 < K; j0 += CH_B) {
-            const int nb = (int)std::min<int64_t>(CH_B, K - j0);
-            hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, M, K, j0, nb, fail);
-            const int64_t rest = K - j0 - nb;
-            if (rest > 0) {
-                hipLaunchKernelGGL(k_chol_trsm, dim3((unsigned)((rest + 255) / 256)), dim3(256), 0, st, M, K, j0, nb);
-                const int64_t T2 = (rest + SY_T - 1) / SY_T;
-                hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(T2 * (T2 + 1) / 2)), dim3(256), 0, st, M, K, j0,
-                                   nb);
-            }
-        }
-        UVC_HIP(hipGetLastError());
-        int f = 0;
-        UVC_HIP(hipMemcpyAsync(&f, fail, 4, hipMemcpyDeviceToHost, st));
-        UVC_HIP(hipStreamSynchronize(st));
-        ok = (f == 0);
-        return UVC_OK;
-    }
-    uvc_status solve(std::vector<double>& r) {
-        UVC_HIP(hipMemcpyAsync(vecK, r.data(), (size_t)K * 8, hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), 0, st, M, K, vecK);
-        UVC_HIP(hipMemcpyAsync(r.data(), vecK, (size_t)K * 8, hipMemcpyDeviceToHost, st));
-        UVC_HIP(hipStreamSynchronize(st));
-        return UVC_OK;
-    }
 };
-
-static double norm2(const std::vector<double>& v) {
-    double s = 0.0;
-    for (double x : v) s += x * x;
-    return std::sqrt(s);
-}
 
 static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* pen_dev, double mu, double tmax,
                             double tol, int32_t max_iter, double* t_out, double* s_out, uvc_lp_info* info,
                             hipStream_t st) {
     if ((double)K * (double)K * 8.0 > 64e9) return fail(UVC_EUNSUPPORTED, "K too large for the dense normal matrix");
-    LpDev D;
-    D.st = st;
-    D.K = K;
-    D.N = N;
-    D.E = E;
-    D.rows_per = std::max<int64_t>(64, (K + 15) / 16);
-    D.chunks = (K + D.rows_per - 1) / D.rows_per;
+    LpWork W;
+    const int64_t rows_per = std::max<int64_t>(64, (K + 15) / 16);
+    const int64_t chunks = (K + rows_per - 1) / rows_per;
+    // SYRK split over N: enough workgroups for the chip, bounded scratch
+    const int64_t T = (K + SY_T - 1) / SY_T, tiles = T * (T + 1) / 2;
+    int splits = (int)std::min<int64_t>(64, std::max<int64_t>(1, (1024 + tiles - 1) / tiles));
+    while (splits > 1 && ((double)splits * K * K * 8.0 > 512e6 || N / splits < 4 * SY_KC)) --splits;
     float *cmax_part = nullptr, *cmax = nullptr;
-    double *sq_part = nullptr, *sq = nullptr;
-    UVC_TRY(D.alloc(&cmax_part, (size_t)D.chunks * N, "lp colmax"));
-    UVC_TRY(D.alloc(&cmax, N, "lp colmax"));
-    UVC_TRY(D.alloc(&sq_part, (size_t)D.chunks * N, "lp norm"));
-    UVC_TRY(D.alloc(&sq, N, "lp norm"));
-    UVC_TRY(D.alloc(&D.vecK, K, "lp vec"));
-    UVC_TRY(D.alloc(&D.vecN, N, "lp vec"));
-    UVC_TRY(D.alloc(&D.outN, N, "lp vec"));
-    UVC_TRY(D.alloc(&D.outK, K, "lp vec"));
-    UVC_TRY(D.alloc(&D.part, (size_t)D.chunks * N, "lp partial sums"));
-    UVC_TRY(D.alloc(&D.M, (size_t)K * K, "lp normal matrix"));
-    UVC_TRY(D.alloc(&D.fail, 1, "lp flag"));
+    double *sq_part = nullptr, *sq = nullptr, *part = nullptr, *M = nullptr, *Mpart = nullptr, *rpart = nullptr;
+    unsigned char* vis_d = nullptr;
+    int* failf = nullptr;
+    UVC_TRY(W.alloc(&cmax_part, (size_t)chunks * N, "lp colmax"));
+    UVC_TRY(W.alloc(&cmax, N, "lp colmax"));
+    UVC_TRY(W.alloc(&sq_part, (size_t)chunks * N, "lp norm"));
+    UVC_TRY(W.alloc(&sq, N, "lp norm"));
+    UVC_TRY(W.alloc(&part, (size_t)chunks * N, "lp partial sums"));
+    UVC_TRY(W.alloc(&M, (size_t)K * K, "lp normal matrix"));
+    if (splits > 1) UVC_TRY(W.alloc(&Mpart, (size_t)splits * K * K, "lp normal matrix partials"));
+    UVC_TRY(W.alloc(&vis_d, N, "lp visibility"));
+    UVC_TRY(W.alloc(&failf, 1, "lp flag"));
+    const int RB = 512;  // reduction workgroups
+    UVC_TRY(W.alloc(&rpart, (size_t)RB * IPM_SUMS, "lp reduction partials"));
+    IpmPtr P{};
+    double** kvec[] = {&P.xt, &P.zt, &P.rdt, &P.tht, &P.mvK, &P.mvK2, &P.dt[0], &P.dt[1], &P.dzt[0], &P.dzt[1]};
+    for (double** p : kvec) UVC_TRY(W.alloc(p, K, "lp pose vector"));
+    double** nvec[] = {&P.xs,     &P.zs,     &P.yc,     &P.sc,     &P.pen,    &P.rpc,   &P.rds,
+                       &P.drc,    &P.ths,    &P.dtil,   &P.rhs,    &P.rpp,    &P.mvN,   &P.u,
+                       &P.dsig[0], &P.dsig[1], &P.dzs[0], &P.dzs[1], &P.dyc[0], &P.dyc[1], &P.dsc[0],
+                       &P.dsc[1]};
+    for (double** p : nvec) UVC_TRY(W.alloc(p, N, "lp element vector"));
+    UVC_TRY(W.alloc(&P.S, 16, "lp scalars"));
+    P.vis = vis_d;
 
-    hipLaunchKernelGGL(k_lp_colstats, dim3(nblk(N), (unsigned)D.chunks), dim3(LP_TB), 0, st, E, K, N, D.rows_per,
+    auto Etu = [&](const double* u, double* out) {  // out[i] = sum_k E[k,i] u[k]
+        hipLaunchKernelGGL(k_lp_Etu, dim3(nblk(N), (unsigned)chunks), dim3(LP_TB), 0, st, E, K, N, rows_per, u, part);
+        hipLaunchKernelGGL(k_lp_sum_parts, dim3(nblk(N)), dim3(LP_TB), 0, st, part, chunks, N, out);
+    };
+    auto Ev = [&](const double* v, double* out) {  // out[k] = sum_i E[k,i] v[i]
+        hipLaunchKernelGGL(k_lp_Ev, dim3((unsigned)K), dim3(LP_TB), 0, st, E, N, v, out);
+    };
+    double red[IPM_SUMS];
+    auto reduce = [&](int job, int d, double ap, double ad) -> uvc_status {
+        hipLaunchKernelGGL(k_ipm_reduce, dim3(RB), dim3(LP_TB), 0, st, P, K, N, job, d, ap, ad, rpart);
+        hipLaunchKernelGGL(k_ipm_reduce2, dim3(1), dim3(512), 0, st, rpart, RB, (job == 1 || job == 6) ? 1 : 0,
+                           P.S + S_RED);
+        UVC_HIP(hipGetLastError());
+        UVC_HIP(hipMemcpyAsync(red, P.S + S_RED, sizeof(red), hipMemcpyDeviceToHost, st));
+        UVC_HIP(hipStreamSynchronize(st));
+        return UVC_OK;
+    };
+
+    // column statistics: visibility, ||E||_F, finiteness
+    hipLaunchKernelGGL(k_lp_colstats, dim3(nblk(N), (unsigned)chunks), dim3(LP_TB), 0, st, E, K, N, rows_per,
                        cmax_part, sq_part);
-    hipLaunchKernelGGL(k_lp_max_parts, dim3(nblk(N)), dim3(LP_TB), 0, st, cmax_part, D.chunks, N, cmax);
-    hipLaunchKernelGGL(k_lp_sum_parts, dim3(nblk(N)), dim3(LP_TB), 0, st, sq_part, D.chunks, N, sq);
+    hipLaunchKernelGGL(k_lp_max_parts, dim3(nblk(N)), dim3(LP_TB), 0, st, cmax_part, chunks, N, cmax);
+    hipLaunchKernelGGL(k_lp_sum_parts, dim3(nblk(N)), dim3(LP_TB), 0, st, sq_part, chunks, N, sq);
     std::vector<float> hcmax((size_t)N);
     std::vector<double> hsq((size_t)N);
     UVC_HIP(hipMemcpyAsync(hcmax.data(), cmax, (size_t)N * 4, hipMemcpyDeviceToHost, st));
@@ -522,207 +890,211 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
         nvis += vis[(size_t)i];
         fro2 += hsq[(size_t)i];
     }
-    std::vector<double> pen((size_t)N, 1.001 * std::sqrt(fro2));
+    const double pdef = 1.001 * std::sqrt(fro2);
+    double p0 = pdef;
     if (pen_dev) {
-        UVC_HIP(hipMemcpyAsync(pen.data(), pen_dev, (size_t)N * 8, hipMemcpyDeviceToHost, st));
+        std::vector<double> hp((size_t)N);
+        UVC_HIP(hipMemcpyAsync(hp.data(), pen_dev, (size_t)N * 8, hipMemcpyDeviceToHost, st));
         UVC_HIP(hipStreamSynchronize(st));
+        for (int64_t i = 0; i < N; ++i)
+            if (vis[(size_t)i] && !(std::isfinite(hp[(size_t)i]) && hp[(size_t)i] >= 0.0))
+                return fail(UVC_EINVAL, "penalty must be finite and >= 0");
+        p0 = hp[0];
     }
-    std::vector<double> t((size_t)K, 0.0), sg((size_t)N, mu);
+    UVC_HIP(hipMemcpyAsync(vis_d, vis.data(), (size_t)N, hipMemcpyHostToDevice, st));
+
     double obj = 0.0, pres = 0.0, dres = 0.0, rgap = 0.0;
     int32_t it = 0;
     bool converged = nvis == 0;
+    const unsigned gK = nblk(K), gN = nblk(N), gKN = nblk(std::max(K, N));
     if (nvis > 0) {
-        // variables over all N columns; invisible elements are held out (their
-        // sigma is fixed at mu, their rows and columns carry no weight)
-        const int64_t n = K + N, m = N + 1;
-        std::vector<double> c((size_t)n, 0.0), h((size_t)m, 0.0);
-        for (int64_t k = 0; k < K; ++k) c[(size_t)k] = 1.0;
-        for (int64_t i = 0; i < N; ++i) {
-            c[(size_t)(K + i)] = vis[(size_t)i] ? pen[(size_t)i] : 0.0;
-            h[(size_t)i] = vis[(size_t)i] ? mu : 0.0;
+        // starting point and norms of h and c
+        double pmax = pdef;
+        double psq = 0.0;
+        if (pen_dev) {
+            hipLaunchKernelGGL(k_ipm_init, dim3(gKN), dim3(LP_TB), 0, st, P, K, N, 0.0, pdef, pen_dev, mu);
+            UVC_TRY(reduce(4, 0, 0.0, 0.0));
+            psq = red[0];
+            std::vector<double> hp((size_t)N);
+            UVC_HIP(hipMemcpyAsync(hp.data(), P.pen, (size_t)N * 8, hipMemcpyDeviceToHost, st));
+            UVC_HIP(hipStreamSynchronize(st));
+            pmax = 0.0;
+            for (double v : hp) pmax = std::max(pmax, v);
+        } else {
+            psq = (double)nvis * pdef * pdef;
         }
-        h[(size_t)N] = -tmax;
-        double cmaxv = 0.0;
-        for (double v : c) cmaxv = std::max(cmaxv, std::fabs(v));
-        const double sc0 = std::max(1.0, std::max(mu, std::sqrt(cmaxv)));
-        std::vector<double> x((size_t)n, sc0), z((size_t)n, sc0), s((size_t)m, sc0), y((size_t)m, 1.0);
-        for (int64_t i = 0; i < N; ++i)
-            if (!vis[(size_t)i]) {
-                x[(size_t)(K + i)] = 0.0;
-                z[(size_t)(K + i)] = 0.0;
-                s[(size_t)i] = 0.0;
-                y[(size_t)i] = 0.0;
+        const double x0 = std::max(1.0, std::max(mu, std::sqrt(std::max(1.0, pmax))));
+        hipLaunchKernelGGL(k_ipm_init, dim3(gKN), dim3(LP_TB), 0, st, P, K, N, x0, pdef, pen_dev, mu);
+        UVC_HIP(hipGetLastError());
+        // M = E diag(dtil) E^T + Db 1 1^T + diag(tht), regularised, then its Cholesky factor in place
+        auto factor = [&](double Db) -> uvc_status {
+            if (splits > 1) {
+                hipLaunchKernelGGL(k_syrk, dim3((unsigned)tiles, (unsigned)splits), dim3(256), 0, st, E, K, N, P.dtil,
+                                   Mpart, splits);
+                hipLaunchKernelGGL(k_sum_splits, dim3(nblk(K), (unsigned)K), dim3(LP_TB), 0, st, Mpart, splits, K, M);
+            } else {
+                hipLaunchKernelGGL(k_syrk, dim3((unsigned)tiles, 1u), dim3(256), 0, st, E, K, N, P.dtil, M, 1);
             }
-        const double hn = norm2(h), cn = norm2(c);
-        std::vector<double> Etmp, Evt;
-        // G x = (E^T t + sigma, -sum t)
-        auto Gx = [&](const std::vector<double>& xx, std::vector<double>& out) -> uvc_status {
-            std::vector<double> tt(xx.begin(), xx.begin() + K);
-            UVC_TRY(D.Etu(tt, Etmp));
-            out.assign((size_t)m, 0.0);
-            double st_ = 0.0;
-            for (int64_t k = 0; k < K; ++k) st_ += tt[(size_t)k];
-            for (int64_t i = 0; i < N; ++i) out[(size_t)i] = vis[(size_t)i] ? Etmp[(size_t)i] + xx[(size_t)(K + i)] : 0.0;
-            out[(size_t)N] = -st_;
+            hipLaunchKernelGGL(k_mat_finish, dim3(nblk(K), (unsigned)K), dim3(LP_TB), 0, st, M, K, Db, P.tht, 0.0);
+            hipLaunchKernelGGL(k_diag_max, dim3(1), dim3(LP_TB), 0, st, M, K, P.S);
+            hipLaunchKernelGGL(k_diag_reg, dim3(gK), dim3(LP_TB), 0, st, M, K, P.S, 1e-13);
+            UVC_HIP(hipMemsetAsync(failf, 0, 4, st));
+            for (int64_t j0 = 0; j0 < K; j0 += CH_B) {
+                const int nb = (int)std::min<int64_t>(CH_B, K - j0);
+                hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, M, K, j0, nb, failf);
+                const int64_t rest = K - j0 - nb;
+                if (rest > 0) {
+                    hipLaunchKernelGGL(k_chol_trsm, dim3((unsigned)((rest + 255) / 256)), dim3(256), 0, st, M, K, j0,
+                                       nb);
+                    const int64_t T2 = (rest + SY_T - 1) / SY_T;
+                    hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(T2 * (T2 + 1) / 2)), dim3(256), 0, st, M, K,
+                                       j0, nb);
+                }
+            }
+            UVC_HIP(hipGetLastError());
             return UVC_OK;
         };
-        // G^T y = (E y_c - y_b, y_c)
-        auto GTy = [&](const std::vector<double>& yy, std::vector<double>& out) -> uvc_status {
-            std::vector<double> yc((size_t)N);
-            for (int64_t i = 0; i < N; ++i) yc[(size_t)i] = vis[(size_t)i] ? yy[(size_t)i] : 0.0;
-            UVC_TRY(D.Ev(yc, Evt));
-            out.assign((size_t)n, 0.0);
-            for (int64_t k = 0; k < K; ++k) out[(size_t)k] = Evt[(size_t)k] - yy[(size_t)N];
-            for (int64_t i = 0; i < N; ++i) out[(size_t)(K + i)] = yc[(size_t)i];
-            return UVC_OK;
-        };
-        std::vector<double> gx, gty, rp((size_t)m), rd((size_t)n);
+        double sb = x0, yb = 1.0;
+        {
+            // Mehrotra's starting point (falls back to the constant point
+            // above if it is not finite or the unit-scaled factor fails)
+            hipLaunchKernelGGL(k_st_N, dim3(gN), dim3(LP_TB), 0, st, P, N, 4, mu);
+            hipLaunchKernelGGL(k_st_K, dim3(gK), dim3(LP_TB), 0, st, P, K, 3, 0.0);
+            UVC_TRY(factor(1.0));
+            hipLaunchKernelGGL(k_st_N, dim3(gN), dim3(LP_TB), 0, st, P, N, 0, mu);
+            Ev(P.u, P.mvK);
+            hipLaunchKernelGGL(k_st_K, dim3(gK), dim3(LP_TB), 0, st, P, K, 0, tmax);
+            hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), 0, st, M, K, P.xt);
+            Etu(P.xt, P.mvN);
+            hipLaunchKernelGGL(k_st_N, dim3(gN), dim3(LP_TB), 0, st, P, N, 1, mu);
+            Etu(P.dt[1], P.mvN);
+            hipLaunchKernelGGL(k_st_N, dim3(gN), dim3(LP_TB), 0, st, P, N, 2, mu);
+            Ev(P.u, P.mvK);
+            hipLaunchKernelGGL(k_st_K, dim3(gK), dim3(LP_TB), 0, st, P, K, 1, (double)K);
+            hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), 0, st, M, K, P.dt[0]);
+            Etu(P.dt[0], P.mvN);
+            hipLaunchKernelGGL(k_st_N, dim3(gN), dim3(LP_TB), 0, st, P, N, 3, mu);
+            UVC_TRY(reduce(5, 0, 0.0, 0.0));
+            const double yb0 = -(double)K + red[0];
+            double sumt = 0.0;
+            {
+                // sum of t~: dt[1] is free again
+                UVC_HIP(hipMemcpyAsync(P.dt[1], P.xt, (size_t)K * 8, hipMemcpyDeviceToDevice, st));
+                UVC_TRY(reduce(5, 1, 0.0, 0.0));
+                sumt = red[0];
+            }
+            const double sb0 = tmax - sumt;
+            Ev(P.yc, P.mvK2);
+            hipLaunchKernelGGL(k_st_K, dim3(gK), dim3(LP_TB), 0, st, P, K, 2, yb0);
+            int f = 0;
+            UVC_HIP(hipMemcpyAsync(&f, failf, 4, hipMemcpyDeviceToHost, st));
+            UVC_TRY(reduce(6, 0, 0.0, 0.0));
+            const double dx = std::max(-1.5 * std::min(red[0], sb0), 0.0);
+            const double dz = std::max(-1.5 * std::min(red[1], yb0), 0.0);
+            hipLaunchKernelGGL(k_st_shift, dim3(gKN), dim3(LP_TB), 0, st, P, K, N, dx, dz);
+            double sb1 = sb0 + dx, yb1 = yb0 + dz;
+            UVC_TRY(reduce(7, 0, 0.0, 0.0));
+            const double xz = red[0] + sb1 * yb1, sz = red[1] + yb1, sx = red[2] + sb1;
+            const double dx2 = 0.5 * xz / sz, dz2 = 0.5 * xz / sx;
+            const bool good = f == 0 && std::isfinite(dx2) && std::isfinite(dz2) && std::isfinite(xz) &&
+                              sb1 + dx2 > 0.0 && yb1 + dz2 > 0.0 && dx + dx2 > 0.0 && dz + dz2 > 0.0;
+            if (good) {
+                hipLaunchKernelGGL(k_st_shift, dim3(gKN), dim3(LP_TB), 0, st, P, K, N, dx2, dz2);
+                sb = sb1 + dx2;
+                yb = yb1 + dz2;
+            } else {
+                hipLaunchKernelGGL(k_ipm_init, dim3(gKN), dim3(LP_TB), 0, st, P, K, N, x0, pdef, pen_dev, mu);
+            }
+            UVC_HIP(hipGetLastError());
+        }
+        const double hn = std::sqrt((double)nvis * mu * mu + tmax * tmax);
+        const double cn = std::sqrt((double)K + psq);
+        const double ncomp = (double)(nvis * 2 + K + 1);
         for (it = 0; it < max_iter; ++it) {
-            UVC_TRY(Gx(x, gx));
-            UVC_TRY(GTy(y, gty));
-            double gap = 0.0;
-            for (int64_t j = 0; j < n; ++j) {
-                rd[(size_t)j] = (j >= K && !vis[(size_t)(j - K)]) ? 0.0 : c[(size_t)j] - gty[(size_t)j] - z[(size_t)j];
-                gap += x[(size_t)j] * z[(size_t)j];
-            }
-            for (int64_t i = 0; i < m; ++i) {
-                rp[(size_t)i] = (i < N && !vis[(size_t)i]) ? 0.0 : h[(size_t)i] - gx[(size_t)i] + s[(size_t)i];
-                gap += s[(size_t)i] * y[(size_t)i];
-            }
-            const double muc = gap / (double)(nvis * 2 + K + 1);
-            double po = 0.0, dob = 0.0;
-            for (int64_t j = 0; j < n; ++j) po += c[(size_t)j] * x[(size_t)j];
-            for (int64_t i = 0; i < m; ++i) dob += h[(size_t)i] * y[(size_t)i];
-            pres = norm2(rp) / (1.0 + hn);
-            dres = norm2(rd) / (1.0 + cn);
+            // residuals and convergence
+            Etu(P.xt, P.mvN);
+            Ev(P.yc, P.mvK);
+            hipLaunchKernelGGL(k_ipm_resid_N, dim3(gN), dim3(LP_TB), 0, st, P, N, mu);
+            hipLaunchKernelGGL(k_ipm_resid_K, dim3(gK), dim3(LP_TB), 0, st, P, K, yb);
+            UVC_TRY(reduce(0, 0, 0.0, 0.0));
+            const double sum_t = red[0];
+            const double rpb = -tmax + sum_t + sb;
+            const double gap = red[1] + sb * yb;
+            const double po = sum_t + red[2];
+            const double dob = mu * red[3] - tmax * yb;
+            pres = std::sqrt(red[4] + rpb * rpb) / (1.0 + hn);
+            dres = std::sqrt(red[5]) / (1.0 + cn);
             rgap = std::fabs(po - dob) / (1.0 + std::fabs(po) + std::fabs(dob));
             obj = po;
             if (std::max(pres, std::max(dres, rgap)) <= tol) {
                 converged = true;
                 break;
             }
-            // normal matrix
-            std::vector<double> Dr((size_t)m, 0.0), Th((size_t)n, 0.0), dt_((size_t)N, 0.0), tht((size_t)K);
-            for (int64_t i = 0; i < m; ++i)
-                if (!(i < N && !vis[(size_t)i])) Dr[(size_t)i] = y[(size_t)i] / s[(size_t)i];
-            for (int64_t j = 0; j < n; ++j)
-                if (!(j >= K && !vis[(size_t)(j - K)])) Th[(size_t)j] = z[(size_t)j] / x[(size_t)j];
-            for (int64_t i = 0; i < N; ++i)
-                if (vis[(size_t)i]) {
-                    const double a = Dr[(size_t)i], b = Th[(size_t)(K + i)];
-                    dt_[(size_t)i] = a * b / (a + b);
-                }
-            for (int64_t k = 0; k < K; ++k) tht[(size_t)k] = Th[(size_t)k];
-            bool ok = true;
-            UVC_TRY(D.factor(dt_, Dr[(size_t)N], tht, ok));
-            if (!ok) break;
-            // solve for a direction given complementarity right-hand sides
-            auto direction = [&](const std::vector<double>& rxz, const std::vector<double>& rsy, std::vector<double>& dx,
-                                 std::vector<double>& dy, std::vector<double>& dz,
-                                 std::vector<double>& ds) -> uvc_status {
-                std::vector<double> rpp((size_t)m), wv((size_t)m), rhs;
-                for (int64_t i = 0; i < m; ++i) {
-                    const bool live = !(i < N && !vis[(size_t)i]);
-                    rpp[(size_t)i] = live ? rp[(size_t)i] + rsy[(size_t)i] / y[(size_t)i] : 0.0;
-                    wv[(size_t)i] = Dr[(size_t)i] * rpp[(size_t)i];
-                }
-                UVC_TRY(GTy(wv, rhs));
-                for (int64_t j = 0; j < n; ++j) {
-                    const bool live = !(j >= K && !vis[(size_t)(j - K)]);
-                    rhs[(size_t)j] = live ? rhs[(size_t)j] - rd[(size_t)j] + rxz[(size_t)j] / x[(size_t)j] : 0.0;
-                }
-                // eliminate sigma: rt2 = rt - E (Dc/(Dc+Ts) * rs)
-                std::vector<double> q((size_t)N, 0.0), eq;
-                for (int64_t i = 0; i < N; ++i)
-                    if (vis[(size_t)i]) {
-                        const double a = Dr[(size_t)i], b = Th[(size_t)(K + i)];
-                        q[(size_t)i] = a / (a + b) * rhs[(size_t)(K + i)];
-                    }
-                UVC_TRY(D.Ev(q, eq));
-                std::vector<double> dtv((size_t)K);
-                for (int64_t k = 0; k < K; ++k) dtv[(size_t)k] = rhs[(size_t)k] - eq[(size_t)k];
-                UVC_TRY(D.solve(dtv));
-                std::vector<double> etd;
-                UVC_TRY(D.Etu(dtv, etd));
-                dx.assign((size_t)n, 0.0);
-                for (int64_t k = 0; k < K; ++k) dx[(size_t)k] = dtv[(size_t)k];
-                for (int64_t i = 0; i < N; ++i)
-                    if (vis[(size_t)i]) {
-                        const double a = Dr[(size_t)i], b = Th[(size_t)(K + i)];
-                        dx[(size_t)(K + i)] = (rhs[(size_t)(K + i)] - a * etd[(size_t)i]) / (a + b);
-                    }
-                // G dx without another E^T pass: (E^T dt + dsigma, -sum dt)
-                std::vector<double> gdx((size_t)m, 0.0);
-                double sdt = 0.0;
-                for (int64_t k = 0; k < K; ++k) sdt += dtv[(size_t)k];
-                for (int64_t i = 0; i < N; ++i)
-                    if (vis[(size_t)i]) gdx[(size_t)i] = etd[(size_t)i] + dx[(size_t)(K + i)];
-                gdx[(size_t)N] = -sdt;
-                dy.assign((size_t)m, 0.0);
-                ds.assign((size_t)m, 0.0);
-                for (int64_t i = 0; i < m; ++i)
-                    if (!(i < N && !vis[(size_t)i])) {
-                        dy[(size_t)i] = Dr[(size_t)i] * (rpp[(size_t)i] - gdx[(size_t)i]);
-                        ds[(size_t)i] = (rsy[(size_t)i] - s[(size_t)i] * dy[(size_t)i]) / y[(size_t)i];
-                    }
-                // dz from dual feasibility (G^T dy + dz = rd), which keeps the
-                // dual residual from drifting when the normal matrix is
-                // ill-conditioned near the optimum
-                std::vector<double> gtdy;
-                UVC_TRY(GTy(dy, gtdy));
-                dz.assign((size_t)n, 0.0);
-                for (int64_t j = 0; j < n; ++j)
-                    if (!(j >= K && !vis[(size_t)(j - K)])) dz[(size_t)j] = rd[(size_t)j] - gtdy[(size_t)j];
+            const double muc = gap / ncomp;
+            // normal matrix M = E diag(dtil) E^T + D_b 1 1^T + diag(theta_t), regularised, and its factor
+            const double Db = yb / sb;
+            hipLaunchKernelGGL(k_ipm_scale, dim3(gKN), dim3(LP_TB), 0, st, P, K, N);
+            UVC_TRY(factor(Db));
+            // one Newton direction into slot d (mode 0 predictor, 1 corrector)
+            auto direction = [&](int mode, int d, double sigmu, double rsyb) {
+                const double rppb = rpb + rsyb / yb;
+                const double wvb = Db * rppb;
+                hipLaunchKernelGGL(k_dir_a, dim3(gN), dim3(LP_TB), 0, st, P, N, mode, sigmu);
+                Ev(P.u, P.mvK);
+                hipLaunchKernelGGL(k_dir_b, dim3(gK), dim3(LP_TB), 0, st, P, K, mode, sigmu, wvb, d);
+                hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), 0, st, M, K, P.dt[d]);
+                Etu(P.dt[d], P.mvN);
+                hipLaunchKernelGGL(k_ipm_bscal, dim3(1), dim3(LP_TB), 0, st, P, K, d, Db, rppb, rsyb, sb, yb);
+                hipLaunchKernelGGL(k_dir_c, dim3(gN), dim3(LP_TB), 0, st, P, N, mode, sigmu, d);
+                Ev(P.dyc[d], P.mvK2);
+                hipLaunchKernelGGL(k_dir_d, dim3(gK), dim3(LP_TB), 0, st, P, K, d);
+            };
+            auto steps = [&](int d, double& ap, double& ad, double& dyb, double& dsb) -> uvc_status {
+                UVC_TRY(reduce(1, d, 0.0, 0.0));
+                double sc3[3];
+                UVC_HIP(hipMemcpyAsync(sc3, P.S + 3 * d, sizeof(sc3), hipMemcpyDeviceToHost, st));
+                UVC_HIP(hipStreamSynchronize(st));
+                dyb = sc3[1];
+                dsb = sc3[2];
+                ap = std::min(1.0, red[0]);
+                ad = std::min(1.0, red[1]);
+                if (dsb < 0.0 && sb > 0.0) ap = std::min(ap, -sb / dsb);
+                if (dyb < 0.0 && yb > 0.0) ad = std::min(ad, -yb / dyb);
                 return UVC_OK;
             };
-            auto maxstep = [](const std::vector<double>& v, const std::vector<double>& dv) {
-                double a = 1.0;
-                for (size_t j = 0; j < v.size(); ++j)
-                    if (dv[j] < 0.0 && v[j] > 0.0) a = std::min(a, -v[j] / dv[j]);
-                return a;
-            };
-            std::vector<double> rxz((size_t)n), rsy((size_t)m), dx, dy, dz, ds;
-            for (int64_t j = 0; j < n; ++j) rxz[(size_t)j] = -x[(size_t)j] * z[(size_t)j];
-            for (int64_t i = 0; i < m; ++i) rsy[(size_t)i] = -s[(size_t)i] * y[(size_t)i];
-            UVC_TRY(direction(rxz, rsy, dx, dy, dz, ds));
-            double ap = std::min(maxstep(x, dx), maxstep(s, ds)), ad = std::min(maxstep(z, dz), maxstep(y, dy));
-            double gaff = 0.0;
-            for (int64_t j = 0; j < n; ++j) gaff += (x[(size_t)j] + ap * dx[(size_t)j]) * (z[(size_t)j] + ad * dz[(size_t)j]);
-            for (int64_t i = 0; i < m; ++i) gaff += (s[(size_t)i] + ap * ds[(size_t)i]) * (y[(size_t)i] + ad * dy[(size_t)i]);
+            direction(0, 0, 0.0, -sb * yb);
+            double ap = 1.0, ad = 1.0, dyb0 = 0.0, dsb0 = 0.0;
+            UVC_TRY(steps(0, ap, ad, dyb0, dsb0));
+            int f = 0;
+            UVC_HIP(hipMemcpyAsync(&f, failf, 4, hipMemcpyDeviceToHost, st));
+            UVC_HIP(hipStreamSynchronize(st));
+            if (f != 0) break;
+            UVC_TRY(reduce(2, 0, ap, ad));
+            const double gaff = red[0] + (sb + ap * dsb0) * (yb + ad * dyb0);
             const double sig = std::pow(gaff / std::max(gap, 1e-300), 3.0);
-            for (int64_t j = 0; j < n; ++j) {
-                const bool live = !(j >= K && !vis[(size_t)(j - K)]);
-                rxz[(size_t)j] = live ? sig * muc - x[(size_t)j] * z[(size_t)j] - dx[(size_t)j] * dz[(size_t)j] : 0.0;
-            }
-            for (int64_t i = 0; i < m; ++i) {
-                const bool live = !(i < N && !vis[(size_t)i]);
-                rsy[(size_t)i] = live ? sig * muc - s[(size_t)i] * y[(size_t)i] - ds[(size_t)i] * dy[(size_t)i] : 0.0;
-            }
-            UVC_TRY(direction(rxz, rsy, dx, dy, dz, ds));
-            ap = 0.99 * std::min(maxstep(x, dx), maxstep(s, ds));
-            ad = 0.99 * std::min(maxstep(z, dz), maxstep(y, dy));
-            for (int64_t j = 0; j < n; ++j) {
-                x[(size_t)j] += ap * dx[(size_t)j];
-                z[(size_t)j] += ad * dz[(size_t)j];
-            }
-            for (int64_t i = 0; i < m; ++i) {
-                s[(size_t)i] += ap * ds[(size_t)i];
-                y[(size_t)i] += ad * dy[(size_t)i];
-            }
+            const double sigmu = sig * muc;
+            direction(1, 1, sigmu, sigmu - sb * yb - dsb0 * dyb0);
+            double dyb1 = 0.0, dsb1 = 0.0;
+            UVC_TRY(steps(1, ap, ad, dyb1, dsb1));
+            ap *= 0.99;
+            ad *= 0.99;
+            hipLaunchKernelGGL(k_ipm_update, dim3(gKN), dim3(LP_TB), 0, st, P, K, N, ap, ad);
+            UVC_HIP(hipGetLastError());
+            sb += ap * dsb1;
+            yb += ad * dyb1;
         }
-        obj = 0.0;
-        for (int64_t k = 0; k < K; ++k) {
-            t[(size_t)k] = std::max(0.0, x[(size_t)k]);
-            obj += t[(size_t)k];
+        UVC_TRY(reduce(3, 0, 0.0, 0.0));
+        obj = red[0] + red[1];
+        hipLaunchKernelGGL(k_ipm_output, dim3(gKN), dim3(LP_TB), 0, st, P, K, N, mu, t_out, s_out);
+    } else {
+        if (t_out) UVC_HIP(hipMemsetAsync(t_out, 0, (size_t)K * 8, st));
+        if (s_out) {
+            std::vector<double> hs((size_t)N, mu);
+            UVC_HIP(hipMemcpyAsync(s_out, hs.data(), (size_t)N * 8, hipMemcpyHostToDevice, st));
+            UVC_HIP(hipStreamSynchronize(st));
         }
-        for (int64_t i = 0; i < N; ++i)
-            if (vis[(size_t)i]) {
-                sg[(size_t)i] = std::max(0.0, x[(size_t)(K + i)]);
-                obj += pen[(size_t)i] * sg[(size_t)i];
-            }
     }
-    if (t_out) UVC_HIP(hipMemcpyAsync(t_out, t.data(), (size_t)K * 8, hipMemcpyHostToDevice, st));
-    if (s_out) UVC_HIP(hipMemcpyAsync(s_out, sg.data(), (size_t)N * 8, hipMemcpyHostToDevice, st));
+    UVC_HIP(hipGetLastError());
     UVC_HIP(hipStreamSynchronize(st));
     if (info) {
         info->objective = obj;
@@ -731,7 +1103,7 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
         info->gap = rgap;
         info->iterations = it;
         info->n_visible = nvis;
-        info->penalty = pen.empty() ? 0.0 : pen[0];
+        info->penalty = p0;
     }
     if (!converged)
         return fail(UVC_ENOTCONV, "LP did not reach tol; residuals " + std::to_string(pres) + " " +

@@ -40,6 +40,40 @@ __global__ void k_colmax(const float* __restrict__ E, int64_t K, int64_t n, floa
     out[j] = m;
 }
 
+// Greedy repair of a pruned plan.  For the check block Ec (K x c) of the
+// uncovered elements, a pose "covers" column j when Ec[k,j] >= alpha *
+// cm[j], cm[j] = the column's largest entry.  counts[k] = number of columns
+// still to cover that pose k covers (0 for poses already kept).
+__global__ __launch_bounds__(256) void k_cover_count(const float* __restrict__ Ec, int64_t c,
+                                                     const float* __restrict__ cm, const uint8_t* __restrict__ todo,
+                                                     const uint8_t* __restrict__ is_kept, float alpha,
+                                                     int32_t* __restrict__ counts) {
+    __shared__ int32_t red[256];
+    const int64_t k = blockIdx.x;
+    int32_t n = 0;
+    if (!is_kept[k])
+        for (int64_t j = threadIdx.x; j < c; j += 256) n += (todo[j] && Ec[k * c + j] >= alpha * cm[j]) ? 1 : 0;
+    red[threadIdx.x] = n;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) counts[k] = red[0];
+}
+
+// todo[j] = coverable[j] initially (mode 0), then cleared where row k of Ec
+// covers column j (mode 1).
+__global__ void k_cover_mark(const float* __restrict__ Ec, int64_t c, int64_t k, const float* __restrict__ cm,
+                             float alpha, float need, int mode, uint8_t* __restrict__ todo) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= c) return;
+    if (mode == 0)
+        todo[j] = cm[j] >= need ? 1 : 0;
+    else if (Ec[k * c + j] >= alpha * cm[j])
+        todo[j] = 0;
+}
+
 // Per column i: a = sum_k E[k,i] t_k (FP64, ascending k), visible = some
 // E[k,i] > 0, shortfall = max(0, mu - a) over visible columns.  Per block:
 // the shortfall sum, the count of shortfalls above short_tol, and the sum of
@@ -95,9 +129,14 @@ unsigned grid_of(int64_t n, int tb) { return (unsigned)((n + tb - 1) / tb); }
 
 struct Dev {
     void* p = nullptr;
-    ~Dev() {
+    Dev() = default;
+    Dev(const Dev&) = delete;
+    Dev& operator=(const Dev&) = delete;
+    void reset() {
         if (p) (void)hipFree(p);
+        p = nullptr;
     }
+    ~Dev() { reset(); }
 };
 
 template <class T>
@@ -127,7 +166,8 @@ using namespace uvc;
 extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses_dev, int64_t K, int32_t pose_dim,
                                       const uvc_lamp* lamp, const uvc_opts* opts, int32_t score_mode,
                                       const float* params_dev, int32_t bf16, float keep_frac, float feature_height,
-                                      double mu_min, double t_max, double tol, int32_t max_iter, double* t_out_dev,
+                                      double mu_min, double t_max, double tol, int32_t max_iter,
+                                      int32_t repair_rounds, double* t_out_dev,
                                       double* sigma_out_dev, int32_t* kept_host, uvc_plan_info* info,
                                       void* hip_stream) {
     if (!scene || !poses_dev || !lamp || !t_out_dev || !sigma_out_dev || !info)
@@ -138,6 +178,7 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
         return fail(UVC_EINVAL, "unknown score_mode");
     if (score_mode == UVC_RANK_MLP && !params_dev) return fail(UVC_EINVAL, "MLP scoring needs params_dev");
     if (!(keep_frac > 0.f && keep_frac <= 1.f)) return fail(UVC_EINVAL, "keep_frac must lie in (0, 1]");
+    if (repair_rounds != 0 && repair_rounds != 1) return fail(UVC_EINVAL, "repair_rounds must be 0 or 1");
     const int64_t N = scene->n;
     if (N < 1) return fail(UVC_EINVAL, "empty scene");
     hipStream_t st = (hipStream_t)hip_stream;
@@ -193,7 +234,7 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
     UVC_HIP(hipStreamSynchronize(st));
     // 2. keep the ceil(keep_frac K) best scores (ties: lower index first),
     // then restore the candidates' own order
-    const int64_t keep = std::min<int64_t>(K, std::max<int64_t>(1, (int64_t)std::ceil((double)keep_frac * (double)K)));
+    const int64_t keep0 = std::min<int64_t>(K, std::max<int64_t>(1, (int64_t)std::ceil((double)keep_frac * (double)K)));
     std::vector<int32_t> order((size_t)K);
     std::iota(order.begin(), order.end(), 0);
     auto better = [&](int32_t a, int32_t b) {
@@ -203,77 +244,153 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
         if (!na && sa != sb) return sa > sb;
         return a < b;
     };
-    std::partial_sort(order.begin(), order.begin() + keep, order.end(), better);
-    std::vector<int32_t> kept(order.begin(), order.begin() + keep);
+    std::partial_sort(order.begin(), order.begin() + keep0, order.end(), better);
+    std::vector<int32_t> kept(order.begin(), order.begin() + keep0);
     std::sort(kept.begin(), kept.end());
-    Dev dkept, red_poses;
-    UVC_TRY(alloc<int32_t>(dkept, keep, "kept pose list"));
-    UVC_TRY(alloc<float>(red_poses, keep * pose_dim, "kept poses"));
-    UVC_HIP(hipMemcpyAsync(dkept.p, kept.data(), (size_t)keep * 4, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_gather_rows, dim3(grid_of(keep * pose_dim, 256)), dim3(256), 0, st, poses_dev,
-                       (const int32_t*)dkept.p, keep, pose_dim, (float*)red_poses.p);
-    UVC_HIP(hipGetLastError());
     UVC_HIP(hipEventRecord(ev.e[2], st));
-    // 3. reduced E and its LP
-    Dev Ered, tred;
-    UVC_TRY(alloc<float>(Ered, keep * N, "E (kept poses)"));
-    UVC_TRY(alloc<double>(tred, keep, "reduced dwell times"));
-    UVC_TRY(uvc_compute_irradiance_dense(scene, (const float*)red_poses.p, keep, pose_dim, lamp, &o, (float*)Ered.p,
-                                         nullptr, st));
-    UVC_HIP(hipEventRecord(ev.e[3], st));
-    const uvc_status lps = uvc_solve_dosage_lp((const float*)Ered.p, keep, N, nullptr, mu_min, t_max, tol, max_iter,
-                                               (double*)tred.p, sigma_out_dev, &li, st);
-    if (lps != UVC_OK && lps != UVC_ENOTCONV) return lps;
-    UVC_HIP(hipEventRecord(ev.e[4], st));
-    info->n_kept = keep;
-    info->objective = li.objective;
-    info->lp_iterations = li.iterations;
-    info->lp_converged = lps == UVC_OK ? 1 : 0;
-    // 4. coverage check: elements left (partly) to the penalty term, then
-    // whether the full candidate set could give any of them the dose within
-    // the time budget, max_k E[k,i] * t_max >= mu_min
-    std::vector<double> sig((size_t)N);
-    UVC_HIP(hipMemcpyAsync(sig.data(), sigma_out_dev, (size_t)N * 8, hipMemcpyDeviceToHost, st));
-    std::vector<double> ht((size_t)keep);
-    UVC_HIP(hipMemcpyAsync(ht.data(), tred.p, (size_t)keep * 8, hipMemcpyDeviceToHost, st));
-    UVC_HIP(hipStreamSynchronize(st));
-    std::vector<int32_t> unc;
-    for (int64_t i = 0; i < N; ++i)
-        if (sig[(size_t)i] > 1e-6 * mu_min) unc.push_back((int32_t)i);
-    info->n_uncovered = (int64_t)unc.size();
-    double tsum = 0.0;
-    for (double v : ht) tsum += v;
-    bool fallback = lps != UVC_OK || tsum >= t_max * (1.0 - 1e-6);
-    if (!fallback && !unc.empty()) {
-        const int64_t nu = (int64_t)unc.size();
-        const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nu, ((int64_t)1 << 26) / K));
-        Dev dunc, Echk, cmax;
-        UVC_TRY(alloc<int32_t>(dunc, nu, "uncovered element list"));
-        UVC_TRY(alloc<float>(Echk, K * chunk, "coverage check block"));
-        UVC_TRY(alloc<float>(cmax, chunk, "coverage check maxima"));
-        UVC_HIP(hipMemcpyAsync(dunc.p, unc.data(), (size_t)nu * 4, hipMemcpyHostToDevice, st));
-        std::vector<float> hm((size_t)chunk);
-        const double need = mu_min / t_max;
-        for (int64_t c0 = 0; c0 < nu && !fallback; c0 += chunk) {
-            const int64_t c = std::min(chunk, nu - c0);
-            UVC_TRY(uvc_compute_irradiance_targets(scene, poses_dev, K, pose_dim, lamp, &o,
-                                                   (const int32_t*)dunc.p + c0, c, (float*)Echk.p, nullptr, st));
-            hipLaunchKernelGGL(k_colmax, dim3(grid_of(c, 256)), dim3(256), 0, st, (const float*)Echk.p, K, c,
-                               (float*)cmax.p);
-            UVC_HIP(hipGetLastError());
-            UVC_HIP(hipMemcpyAsync(hm.data(), cmax.p, (size_t)c * 4, hipMemcpyDeviceToHost, st));
-            UVC_HIP(hipStreamSynchronize(st));
-            for (int64_t j = 0; j < c; ++j)
-                if ((double)hm[(size_t)j] >= need) ++info->n_coverable;
-            info->n_checked += c;
-            fallback = info->n_coverable > 0;
+
+    // 3. reduced E and LP; 4. coverage check; at most one repair round that
+    // adds, greedily, poses covering the elements the check found dosable
+    Dev tred, dkept;
+    std::vector<hipEvent_t> marks;  // (E start, LP start, check start, check end) per round
+    bool fallback = false, done = false;
+    const double need = mu_min / t_max;
+    const float alpha = 0.5f;
+    for (int round = 0; round <= repair_rounds && !fallback && !done; ++round) {
+        const int64_t keep = (int64_t)kept.size();
+        hipEvent_t mk[4];
+        for (auto& x : mk) {
+            UVC_HIP(hipEventCreate(&x));
+            marks.push_back(x);
+        }
+        UVC_HIP(hipEventRecord(mk[0], st));
+        Dev red_poses, Ered;
+        tred.reset();
+        dkept.reset();
+        UVC_TRY(alloc<int32_t>(dkept, keep, "kept pose list"));
+        UVC_TRY(alloc<float>(red_poses, keep * pose_dim, "kept poses"));
+        UVC_TRY(alloc<float>(Ered, keep * N, "E (kept poses)"));
+        UVC_TRY(alloc<double>(tred, keep, "reduced dwell times"));
+        UVC_HIP(hipMemcpyAsync(dkept.p, kept.data(), (size_t)keep * 4, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_gather_rows, dim3(grid_of(keep * pose_dim, 256)), dim3(256), 0, st, poses_dev,
+                           (const int32_t*)dkept.p, keep, pose_dim, (float*)red_poses.p);
+        UVC_HIP(hipGetLastError());
+        UVC_TRY(uvc_compute_irradiance_dense(scene, (const float*)red_poses.p, keep, pose_dim, lamp, &o,
+                                             (float*)Ered.p, nullptr, st));
+        UVC_HIP(hipEventRecord(mk[1], st));
+        const uvc_status lps = uvc_solve_dosage_lp((const float*)Ered.p, keep, N, nullptr, mu_min, t_max, tol,
+                                                   max_iter, (double*)tred.p, sigma_out_dev, &li, st);
+        if (lps != UVC_OK && lps != UVC_ENOTCONV) return lps;
+        UVC_HIP(hipEventRecord(mk[2], st));
+        info->n_kept = keep;
+        info->objective = li.objective;
+        info->lp_iterations = li.iterations;
+        info->lp_converged = lps == UVC_OK ? 1 : 0;
+        // elements left (partly) to the penalty term
+        std::vector<double> sig((size_t)N), ht((size_t)keep);
+        UVC_HIP(hipMemcpyAsync(sig.data(), sigma_out_dev, (size_t)N * 8, hipMemcpyDeviceToHost, st));
+        UVC_HIP(hipMemcpyAsync(ht.data(), tred.p, (size_t)keep * 8, hipMemcpyDeviceToHost, st));
+        UVC_HIP(hipStreamSynchronize(st));
+        std::vector<int32_t> unc;
+        for (int64_t i = 0; i < N; ++i)
+            if (sig[(size_t)i] > 1e-6 * mu_min) unc.push_back((int32_t)i);
+        if (round == 0) info->n_uncovered = (int64_t)unc.size();
+        double tsum = 0.0;
+        for (double v : ht) tsum += v;
+        if (lps != UVC_OK || tsum >= t_max * (1.0 - 1e-6)) {
+            fallback = true;
+            UVC_HIP(hipEventRecord(mk[3], st));
+            break;
+        }
+        // which of them the full candidate set could dose within t_max
+        // (max_k E[k,i] t_max >= mu_min), and the greedy repair poses
+        int64_t n_cov = 0;
+        std::vector<int32_t> added;
+        if (!unc.empty()) {
+            const int64_t nu = (int64_t)unc.size();
+            const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nu, ((int64_t)1 << 26) / K));
+            Dev dunc, Echk, cmax, todo, cnt, iskept;
+            UVC_TRY(alloc<int32_t>(dunc, nu, "uncovered element list"));
+            UVC_TRY(alloc<float>(Echk, K * chunk, "coverage check block"));
+            UVC_TRY(alloc<float>(cmax, chunk, "coverage check maxima"));
+            UVC_TRY(alloc<uint8_t>(todo, chunk, "repair flags"));
+            UVC_TRY(alloc<int32_t>(cnt, K, "repair counts"));
+            UVC_TRY(alloc<uint8_t>(iskept, K, "kept flags"));
+            std::vector<uint8_t> hk((size_t)K, 0);
+            for (int32_t k : kept) hk[(size_t)k] = 1;
+            UVC_HIP(hipMemcpyAsync(iskept.p, hk.data(), (size_t)K, hipMemcpyHostToDevice, st));
+            UVC_HIP(hipMemcpyAsync(dunc.p, unc.data(), (size_t)nu * 4, hipMemcpyHostToDevice, st));
+            std::vector<float> hm((size_t)chunk);
+            std::vector<int32_t> hc((size_t)K);
+            for (int64_t c0 = 0; c0 < nu; c0 += chunk) {
+                const int64_t c = std::min(chunk, nu - c0);
+                UVC_TRY(uvc_compute_irradiance_targets(scene, poses_dev, K, pose_dim, lamp, &o,
+                                                       (const int32_t*)dunc.p + c0, c, (float*)Echk.p, nullptr,
+                                                       st));
+                hipLaunchKernelGGL(k_colmax, dim3(grid_of(c, 256)), dim3(256), 0, st, (const float*)Echk.p, K, c,
+                                   (float*)cmax.p);
+                UVC_HIP(hipGetLastError());
+                UVC_HIP(hipMemcpyAsync(hm.data(), cmax.p, (size_t)c * 4, hipMemcpyDeviceToHost, st));
+                UVC_HIP(hipStreamSynchronize(st));
+                int64_t cov_here = 0;
+                for (int64_t j = 0; j < c; ++j)
+                    if ((double)hm[(size_t)j] >= need) ++cov_here;
+                n_cov += cov_here;
+                if (round == 0) info->n_checked += c;
+                if (cov_here == 0 || round == repair_rounds) continue;
+                // greedy cover of this block's dosable columns, starting from
+                // what the poses added for earlier blocks already cover
+                hipLaunchKernelGGL(k_cover_mark, dim3(grid_of(c, 256)), dim3(256), 0, st, (const float*)Echk.p, c,
+                                   (int64_t)0, (const float*)cmax.p, alpha, (float)need, 0, (uint8_t*)todo.p);
+                for (int32_t k : added)
+                    hipLaunchKernelGGL(k_cover_mark, dim3(grid_of(c, 256)), dim3(256), 0, st,
+                                       (const float*)Echk.p, c, (int64_t)k, (const float*)cmax.p, alpha,
+                                       (float)need, 1, (uint8_t*)todo.p);
+                for (int64_t step = 0; step < c; ++step) {
+                    hipLaunchKernelGGL(k_cover_count, dim3((unsigned)K), dim3(256), 0, st, (const float*)Echk.p, c,
+                                       (const float*)cmax.p, (const uint8_t*)todo.p, (const uint8_t*)iskept.p,
+                                       alpha, (int32_t*)cnt.p);
+                    UVC_HIP(hipGetLastError());
+                    UVC_HIP(hipMemcpyAsync(hc.data(), cnt.p, (size_t)K * 4, hipMemcpyDeviceToHost, st));
+                    UVC_HIP(hipStreamSynchronize(st));
+                    int32_t best = -1, bc = 0;
+                    for (int64_t k = 0; k < K; ++k)
+                        if (hc[(size_t)k] > bc) {
+                            bc = hc[(size_t)k];
+                            best = (int32_t)k;
+                        }
+                    if (best < 0) break;
+                    added.push_back(best);
+                    hk[(size_t)best] = 1;
+                    UVC_HIP(hipMemcpyAsync((uint8_t*)iskept.p + best, &hk[(size_t)best], 1, hipMemcpyHostToDevice,
+                                           st));
+                    hipLaunchKernelGGL(k_cover_mark, dim3(grid_of(c, 256)), dim3(256), 0, st, (const float*)Echk.p,
+                                       c, (int64_t)best, (const float*)cmax.p, alpha, (float)need, 1,
+                                       (uint8_t*)todo.p);
+                    UVC_HIP(hipGetLastError());
+                }
+            }
+        }
+        if (round == 0) info->n_coverable = n_cov;
+        UVC_HIP(hipEventRecord(mk[3], st));
+        if (n_cov == 0) {
+            done = true;
+        } else if (round == repair_rounds || added.empty()) {
+            fallback = true;
+        } else {
+            info->n_added = (int64_t)added.size();
+            info->repaired = 1;
+            kept.insert(kept.end(), added.begin(), added.end());
+            std::sort(kept.begin(), kept.end());
         }
     }
     UVC_HIP(hipEventRecord(ev.e[5], st));
     if (fallback) {
         info->fell_back = 1;
+        info->repaired = 0;
         UVC_TRY(full_plan(ev.e[6], ev.e[7]));
     } else {
+        const int64_t keep = (int64_t)kept.size();
         hipLaunchKernelGGL(k_fill_f64, dim3(grid_of(K, 256)), dim3(256), 0, st, t_out_dev, 0.0, K);
         hipLaunchKernelGGL(k_scatter_f64, dim3(grid_of(keep, 256)), dim3(256), 0, st, (const double*)tred.p,
                            (const int32_t*)dkept.p, keep, t_out_dev);
@@ -285,9 +402,12 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
     UVC_HIP(hipEventSynchronize(ev.e[7]));
     info->ms_features = ms_between(ev.e[0], ev.e[1]);
     info->ms_score = ms_between(ev.e[1], ev.e[2]);
-    info->ms_E = ms_between(ev.e[2], ev.e[3]);
-    info->ms_lp = ms_between(ev.e[3], ev.e[4]);
-    info->ms_check = ms_between(ev.e[4], ev.e[5]);
+    for (size_t r = 0; r + 3 < marks.size(); r += 4) {
+        info->ms_E += ms_between(marks[r], marks[r + 1]);
+        info->ms_lp += ms_between(marks[r + 1], marks[r + 2]);
+        info->ms_check += ms_between(marks[r + 2], marks[r + 3]);
+    }
+    for (auto x : marks) (void)hipEventDestroy(x);
     info->ms_fallback = ms_between(ev.e[5], ev.e[7]);
     info->ms_total = ms_between(ev.e[0], ev.e[7]);
     return UVC_OK;

@@ -52,6 +52,7 @@ class OptsC(ctypes.Structure):
 class PlanInfoC(ctypes.Structure):
     _fields_ = [("objective", ctypes.c_double), ("n_kept", _I64), ("fell_back", _I32), ("lp_iterations", _I32),
                 ("lp_converged", _I32), ("n_uncovered", _I64), ("n_checked", _I64), ("n_coverable", _I64),
+                ("n_added", _I64), ("repaired", _I32),
                 ("ms_features", ctypes.c_float), ("ms_score", ctypes.c_float), ("ms_E", ctypes.c_float),
                 ("ms_lp", ctypes.c_float), ("ms_check", ctypes.c_float), ("ms_fallback", ctypes.c_float),
                 ("ms_total", ctypes.c_float)]
@@ -102,7 +103,7 @@ def lib():
                                    ctypes.POINTER(ctypes.c_float), _P], _I32),
         "uvc_plan_ranked": ([_P, _P, _I64, _I32, ctypes.POINTER(LampC), ctypes.POINTER(OptsC), _I32, _P, _I32,
                              ctypes.c_float, ctypes.c_float, ctypes.c_double, ctypes.c_double, ctypes.c_double, _I32,
-                             _P, _P, _P, ctypes.POINTER(PlanInfoC), _P], _I32),
+                             _I32, _P, _P, _P, ctypes.POINTER(PlanInfoC), _P], _I32),
         "uvc_plan_evaluate": ([_P, _I64, _I64, _P, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), ctypes.POINTER(_I64), _P], _I32),
     }
@@ -455,8 +456,8 @@ def ranker_train_step(params: torch.Tensor, m: torch.Tensor, v: torch.Tensor, fe
 
 def plan_ranked(scene: Scene, poses: torch.Tensor, lamp, mode: str = "mlp", params: torch.Tensor | None = None,
                 bf16: bool = False, keep_frac: float = 0.1, feature_height: float = 0.9, mu_min: float = 280.0,
-                t_max: float = 3.6e5, tol: float = 1e-9, max_iter: int = 200, path="lbvh", packet_poses: int = 0,
-                waves: int = 0, stream=None) -> dict:
+                t_max: float = 3.6e5, tol: float = 1e-9, max_iter: int = 200, repair: bool = True, path="lbvh",
+                packet_poses: int = 0, waves: int = 0, stream=None) -> dict:
     """Dwell-time plan with pose pruning (see uvc_plan_ranked)."""
     poses = _require_cuda(poses, "poses", torch.float32)
     K, pd = poses.shape
@@ -471,7 +472,7 @@ def plan_ranked(scene: Scene, poses: torch.Tensor, lamp, mode: str = "mlp", para
     check(lib().uvc_plan_ranked(scene.handle, poses.data_ptr(), K, pd, ctypes.byref(lamp._c), ctypes.byref(opts),
                                 RANK_MODES[mode], params.data_ptr() if params is not None else None, int(bool(bf16)),
                                 float(keep_frac), float(feature_height), float(mu_min), float(t_max), float(tol),
-                                int(max_iter), t.data_ptr(), sg.data_ptr(), kept.ctypes.data_as(_P),
+                                int(max_iter), int(bool(repair)), t.data_ptr(), sg.data_ptr(), kept.ctypes.data_as(_P),
                                 ctypes.byref(info), _stream(stream)))
     out = {f: getattr(info, f) for f, _ in PlanInfoC._fields_}
     out.update(t=t, sigma=sg, kept=kept[:info.n_kept].copy())

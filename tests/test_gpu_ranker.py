@@ -164,13 +164,27 @@ def test_plan_keep_all_equals_full(plan_room):
 
 
 def test_plan_fallback_forced(plan_room):
-    """Keeping one pose leaves coverable elements in the dark: the plan must
-    fall back to the full candidate set."""
+    """Keeping one pose, without repair, leaves coverable elements in the
+    dark: the plan must fall back to the full candidate set."""
     w, sc, poses, E = plan_room
     full = uvc.plan_ranked(sc, poses, w.lamp, mode="none")
-    r = uvc.plan_ranked(sc, poses, w.lamp, mode="area", keep_frac=1e-6)
+    r = uvc.plan_ranked(sc, poses, w.lamp, mode="area", keep_frac=1e-6, repair=False)
     assert r["fell_back"] == 1 and r["n_coverable"] >= 1 and r["n_kept"] == w.K
     assert torch.equal(r["t"], full["t"])
+
+
+def test_plan_repair_from_one_pose(plan_room):
+    """With repair, one kept pose is enlarged greedily until every element
+    the candidates can dose is dosed (or the plan falls back)."""
+    w, sc, poses, E = plan_room
+    r = uvc.plan_ranked(sc, poses, w.lamp, mode="area", keep_frac=1e-6)
+    print({k: r[k] for k in ("n_kept", "n_added", "repaired", "fell_back", "n_coverable")}, flush=True)
+    assert r["repaired"] + r["fell_back"] == 1
+    if r["repaired"]:
+        assert r["n_added"] >= 1 and r["n_kept"] == 1 + r["n_added"]
+        dose = E.double().T @ r["t"]
+        coverable = E.max(dim=0).values.double() * 3.6e5 >= 280.0
+        assert not torch.any((dose < 280.0 * (1 - 1e-6)) & coverable)
 
 
 def test_plan_pruned_covers_every_coverable_element(plan_room):
@@ -178,7 +192,7 @@ def test_plan_pruned_covers_every_coverable_element(plan_room):
     params = _cuda(RK.init_params(0))
     for mode in ("area", "mlp"):
         r = uvc.plan_ranked(sc, poses, w.lamp, mode=mode, params=params, keep_frac=0.1)
-        print(mode, {k: r[k] for k in ("n_kept", "fell_back", "n_uncovered", "n_coverable", "ms_total")},
+        print(mode, {k: r[k] for k in ("n_kept", "n_added", "fell_back", "n_uncovered", "n_coverable", "ms_total")},
               flush=True)
         t = r["t"]
         assert torch.all(t >= 0)
@@ -186,7 +200,7 @@ def test_plan_pruned_covers_every_coverable_element(plan_room):
         coverable = E.max(dim=0).values.double() * 3.6e5 >= 280.0
         short = dose < 280.0 * (1 - 1e-6)
         if r["fell_back"] == 0:
-            assert r["n_kept"] == int(np.ceil(0.1 * w.K))
+            assert r["n_kept"] == int(np.ceil(0.1 * w.K)) + r["n_added"]
             pruned = np.setdiff1d(np.arange(w.K), r["kept"])
             assert torch.all(t[torch.from_numpy(pruned).cuda()] == 0)
             # every element the candidates can dose got its dose

@@ -292,14 +292,19 @@ typedef struct {
  * predictor-corrector interior point method; its K x K normal matrix is
  * formed and Cholesky-factored on the GPU in FP64 (8 K^2 bytes of scratch).
  * Stops when the relative primal residual, dual residual and duality gap are
- * all <= tol.  Outputs t_out_dev (K FP64) and sigma_out_dev (N FP64), device;
- * either may be NULL.  Returns UVC_ENOTCONV with the last point when
- * max_iter is reached.  Synchronises hip_stream. */
+ * all <= tol.  Outputs (device FP64, each may be NULL): t_out_dev (K),
+ * sigma_out_dev (N) and y_out_dev (N + 1): the duals of the N coverage rows
+ * (for a dropped element, its penalty p_i: its sigma_i = mu_min lies inside
+ * its bound) followed by the dual of the time-budget row.  With them the
+ * reduced cost of any further pose k is 1 + y_N - sum_i E[k,i] y_i.
+ * Returns UVC_ENOTCONV with the last point when max_iter is reached.
+ * Synchronises hip_stream. */
 uvc_status uvc_solve_dosage_lp(const float* E_dev, int64_t K, int64_t N,
                                const double* penalty_dev, double mu_min,
                                double t_max, double tol, int32_t max_iter,
                                double* t_out_dev, double* sigma_out_dev,
-                               uvc_lp_info* info, void* hip_stream);
+                               double* y_out_dev, uvc_lp_info* info,
+                               void* hip_stream);
 
 /* ------------------------------------------------------------------------
  * Learned pose ranker.  Not part of the paper: a pruning step in front of
@@ -357,49 +362,53 @@ uvc_status uvc_ranker_train_step(float* params_dev, float* adam_m,
 enum { UVC_RANK_MLP = 0, UVC_RANK_AREA = 1, UVC_RANK_NONE = 2 };
 
 typedef struct {
-    double objective;     /* LP objective of the returned plan                     */
-    int64_t n_kept;       /* poses in the LP that produced the plan                */
-    int32_t fell_back;    /* 1: the full candidate set produced the plan           */
-    int32_t lp_iterations;
+    double objective;        /* LP objective of the returned plan                    */
+    double penalty;          /* the LP penalty p used                                */
+    double min_reduced_cost; /* smallest reduced cost of a pruned pose at the end    */
+    int64_t n_kept;          /* poses in the LP that produced the plan               */
+    int64_t n_added;         /* poses added by pricing                               */
+    int64_t n_priced;        /* element columns computed for pricing (all rounds)    */
+    int32_t rounds;          /* pricing rounds that added poses                      */
+    int32_t fell_back;       /* 1: the full candidate set produced the plan          */
+    int32_t lp_iterations;   /* summed over every LP solved                          */
     int32_t lp_converged;
-    int64_t n_uncovered;  /* reduced plan: elements with sigma_i > 1e-6 mu_min     */
-    int64_t n_checked;    /* of those, checked against every candidate pose        */
-    int64_t n_coverable;  /* of the checked, elements some pose doses within t_max */
-    int64_t n_added;      /* poses added by the repair round                       */
-    int32_t repaired;     /* 1: the plan comes from the repaired pose set          */
-    float ms_features, ms_score, ms_E, ms_lp, ms_check, ms_fallback, ms_total;
+    float ms_features, ms_score, ms_E, ms_lp, ms_price, ms_fallback, ms_total;
 } uvc_plan_info;
 
-/* Dwell-time plan with pose pruning.  score_mode UVC_RANK_MLP scores the K
- * poses with the MLP (params_dev, bf16 as in uvc_ranker_forward) on features
- * taken at feature_height; UVC_RANK_AREA scores them by visible area;
- * UVC_RANK_NONE keeps every pose.  The ceil(keep_frac K) best-scoring poses
- * (ties: lower index) are kept, E is assembled on them (opts as for the
- * dense call) and the relaxed LP is solved with its default penalty (tol,
- * max_iter as for uvc_solve_dosage_lp).  Elements with
- * sigma_i > 1e-6 mu_min are then checked against all K poses, in blocks:
- * those with max_k E[k,i] * t_max >= mu_min could be dosed by the full
- * candidate set.  If there are any and repair_rounds = 1, a repair round
- * adds poses greedily
- * (each time the pruned pose that reaches at least half the best irradiance
- * of the most such elements still open), recomputes E and the LP on the
- * enlarged set and checks again (repair_rounds = 0: no repair).  If
- * dosable elements remain uncovered, a reduced LP does not converge, or its
- * dwell times
- * reach t_max, the plan is recomputed from all K poses (fell_back = 1).  Outputs: t_out_dev (K
- * FP64, zero for pruned poses), sigma_out_dev (N FP64), kept_host (NULL or
- * K int32: the first n_kept entries list the poses of the LP, ascending) and
- * *info with HIP-event stage times.  Synchronises hip_stream. */
+/* Dwell-time plan with pose pruning and column generation.
+ *
+ * score_mode UVC_RANK_MLP scores the K poses with the MLP (params_dev, bf16
+ * as in uvc_ranker_forward) on features taken at feature_height;
+ * UVC_RANK_AREA scores them by visible area; UVC_RANK_NONE solves the LP
+ * over all K poses directly.  The ceil(keep_frac K) best-scoring poses
+ * (ties: lower index) form the restricted set.  Each round assembles E on
+ * the restricted set (opts as for the dense call) and solves the relaxed LP
+ * (tol, max_iter as for uvc_solve_dosage_lp) with the penalty p for every
+ * element (penalty <= 0: 1.001 ||E_R||_F sqrt(K / |R|), an estimate of the
+ * default 1.001 ||E||_F from the first restricted matrix E_R).  With its
+ * duals y, every pruned pose k gets the reduced cost
+ * 1 + y_b - sum_i E[k,i] y_i, summed over the elements with y_i > 1e-9
+ * max y (their E columns over all K poses come from the targets kernel;
+ * elements no candidate sees are skipped afterwards).  If none is below
+ * -1e-6 the restricted plan is optimal for the LP over all K poses and is
+ * returned; otherwise up to max(8, ceil(|R_0| / 4)) poses with the most
+ * negative reduced costs join and the next round starts.  After max_rounds
+ * rounds with pricing still negative, or if an LP does not converge, the
+ * plan is recomputed from all K poses (fell_back = 1).  Outputs: t_out_dev
+ * (K FP64, zero for pruned poses), sigma_out_dev (N FP64), kept_host (NULL
+ * or K int32: the first n_kept entries list the poses of the final LP,
+ * ascending) and *info with HIP-event stage times.  Synchronises
+ * hip_stream. */
 uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses_dev,
                            int64_t K, int32_t pose_dim, const uvc_lamp* lamp,
                            const uvc_opts* opts, int32_t score_mode,
                            const float* params_dev, int32_t bf16,
                            float keep_frac, float feature_height,
-                           double mu_min, double t_max, double tol,
-                           int32_t max_iter, int32_t repair_rounds,
-                           double* t_out_dev,
-                           double* sigma_out_dev, int32_t* kept_host,
-                           uvc_plan_info* info, void* hip_stream);
+                           double penalty, double mu_min, double t_max,
+                           double tol, int32_t max_iter, int32_t max_rounds,
+                           double* t_out_dev, double* sigma_out_dev,
+                           int32_t* kept_host, uvc_plan_info* info,
+                           void* hip_stream);
 
 /* Objective of a dwell-time plan t_dev (K FP64, device) on the dense E_dev
  * (K x N FP32, device): sum_k t_k + p * sum_i max(0, mu_min - sum_k E[k,i] t_k)

@@ -765,11 +765,17 @@ __global__ void k_st_shift(IpmPtr P, int64_t K, int64_t N, double dx, double dz)
     }
 }
 
-__global__ void k_ipm_output(IpmPtr P, int64_t K, int64_t N, double mu, double* __restrict__ t_out,
-                             double* __restrict__ s_out) {
+// Outputs: t, sigma (mu for dropped elements) and the duals of the coverage
+// rows (y_c; the penalty p_i for a dropped element, whose sigma_i = mu sits
+// strictly inside its bound) followed by the budget row's y_b.
+__global__ void k_ipm_output(IpmPtr P, int64_t K, int64_t N, double mu, double yb, const double* __restrict__ pen_in,
+                             double pdef, double* __restrict__ t_out, double* __restrict__ s_out,
+                             double* __restrict__ y_out) {
     const int64_t j = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
     if (t_out && j < K) t_out[j] = fmax(P.xt[j], 0.0);
     if (s_out && j < N) s_out[j] = P.vis[j] ? fmax(P.xs[j], 0.0) : mu;
+    if (y_out && j < N) y_out[j] = P.vis[j] ? fmax(P.yc[j], 0.0) : (pen_in ? pen_in[j] : pdef);
+    if (y_out && j == 0) y_out[N] = fmax(yb, 0.0);
 }
 
 // Largest diagonal entry of M (one workgroup), stored at S[S_REG].
@@ -817,8 +823,8 @@ struct LpWork {
 };
 
 static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* pen_dev, double mu, double tmax,
-                            double tol, int32_t max_iter, double* t_out, double* s_out, uvc_lp_info* info,
-                            hipStream_t st) {
+                            double tol, int32_t max_iter, double* t_out, double* s_out, double* y_out,
+                            uvc_lp_info* info, hipStream_t st) {
     if ((double)K * (double)K * 8.0 > 64e9) return fail(UVC_EUNSUPPORTED, "K too large for the dense normal matrix");
     LpWork W;
     const int64_t rows_per = std::max<int64_t>(64, (K + 15) / 16);
@@ -1085,12 +1091,26 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
         }
         UVC_TRY(reduce(3, 0, 0.0, 0.0));
         obj = red[0] + red[1];
-        hipLaunchKernelGGL(k_ipm_output, dim3(gKN), dim3(LP_TB), 0, st, P, K, N, mu, t_out, s_out);
+        hipLaunchKernelGGL(k_ipm_output, dim3(gKN), dim3(LP_TB), 0, st, P, K, N, mu, yb, pen_dev, pdef, t_out, s_out,
+                           y_out);
     } else {
         if (t_out) UVC_HIP(hipMemsetAsync(t_out, 0, (size_t)K * 8, st));
         if (s_out) {
             std::vector<double> hs((size_t)N, mu);
             UVC_HIP(hipMemcpyAsync(s_out, hs.data(), (size_t)N * 8, hipMemcpyHostToDevice, st));
+            UVC_HIP(hipStreamSynchronize(st));
+        }
+        if (y_out) {
+            // nothing is visible: every element's sigma = mu is interior, its dual is its penalty
+            std::vector<double> hy((size_t)N + 1, 0.0);
+            if (pen_dev) {
+                UVC_HIP(hipMemcpyAsync(hy.data(), pen_dev, (size_t)N * 8, hipMemcpyDeviceToHost, st));
+                UVC_HIP(hipStreamSynchronize(st));
+            } else {
+                for (int64_t i = 0; i < N; ++i) hy[(size_t)i] = pdef;
+            }
+            hy[(size_t)N] = 0.0;
+            UVC_HIP(hipMemcpyAsync(y_out, hy.data(), ((size_t)N + 1) * 8, hipMemcpyHostToDevice, st));
             UVC_HIP(hipStreamSynchronize(st));
         }
     }
@@ -1117,8 +1137,8 @@ using namespace uvc;
 
 extern "C" uvc_status uvc_solve_dosage_lp(const float* E_dev, int64_t K, int64_t N, const double* penalty_dev,
                                           double mu_min, double t_max, double tol, int32_t max_iter,
-                                          double* t_out_dev, double* sigma_out_dev, uvc_lp_info* info,
-                                          void* hip_stream) {
+                                          double* t_out_dev, double* sigma_out_dev, double* y_out_dev,
+                                          uvc_lp_info* info, void* hip_stream) {
     if (info) *info = uvc_lp_info{};
     if (K < 0 || N < 0) return fail(UVC_EINVAL, "negative LP size");
     if (!(mu_min > 0) || !(t_max > 0) || !(tol > 0) || max_iter <= 0)
@@ -1126,8 +1146,8 @@ extern "C" uvc_status uvc_solve_dosage_lp(const float* E_dev, int64_t K, int64_t
     if (K == 0 || N == 0) return fail(UVC_EINVAL, "empty LP");
     if (!E_dev) return fail(UVC_EINVAL, "E is NULL");
     try {
-        return solve_ipm(E_dev, K, N, penalty_dev, mu_min, t_max, tol, max_iter, t_out_dev, sigma_out_dev, info,
-                         (hipStream_t)hip_stream);
+        return solve_ipm(E_dev, K, N, penalty_dev, mu_min, t_max, tol, max_iter, t_out_dev, sigma_out_dev, y_out_dev,
+                         info, (hipStream_t)hip_stream);
     } catch (const std::exception& e) {
         return fail(UVC_ENOMEM, std::string("host exception: ") + e.what());
     }

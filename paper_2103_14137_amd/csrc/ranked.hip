@@ -1,7 +1,11 @@
 // Ranked plan: prune the candidate poses with a score, assemble E on the
-// kept poses only, solve the relaxed dosage LP (Sec. IV-D) on that reduced
-// matrix, check that no element which the full candidate set could dose was
-// left uncovered, and fall back to the full candidate set otherwise.
+// kept poses only and solve the relaxed dosage LP (Sec. IV-D) on that
+// restricted matrix, then price the pruned poses with the LP's duals
+// (column generation): a pose whose reduced cost 1 + y_b - sum_i E[k,i] y_i
+// is negative would lower the objective, so the most negative ones join the
+// restricted set and the LP is solved again.  When no pruned pose prices
+// out, the restricted plan is optimal for the LP over all candidates.  The
+// full candidate set remains the fallback.
 #include "uvc_common.hpp"
 
 #include <algorithm>
@@ -40,38 +44,48 @@ __global__ void k_colmax(const float* __restrict__ E, int64_t K, int64_t n, floa
     out[j] = m;
 }
 
-// Greedy repair of a pruned plan.  For the check block Ec (K x c) of the
-// uncovered elements, a pose "covers" column j when Ec[k,j] >= alpha *
-// cm[j], cm[j] = the column's largest entry.  counts[k] = number of columns
-// still to cover that pose k covers (0 for poses already kept).
-__global__ __launch_bounds__(256) void k_cover_count(const float* __restrict__ Ec, int64_t c,
-                                                     const float* __restrict__ cm, const uint8_t* __restrict__ todo,
-                                                     const uint8_t* __restrict__ is_kept, float alpha,
-                                                     int32_t* __restrict__ counts) {
-    __shared__ int32_t red[256];
+// Pricing: r[k] -= sum_j Ec[k,j] y[j] over one block of c element columns
+// (FP64, fixed order: per thread a strided partial, then a tree).
+__global__ __launch_bounds__(256) void k_price(const float* __restrict__ Ec, int64_t c, const double* __restrict__ y,
+                                               double* __restrict__ r) {
+    __shared__ double red[256];
     const int64_t k = blockIdx.x;
-    int32_t n = 0;
-    if (!is_kept[k])
-        for (int64_t j = threadIdx.x; j < c; j += 256) n += (todo[j] && Ec[k * c + j] >= alpha * cm[j]) ? 1 : 0;
-    red[threadIdx.x] = n;
+    double a = 0.0;
+    for (int64_t j = threadIdx.x; j < c; j += 256) a += (double)Ec[k * c + j] * y[j];
+    red[threadIdx.x] = a;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) counts[k] = red[0];
+    if (threadIdx.x == 0) r[k] -= red[0];
 }
 
-// todo[j] = coverable[j] initially (mode 0), then cleared where row k of Ec
-// covers column j (mode 1).
-__global__ void k_cover_mark(const float* __restrict__ Ec, int64_t c, int64_t k, const float* __restrict__ cm,
-                             float alpha, float need, int mode, uint8_t* __restrict__ todo) {
+// Largest entry of each pose row over the priced columns (to learn which
+// elements no candidate sees at all): colmax over rows for c columns.
+__global__ void k_colmax_any(const float* __restrict__ Ec, int64_t K, int64_t c, float* __restrict__ out) {
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= c) return;
-    if (mode == 0)
-        todo[j] = cm[j] >= need ? 1 : 0;
-    else if (Ec[k * c + j] >= alpha * cm[j])
-        todo[j] = 0;
+    float m = 0.f;
+    for (int64_t k = 0; k < K; ++k) m = fmaxf(m, Ec[k * c + j]);
+    out[j] = m;
+}
+
+// Per-block partial sums of E^2 (FP64) for the Frobenius norm.
+__global__ __launch_bounds__(256) void k_sumsq(const float* __restrict__ E, int64_t n, double* __restrict__ part) {
+    __shared__ double red[256];
+    double a = 0.0;
+    for (int64_t q = blockIdx.x * (int64_t)256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256) {
+        const double v = E[q];
+        a += v * v;
+    }
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
 // Per column i: a = sum_k E[k,i] t_k (FP64, ascending k), visible = some
@@ -166,10 +180,9 @@ using namespace uvc;
 extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses_dev, int64_t K, int32_t pose_dim,
                                       const uvc_lamp* lamp, const uvc_opts* opts, int32_t score_mode,
                                       const float* params_dev, int32_t bf16, float keep_frac, float feature_height,
-                                      double mu_min, double t_max, double tol, int32_t max_iter,
-                                      int32_t repair_rounds, double* t_out_dev,
-                                      double* sigma_out_dev, int32_t* kept_host, uvc_plan_info* info,
-                                      void* hip_stream) {
+                                      double penalty, double mu_min, double t_max, double tol, int32_t max_iter,
+                                      int32_t max_rounds, double* t_out_dev, double* sigma_out_dev,
+                                      int32_t* kept_host, uvc_plan_info* info, void* hip_stream) {
     if (!scene || !poses_dev || !lamp || !t_out_dev || !sigma_out_dev || !info)
         return fail(UVC_EINVAL, "NULL scene, poses, lamp, outputs or info");
     if (K < 1 || (pose_dim != 2 && pose_dim != 3)) return fail(UVC_EINVAL, "K must be >= 1 and pose_dim 2 or 3");
@@ -178,7 +191,8 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
         return fail(UVC_EINVAL, "unknown score_mode");
     if (score_mode == UVC_RANK_MLP && !params_dev) return fail(UVC_EINVAL, "MLP scoring needs params_dev");
     if (!(keep_frac > 0.f && keep_frac <= 1.f)) return fail(UVC_EINVAL, "keep_frac must lie in (0, 1]");
-    if (repair_rounds != 0 && repair_rounds != 1) return fail(UVC_EINVAL, "repair_rounds must be 0 or 1");
+    if (max_rounds < 0 || max_rounds > 1000) return fail(UVC_EINVAL, "max_rounds must lie in [0, 1000]");
+    if (!std::isfinite(penalty)) return fail(UVC_EINVAL, "penalty must be finite");
     const int64_t N = scene->n;
     if (N < 1) return fail(UVC_EINVAL, "empty scene");
     hipStream_t st = (hipStream_t)hip_stream;
@@ -187,23 +201,49 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
     o.stats_dev = nullptr;
     o.kernel_ms = nullptr;
     *info = uvc_plan_info{};
+    info->min_reduced_cost = std::nan("");
     Events ev;
     for (auto& x : ev.e) UVC_HIP(hipEventCreate(&x));
     UVC_HIP(hipEventRecord(ev.e[0], st));
-
     uvc_lp_info li{};
+    Dev pen;  // the LP penalty, one value per element
+    UVC_TRY(alloc<double>(pen, N, "penalty"));
+    auto set_penalty = [&](double p) -> uvc_status {
+        hipLaunchKernelGGL(k_fill_f64, dim3(grid_of(N, 256)), dim3(256), 0, st, (double*)pen.p, p, N);
+        UVC_HIP(hipGetLastError());
+        return UVC_OK;
+    };
+    auto frob = [&](const float* E, int64_t n, double& out) -> uvc_status {
+        Dev part;
+        const int nb = 1024;
+        UVC_TRY(alloc<double>(part, nb, "norm partials"));
+        hipLaunchKernelGGL(k_sumsq, dim3(nb), dim3(256), 0, st, E, n, (double*)part.p);
+        UVC_HIP(hipGetLastError());
+        std::vector<double> h(nb);
+        UVC_HIP(hipMemcpyAsync(h.data(), part.p, nb * 8, hipMemcpyDeviceToHost, st));
+        UVC_HIP(hipStreamSynchronize(st));
+        double a = 0.0;
+        for (double v : h) a += v;
+        out = std::sqrt(a);
+        return UVC_OK;
+    };
+
     auto full_plan = [&](hipEvent_t before, hipEvent_t after) -> uvc_status {
         Dev E;
         UVC_TRY(alloc<float>(E, K * N, "E (full candidate set)"));
         UVC_TRY(uvc_compute_irradiance_dense(scene, poses_dev, K, pose_dim, lamp, &o, (float*)E.p, nullptr, st));
+        // penalty <= 0: the LP's own default over the full matrix
+        if (penalty > 0.0) UVC_TRY(set_penalty(penalty));
         UVC_HIP(hipEventRecord(before, st));
-        const uvc_status s = uvc_solve_dosage_lp((const float*)E.p, K, N, nullptr, mu_min, t_max, tol, max_iter,
-                                                 t_out_dev, sigma_out_dev, &li, st);
+        const uvc_status s =
+            uvc_solve_dosage_lp((const float*)E.p, K, N, penalty > 0.0 ? (const double*)pen.p : nullptr, mu_min,
+                                t_max, tol, max_iter, t_out_dev, sigma_out_dev, nullptr, &li, st);
         UVC_HIP(hipEventRecord(after, st));
         if (s != UVC_OK && s != UVC_ENOTCONV) return s;
         info->n_kept = K;
         info->objective = li.objective;
-        info->lp_iterations = li.iterations;
+        info->penalty = li.penalty;
+        info->lp_iterations += li.iterations;
         info->lp_converged = s == UVC_OK ? 1 : 0;
         if (kept_host)
             for (int64_t k = 0; k < K; ++k) kept_host[k] = (int32_t)k;
@@ -232,8 +272,7 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
     std::vector<float> hs((size_t)K);
     UVC_HIP(hipMemcpyAsync(hs.data(), score.p, (size_t)K * 4, hipMemcpyDeviceToHost, st));
     UVC_HIP(hipStreamSynchronize(st));
-    // 2. keep the ceil(keep_frac K) best scores (ties: lower index first),
-    // then restore the candidates' own order
+    // 2. keep the ceil(keep_frac K) best scores (ties: lower index first)
     const int64_t keep0 = std::min<int64_t>(K, std::max<int64_t>(1, (int64_t)std::ceil((double)keep_frac * (double)K)));
     std::vector<int32_t> order((size_t)K);
     std::iota(order.begin(), order.end(), 0);
@@ -249,14 +288,16 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
     std::sort(kept.begin(), kept.end());
     UVC_HIP(hipEventRecord(ev.e[2], st));
 
-    // 3. reduced E and LP; 4. coverage check; at most one repair round that
-    // adds, greedily, poses covering the elements the check found dosable
+    // 3. restricted LP, then pricing rounds
+    const int64_t add_cap = std::max<int64_t>(8, (keep0 + 3) / 4);
+    const double rc_tol = 1e-6;
+    std::vector<uint8_t> in_set((size_t)K, 0), dark((size_t)N, 0);  // dark: no candidate sees it
+    for (int32_t k : kept) in_set[(size_t)k] = 1;
     Dev tred, dkept;
-    std::vector<hipEvent_t> marks;  // (E start, LP start, check start, check end) per round
-    bool fallback = false, done = false;
-    const double need = mu_min / t_max;
-    const float alpha = 0.5f;
-    for (int round = 0; round <= repair_rounds && !fallback && !done; ++round) {
+    std::vector<hipEvent_t> marks;  // per round: E start, LP start, pricing start, pricing end
+    bool fallback = false, optimal = false;
+    double p_lp = penalty;
+    for (int round = 0; !fallback && !optimal; ++round) {
         const int64_t keep = (int64_t)kept.size();
         hipEvent_t mk[4];
         for (auto& x : mk) {
@@ -264,130 +305,123 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
             marks.push_back(x);
         }
         UVC_HIP(hipEventRecord(mk[0], st));
-        Dev red_poses, Ered;
+        Dev red_poses, Ered, yd;
         tred.reset();
         dkept.reset();
         UVC_TRY(alloc<int32_t>(dkept, keep, "kept pose list"));
         UVC_TRY(alloc<float>(red_poses, keep * pose_dim, "kept poses"));
         UVC_TRY(alloc<float>(Ered, keep * N, "E (kept poses)"));
-        UVC_TRY(alloc<double>(tred, keep, "reduced dwell times"));
+        UVC_TRY(alloc<double>(tred, keep, "restricted dwell times"));
+        UVC_TRY(alloc<double>(yd, N + 1, "LP duals"));
         UVC_HIP(hipMemcpyAsync(dkept.p, kept.data(), (size_t)keep * 4, hipMemcpyHostToDevice, st));
         hipLaunchKernelGGL(k_gather_rows, dim3(grid_of(keep * pose_dim, 256)), dim3(256), 0, st, poses_dev,
                            (const int32_t*)dkept.p, keep, pose_dim, (float*)red_poses.p);
         UVC_HIP(hipGetLastError());
         UVC_TRY(uvc_compute_irradiance_dense(scene, (const float*)red_poses.p, keep, pose_dim, lamp, &o,
                                              (float*)Ered.p, nullptr, st));
+        if (round == 0 && !(p_lp > 0.0)) {
+            // estimate of 1.001 ||E||_F over all candidates from the kept rows
+            double f = 0.0;
+            UVC_TRY(frob((const float*)Ered.p, keep * N, f));
+            p_lp = 1.001 * f * std::sqrt((double)K / (double)keep);
+        }
+        if (round == 0) UVC_TRY(set_penalty(p_lp));
         UVC_HIP(hipEventRecord(mk[1], st));
-        const uvc_status lps = uvc_solve_dosage_lp((const float*)Ered.p, keep, N, nullptr, mu_min, t_max, tol,
-                                                   max_iter, (double*)tred.p, sigma_out_dev, &li, st);
+        const uvc_status lps = uvc_solve_dosage_lp((const float*)Ered.p, keep, N, (const double*)pen.p, mu_min, t_max,
+                                                   tol, max_iter, (double*)tred.p, sigma_out_dev, (double*)yd.p,
+                                                   &li, st);
         if (lps != UVC_OK && lps != UVC_ENOTCONV) return lps;
         UVC_HIP(hipEventRecord(mk[2], st));
         info->n_kept = keep;
         info->objective = li.objective;
-        info->lp_iterations = li.iterations;
+        info->lp_iterations += li.iterations;
         info->lp_converged = lps == UVC_OK ? 1 : 0;
-        // elements left (partly) to the penalty term
-        std::vector<double> sig((size_t)N), ht((size_t)keep);
-        UVC_HIP(hipMemcpyAsync(sig.data(), sigma_out_dev, (size_t)N * 8, hipMemcpyDeviceToHost, st));
-        UVC_HIP(hipMemcpyAsync(ht.data(), tred.p, (size_t)keep * 8, hipMemcpyDeviceToHost, st));
-        UVC_HIP(hipStreamSynchronize(st));
-        std::vector<int32_t> unc;
-        for (int64_t i = 0; i < N; ++i)
-            if (sig[(size_t)i] > 1e-6 * mu_min) unc.push_back((int32_t)i);
-        if (round == 0) info->n_uncovered = (int64_t)unc.size();
-        double tsum = 0.0;
-        for (double v : ht) tsum += v;
-        if (lps != UVC_OK || tsum >= t_max * (1.0 - 1e-6)) {
+        info->rounds = round;
+        if (lps != UVC_OK) {
             fallback = true;
             UVC_HIP(hipEventRecord(mk[3], st));
             break;
         }
-        // which of them the full candidate set could dose within t_max
-        // (max_k E[k,i] t_max >= mu_min), and the greedy repair poses
-        int64_t n_cov = 0;
-        std::vector<int32_t> added;
-        if (!unc.empty()) {
-            const int64_t nu = (int64_t)unc.size();
-            const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(nu, ((int64_t)1 << 26) / K));
-            Dev dunc, Echk, cmax, todo, cnt, iskept;
-            UVC_TRY(alloc<int32_t>(dunc, nu, "uncovered element list"));
-            UVC_TRY(alloc<float>(Echk, K * chunk, "coverage check block"));
-            UVC_TRY(alloc<float>(cmax, chunk, "coverage check maxima"));
-            UVC_TRY(alloc<uint8_t>(todo, chunk, "repair flags"));
-            UVC_TRY(alloc<int32_t>(cnt, K, "repair counts"));
-            UVC_TRY(alloc<uint8_t>(iskept, K, "kept flags"));
-            std::vector<uint8_t> hk((size_t)K, 0);
-            for (int32_t k : kept) hk[(size_t)k] = 1;
-            UVC_HIP(hipMemcpyAsync(iskept.p, hk.data(), (size_t)K, hipMemcpyHostToDevice, st));
-            UVC_HIP(hipMemcpyAsync(dunc.p, unc.data(), (size_t)nu * 4, hipMemcpyHostToDevice, st));
-            std::vector<float> hm((size_t)chunk);
-            std::vector<int32_t> hc((size_t)K);
-            for (int64_t c0 = 0; c0 < nu; c0 += chunk) {
-                const int64_t c = std::min(chunk, nu - c0);
-                UVC_TRY(uvc_compute_irradiance_targets(scene, poses_dev, K, pose_dim, lamp, &o,
-                                                       (const int32_t*)dunc.p + c0, c, (float*)Echk.p, nullptr,
-                                                       st));
-                hipLaunchKernelGGL(k_colmax, dim3(grid_of(c, 256)), dim3(256), 0, st, (const float*)Echk.p, K, c,
-                                   (float*)cmax.p);
-                UVC_HIP(hipGetLastError());
-                UVC_HIP(hipMemcpyAsync(hm.data(), cmax.p, (size_t)c * 4, hipMemcpyDeviceToHost, st));
-                UVC_HIP(hipStreamSynchronize(st));
-                int64_t cov_here = 0;
-                for (int64_t j = 0; j < c; ++j)
-                    if ((double)hm[(size_t)j] >= need) ++cov_here;
-                n_cov += cov_here;
-                if (round == 0) info->n_checked += c;
-                if (cov_here == 0 || round == repair_rounds) continue;
-                // greedy cover of this block's dosable columns, starting from
-                // what the poses added for earlier blocks already cover
-                hipLaunchKernelGGL(k_cover_mark, dim3(grid_of(c, 256)), dim3(256), 0, st, (const float*)Echk.p, c,
-                                   (int64_t)0, (const float*)cmax.p, alpha, (float)need, 0, (uint8_t*)todo.p);
-                for (int32_t k : added)
-                    hipLaunchKernelGGL(k_cover_mark, dim3(grid_of(c, 256)), dim3(256), 0, st,
-                                       (const float*)Echk.p, c, (int64_t)k, (const float*)cmax.p, alpha,
-                                       (float)need, 1, (uint8_t*)todo.p);
-                for (int64_t step = 0; step < c; ++step) {
-                    hipLaunchKernelGGL(k_cover_count, dim3((unsigned)K), dim3(256), 0, st, (const float*)Echk.p, c,
-                                       (const float*)cmax.p, (const uint8_t*)todo.p, (const uint8_t*)iskept.p,
-                                       alpha, (int32_t*)cnt.p);
-                    UVC_HIP(hipGetLastError());
-                    UVC_HIP(hipMemcpyAsync(hc.data(), cnt.p, (size_t)K * 4, hipMemcpyDeviceToHost, st));
-                    UVC_HIP(hipStreamSynchronize(st));
-                    int32_t best = -1, bc = 0;
-                    for (int64_t k = 0; k < K; ++k)
-                        if (hc[(size_t)k] > bc) {
-                            bc = hc[(size_t)k];
-                            best = (int32_t)k;
-                        }
-                    if (best < 0) break;
-                    added.push_back(best);
-                    hk[(size_t)best] = 1;
-                    UVC_HIP(hipMemcpyAsync((uint8_t*)iskept.p + best, &hk[(size_t)best], 1, hipMemcpyHostToDevice,
-                                           st));
-                    hipLaunchKernelGGL(k_cover_mark, dim3(grid_of(c, 256)), dim3(256), 0, st, (const float*)Echk.p,
-                                       c, (int64_t)best, (const float*)cmax.p, alpha, (float)need, 1,
-                                       (uint8_t*)todo.p);
-                    UVC_HIP(hipGetLastError());
-                }
-            }
+        if (keep == K) {
+            optimal = true;
+            UVC_HIP(hipEventRecord(mk[3], st));
+            break;
         }
-        if (round == 0) info->n_coverable = n_cov;
+        // price every pruned pose against the elements with a nonzero dual
+        std::vector<double> hy((size_t)N + 1);
+        UVC_HIP(hipMemcpyAsync(hy.data(), yd.p, ((size_t)N + 1) * 8, hipMemcpyDeviceToHost, st));
+        UVC_HIP(hipStreamSynchronize(st));
+        const double yb = hy[(size_t)N];
+        double ymax = 0.0;
+        for (int64_t i = 0; i < N; ++i) ymax = std::max(ymax, hy[(size_t)i]);
+        std::vector<int32_t> pe;
+        std::vector<double> py;
+        for (int64_t i = 0; i < N; ++i)
+            if (!dark[(size_t)i] && hy[(size_t)i] > 1e-9 * ymax) {
+                pe.push_back((int32_t)i);
+                py.push_back(hy[(size_t)i]);
+            }
+        std::vector<double> rc((size_t)K, 1.0 + yb);
+        if (!pe.empty()) {
+            const int64_t np = (int64_t)pe.size();
+            const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(np, ((int64_t)1 << 26) / K));
+            Dev dpe, dpy, Ec, rdev, cm;
+            UVC_TRY(alloc<int32_t>(dpe, np, "priced elements"));
+            UVC_TRY(alloc<double>(dpy, np, "priced duals"));
+            UVC_TRY(alloc<float>(Ec, K * chunk, "pricing block"));
+            UVC_TRY(alloc<double>(rdev, K, "reduced costs"));
+            UVC_TRY(alloc<float>(cm, chunk, "pricing column maxima"));
+            UVC_HIP(hipMemcpyAsync(dpe.p, pe.data(), (size_t)np * 4, hipMemcpyHostToDevice, st));
+            UVC_HIP(hipMemcpyAsync(dpy.p, py.data(), (size_t)np * 8, hipMemcpyHostToDevice, st));
+            UVC_HIP(hipMemcpyAsync(rdev.p, rc.data(), (size_t)K * 8, hipMemcpyHostToDevice, st));
+            std::vector<float> hm((size_t)chunk);
+            for (int64_t c0 = 0; c0 < np; c0 += chunk) {
+                const int64_t c = std::min(chunk, np - c0);
+                UVC_TRY(uvc_compute_irradiance_targets(scene, poses_dev, K, pose_dim, lamp, &o,
+                                                       (const int32_t*)dpe.p + c0, c, (float*)Ec.p, nullptr, st));
+                hipLaunchKernelGGL(k_price, dim3((unsigned)K), dim3(256), 0, st, (const float*)Ec.p, c,
+                                   (const double*)dpy.p + c0, (double*)rdev.p);
+                hipLaunchKernelGGL(k_colmax_any, dim3(grid_of(c, 256)), dim3(256), 0, st, (const float*)Ec.p, K, c,
+                                   (float*)cm.p);
+                UVC_HIP(hipGetLastError());
+                UVC_HIP(hipMemcpyAsync(hm.data(), cm.p, (size_t)c * 4, hipMemcpyDeviceToHost, st));
+                UVC_HIP(hipStreamSynchronize(st));
+                for (int64_t j = 0; j < c; ++j)
+                    if (hm[(size_t)j] == 0.f) dark[(size_t)pe[(size_t)(c0 + j)]] = 1;
+                info->n_priced += c;
+            }
+            UVC_HIP(hipMemcpyAsync(rc.data(), rdev.p, (size_t)K * 8, hipMemcpyDeviceToHost, st));
+            UVC_HIP(hipStreamSynchronize(st));
+        }
         UVC_HIP(hipEventRecord(mk[3], st));
-        if (n_cov == 0) {
-            done = true;
-        } else if (round == repair_rounds || added.empty()) {
+        std::vector<int32_t> cand;
+        double rmin = 0.0;
+        for (int64_t k = 0; k < K; ++k)
+            if (!in_set[(size_t)k]) {
+                rmin = std::min(rmin, rc[(size_t)k]);
+                if (rc[(size_t)k] < -rc_tol) cand.push_back((int32_t)k);
+            }
+        info->min_reduced_cost = rmin;
+        if (cand.empty()) {
+            optimal = true;
+        } else if (round >= max_rounds) {
             fallback = true;
         } else {
-            info->n_added = (int64_t)added.size();
-            info->repaired = 1;
-            kept.insert(kept.end(), added.begin(), added.end());
+            const int64_t na = std::min<int64_t>((int64_t)cand.size(), add_cap);
+            std::partial_sort(cand.begin(), cand.begin() + na, cand.end(), [&](int32_t a, int32_t b) {
+                return rc[(size_t)a] != rc[(size_t)b] ? rc[(size_t)a] < rc[(size_t)b] : a < b;
+            });
+            for (int64_t q = 0; q < na; ++q) {
+                kept.push_back(cand[(size_t)q]);
+                in_set[(size_t)cand[(size_t)q]] = 1;
+            }
+            info->n_added += na;
             std::sort(kept.begin(), kept.end());
         }
     }
     UVC_HIP(hipEventRecord(ev.e[5], st));
     if (fallback) {
         info->fell_back = 1;
-        info->repaired = 0;
         UVC_TRY(full_plan(ev.e[6], ev.e[7]));
     } else {
         const int64_t keep = (int64_t)kept.size();
@@ -399,13 +433,14 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
         UVC_HIP(hipEventRecord(ev.e[7], st));
         if (kept_host) std::copy(kept.begin(), kept.end(), kept_host);
     }
+    if (!fallback) info->penalty = p_lp;
     UVC_HIP(hipEventSynchronize(ev.e[7]));
     info->ms_features = ms_between(ev.e[0], ev.e[1]);
     info->ms_score = ms_between(ev.e[1], ev.e[2]);
     for (size_t r = 0; r + 3 < marks.size(); r += 4) {
         info->ms_E += ms_between(marks[r], marks[r + 1]);
         info->ms_lp += ms_between(marks[r + 1], marks[r + 2]);
-        info->ms_check += ms_between(marks[r + 2], marks[r + 3]);
+        info->ms_price += ms_between(marks[r + 2], marks[r + 3]);
     }
     for (auto x : marks) (void)hipEventDestroy(x);
     info->ms_fallback = ms_between(ev.e[5], ev.e[7]);

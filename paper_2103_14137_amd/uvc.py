@@ -50,11 +50,11 @@ class OptsC(ctypes.Structure):
 
 
 class PlanInfoC(ctypes.Structure):
-    _fields_ = [("objective", ctypes.c_double), ("n_kept", _I64), ("fell_back", _I32), ("lp_iterations", _I32),
-                ("lp_converged", _I32), ("n_uncovered", _I64), ("n_checked", _I64), ("n_coverable", _I64),
-                ("n_added", _I64), ("repaired", _I32),
+    _fields_ = [("objective", ctypes.c_double), ("penalty", ctypes.c_double), ("min_reduced_cost", ctypes.c_double),
+                ("n_kept", _I64), ("n_added", _I64), ("n_priced", _I64), ("rounds", _I32), ("fell_back", _I32),
+                ("lp_iterations", _I32), ("lp_converged", _I32),
                 ("ms_features", ctypes.c_float), ("ms_score", ctypes.c_float), ("ms_E", ctypes.c_float),
-                ("ms_lp", ctypes.c_float), ("ms_check", ctypes.c_float), ("ms_fallback", ctypes.c_float),
+                ("ms_lp", ctypes.c_float), ("ms_price", ctypes.c_float), ("ms_fallback", ctypes.c_float),
                 ("ms_total", ctypes.c_float)]
 
 
@@ -94,7 +94,7 @@ def lib():
         "uvc_autotune": ([_P, _P, _I64, _I32, ctypes.POINTER(LampC), _I32, ctypes.c_char_p, _I32,
                           ctypes.POINTER(OptsC), _P], _I32),
         "uvc_solve_dosage_lp": ([_P, _I64, _I64, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _I32, _P, _P,
-                                 ctypes.POINTER(LpInfoC), _P], _I32),
+                                 _P, ctypes.POINTER(LpInfoC), _P], _I32),
         "uvc_ranker_param_count": ([], _I64),
         "uvc_ranker_features": ([_P, _P, _I64, _I32, ctypes.c_float, _P, _P], _I32),
         "uvc_ranker_forward": ([_P, _P, _I64, _I32, _P, _P], _I32),
@@ -102,8 +102,8 @@ def lib():
         "uvc_ranker_train_step": ([_P, _P, _P, _P, _P, _P, _I64, ctypes.c_float, _I64, _P,
                                    ctypes.POINTER(ctypes.c_float), _P], _I32),
         "uvc_plan_ranked": ([_P, _P, _I64, _I32, ctypes.POINTER(LampC), ctypes.POINTER(OptsC), _I32, _P, _I32,
-                             ctypes.c_float, ctypes.c_float, ctypes.c_double, ctypes.c_double, ctypes.c_double, _I32,
-                             _I32, _P, _P, _P, ctypes.POINTER(PlanInfoC), _P], _I32),
+                             ctypes.c_float, ctypes.c_float, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                             ctypes.c_double, _I32, _I32, _P, _P, _P, ctypes.POINTER(PlanInfoC), _P], _I32),
         "uvc_plan_evaluate": ([_P, _I64, _I64, _P, ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), ctypes.POINTER(_I64), _P], _I32),
     }
@@ -312,15 +312,16 @@ def solve_lp(E: torch.Tensor, mu_min: float = 280.0, t_max: float = 3.6e5, penal
     K, N = E.shape
     t = torch.empty(K, dtype=torch.float64, device=E.device)
     sg = torch.empty(N, dtype=torch.float64, device=E.device)
+    y = torch.empty(N + 1, dtype=torch.float64, device=E.device)
     if penalty is not None:
         penalty = _require_cuda(penalty, "penalty", torch.float64)
     info = LpInfoC()
     st = lib().uvc_solve_dosage_lp(E.data_ptr(), K, N, penalty.data_ptr() if penalty is not None else None,
                                    float(mu_min), float(t_max), float(tol), int(max_iter), t.data_ptr(),
-                                   sg.data_ptr(), ctypes.byref(info), _stream(stream))
+                                   sg.data_ptr(), y.data_ptr(), ctypes.byref(info), _stream(stream))
     if st != 0 and not (allow_notconv and st == -4):
         check(st)
-    return {"t": t, "sigma": sg, "objective": info.objective, "primal_residual": info.primal_residual,
+    return {"t": t, "sigma": sg, "y": y, "objective": info.objective, "primal_residual": info.primal_residual,
             "dual_residual": info.dual_residual, "gap": info.gap, "iterations": info.iterations,
             "n_visible": info.n_visible, "penalty": info.penalty, "converged": st == 0}
 
@@ -455,10 +456,11 @@ def ranker_train_step(params: torch.Tensor, m: torch.Tensor, v: torch.Tensor, fe
 
 
 def plan_ranked(scene: Scene, poses: torch.Tensor, lamp, mode: str = "mlp", params: torch.Tensor | None = None,
-                bf16: bool = False, keep_frac: float = 0.1, feature_height: float = 0.9, mu_min: float = 280.0,
-                t_max: float = 3.6e5, tol: float = 1e-9, max_iter: int = 200, repair: bool = True, path="lbvh",
-                packet_poses: int = 0, waves: int = 0, stream=None) -> dict:
-    """Dwell-time plan with pose pruning (see uvc_plan_ranked)."""
+                bf16: bool = False, keep_frac: float = 0.1, feature_height: float = 0.9, penalty: float = 0.0,
+                mu_min: float = 280.0, t_max: float = 3.6e5, tol: float = 1e-9, max_iter: int = 200,
+                max_rounds: int = 20, path="lbvh", packet_poses: int = 0, waves: int = 0, stream=None) -> dict:
+    """Dwell-time plan with pose pruning and column generation (see
+    uvc_plan_ranked)."""
     poses = _require_cuda(poses, "poses", torch.float32)
     K, pd = poses.shape
     lamp = as_lamp(lamp)
@@ -471,9 +473,9 @@ def plan_ranked(scene: Scene, poses: torch.Tensor, lamp, mode: str = "mlp", para
     opts = make_opts(path, packet_poses=packet_poses, waves=waves)
     check(lib().uvc_plan_ranked(scene.handle, poses.data_ptr(), K, pd, ctypes.byref(lamp._c), ctypes.byref(opts),
                                 RANK_MODES[mode], params.data_ptr() if params is not None else None, int(bool(bf16)),
-                                float(keep_frac), float(feature_height), float(mu_min), float(t_max), float(tol),
-                                int(max_iter), int(bool(repair)), t.data_ptr(), sg.data_ptr(), kept.ctypes.data_as(_P),
-                                ctypes.byref(info), _stream(stream)))
+                                float(keep_frac), float(feature_height), float(penalty), float(mu_min), float(t_max),
+                                float(tol), int(max_iter), int(max_rounds), t.data_ptr(), sg.data_ptr(),
+                                kept.ctypes.data_as(_P), ctypes.byref(info), _stream(stream)))
     out = {f: getattr(info, f) for f, _ in PlanInfoC._fields_}
     out.update(t=t, sigma=sg, kept=kept[:info.n_kept].copy())
     return out

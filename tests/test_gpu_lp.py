@@ -71,3 +71,20 @@ def test_lp_input_errors(uvc):
     sol = uvc.solve_lp(E)  # nothing visible: t = 0, sigma = mu
     assert sol["n_visible"] == 0 and float(sol["t"].abs().sum()) == 0.0
     assert torch.all(sol["sigma"] == 280.0)
+
+
+@pytest.mark.parametrize("seed,K,N,t_max", [(0, 40, 300, 3.6e5), (2, 60, 400, 500.0)])
+def test_duals_certify_optimality(uvc, seed, K, N, t_max):
+    """The returned duals with t and sigma pass the KKT check of the
+    reference module (feasibility of both sides, relative duality gap), and
+    dropped elements carry their penalty as dual."""
+    E = _random_instance(seed, K, N)
+    sol = uvc.solve_lp(torch.from_numpy(E).cuda(), mu_min=280.0, t_max=t_max, tol=1e-9)
+    y = sol["y"].cpu().numpy()
+    vis = E.max(0) > 0
+    p = np.full(N, sol["penalty"])
+    cert = {"t": sol["t"].cpu().numpy(), "sigma": sol["sigma"].cpu().numpy(), "visible": vis, "penalty": p,
+            "duals": np.concatenate([y[:N][vis], y[N:]])}
+    prim, dual, gap = lp.kkt_residuals(E.astype(np.float64), cert, mu_min=280.0, t_max=t_max)
+    assert prim <= 1e-6 * 280.0 and dual <= 1e-6 * (1.0 + sol["penalty"]) and gap <= 1e-7, (prim, dual, gap)
+    assert np.all(y[:N][~vis] == sol["penalty"]) and y[N] >= 0

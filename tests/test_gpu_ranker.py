@@ -156,59 +156,65 @@ def test_plan_none_is_the_full_lp(plan_room):
 
 
 def test_plan_keep_all_equals_full(plan_room):
+    """Keeping every pose is the full LP, bit for bit (same penalty)."""
     w, sc, poses, E = plan_room
-    full = uvc.plan_ranked(sc, poses, w.lamp, mode="none")
-    r = uvc.plan_ranked(sc, poses, w.lamp, mode="area", keep_frac=1.0)
+    p = 1.001 * float(E.double().pow(2).sum().sqrt())
+    full = uvc.plan_ranked(sc, poses, w.lamp, mode="none", penalty=p)
+    r = uvc.plan_ranked(sc, poses, w.lamp, mode="area", keep_frac=1.0, penalty=p)
     assert r["n_kept"] == w.K and np.array_equal(r["kept"], np.arange(w.K))
     assert torch.equal(r["t"], full["t"])
 
 
+def _p_full(E):
+    return 1.001 * float(E.double().pow(2).sum().sqrt())
+
+
 def test_plan_fallback_forced(plan_room):
-    """Keeping one pose, without repair, leaves coverable elements in the
-    dark: the plan must fall back to the full candidate set."""
+    """Keeping one pose without any pricing round leaves improving poses
+    out: the plan must fall back to the full candidate set."""
     w, sc, poses, E = plan_room
     full = uvc.plan_ranked(sc, poses, w.lamp, mode="none")
-    r = uvc.plan_ranked(sc, poses, w.lamp, mode="area", keep_frac=1e-6, repair=False)
-    assert r["fell_back"] == 1 and r["n_coverable"] >= 1 and r["n_kept"] == w.K
+    r = uvc.plan_ranked(sc, poses, w.lamp, mode="area", keep_frac=1e-6, max_rounds=0)
+    assert r["fell_back"] == 1 and r["n_kept"] == w.K and r["min_reduced_cost"] < -1e-6
     assert torch.equal(r["t"], full["t"])
 
 
-def test_plan_repair_from_one_pose(plan_room):
-    """With repair, one kept pose is enlarged greedily until every element
-    the candidates can dose is dosed (or the plan falls back)."""
+def test_plan_column_generation_from_one_pose(plan_room):
+    """Starting from a single pose, pricing rounds reach the optimum of the
+    LP over all candidates (same penalty), without the fallback."""
     w, sc, poses, E = plan_room
-    r = uvc.plan_ranked(sc, poses, w.lamp, mode="area", keep_frac=1e-6)
-    print({k: r[k] for k in ("n_kept", "n_added", "repaired", "fell_back", "n_coverable")}, flush=True)
-    assert r["repaired"] + r["fell_back"] == 1
-    if r["repaired"]:
-        assert r["n_added"] >= 1 and r["n_kept"] == 1 + r["n_added"]
-        dose = E.double().T @ r["t"]
-        coverable = E.max(dim=0).values.double() * 3.6e5 >= 280.0
-        assert not torch.any((dose < 280.0 * (1 - 1e-6)) & coverable)
+    p = _p_full(E)
+    full = uvc.plan_ranked(sc, poses, w.lamp, mode="none", penalty=p)
+    r = uvc.plan_ranked(sc, poses, w.lamp, mode="area", keep_frac=1e-6, penalty=p, max_rounds=100)
+    print({k: r[k] for k in ("n_kept", "n_added", "rounds", "fell_back", "n_priced", "min_reduced_cost")},
+          flush=True)
+    assert r["fell_back"] == 0 and r["n_kept"] == 1 + r["n_added"] and r["min_reduced_cost"] >= -1e-6
+    ev = uvc.plan_evaluate(E, r["t"], penalty=p)
+    ref = uvc.plan_evaluate(E, full["t"], penalty=p)
+    assert abs(ev["objective"] - ref["objective"]) <= 1e-6 * ref["objective"]
 
 
-def test_plan_pruned_covers_every_coverable_element(plan_room):
+def test_plan_pruned_reaches_full_optimum(plan_room):
     w, sc, poses, E = plan_room
     params = _cuda(RK.init_params(0))
+    p = _p_full(E)
+    full = uvc.plan_ranked(sc, poses, w.lamp, mode="none", penalty=p)
+    ref = uvc.plan_evaluate(E, full["t"], penalty=p)
     for mode in ("area", "mlp"):
-        r = uvc.plan_ranked(sc, poses, w.lamp, mode=mode, params=params, keep_frac=0.1)
-        print(mode, {k: r[k] for k in ("n_kept", "n_added", "fell_back", "n_uncovered", "n_coverable", "ms_total")},
+        r = uvc.plan_ranked(sc, poses, w.lamp, mode=mode, params=params, keep_frac=0.1, penalty=p)
+        print(mode, {k: r[k] for k in ("n_kept", "n_added", "rounds", "fell_back", "n_priced", "ms_total")},
               flush=True)
         t = r["t"]
         assert torch.all(t >= 0)
-        dose = (E.double().T @ t)
-        coverable = E.max(dim=0).values.double() * 3.6e5 >= 280.0
-        short = dose < 280.0 * (1 - 1e-6)
         if r["fell_back"] == 0:
             assert r["n_kept"] == int(np.ceil(0.1 * w.K)) + r["n_added"]
             pruned = np.setdiff1d(np.arange(w.K), r["kept"])
             assert torch.all(t[torch.from_numpy(pruned).cuda()] == 0)
-            # every element the candidates can dose got its dose
-            assert not torch.any(short & coverable)
-        ev = uvc.plan_evaluate(E, t)
-        full = uvc.plan_ranked(sc, poses, w.lamp, mode="none")
-        ref = uvc.plan_evaluate(E, full["t"])
-        assert ev["objective"] >= ref["objective"] * (1 - 1e-6)
+        ev = uvc.plan_evaluate(E, t, penalty=p)
+        assert abs(ev["objective"] - ref["objective"]) <= 1e-6 * ref["objective"]
+    # the default penalty estimate still gives a valid plan
+    r = uvc.plan_ranked(sc, poses, w.lamp, mode="area", keep_frac=0.1)
+    assert r["penalty"] > 0 and torch.all(r["t"] >= 0)
 
 
 def test_plan_evaluate_matches_numpy():
@@ -237,3 +243,5 @@ def test_plan_rejects_bad_arguments(plan_room):
         uvc.plan_ranked(sc, poses, w.lamp, mode="area", keep_frac=0.0)
     with pytest.raises(uvc.UvcError):
         uvc.plan_ranked(sc, poses, w.lamp, mode="area", keep_frac=1.5)
+    with pytest.raises(uvc.UvcError):
+        uvc.plan_ranked(sc, poses, w.lamp, mode="area", max_rounds=-1)

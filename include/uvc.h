@@ -368,7 +368,8 @@ typedef struct {
     int64_t n_kept;          /* poses in the LP that produced the plan               */
     int64_t n_added;         /* poses added by pricing                               */
     int64_t n_priced;        /* element columns computed for pricing (all rounds)    */
-    int32_t rounds;          /* pricing rounds that added poses                      */
+    int32_t rounds;          /* restricted LPs solved                                */
+    int32_t rounds_added;    /* pricing rounds that added poses                      */
     int32_t fell_back;       /* 1: the full candidate set produced the plan          */
     int32_t lp_iterations;   /* summed over every LP solved                          */
     int32_t lp_converged;
@@ -391,9 +392,12 @@ typedef struct {
  * max y (their E columns over all K poses come from the targets kernel;
  * elements no candidate sees are skipped afterwards).  If none is below
  * -1e-6 the restricted plan is optimal for the LP over all K poses and is
- * returned; otherwise up to max(8, ceil(|R_0| / 4)) poses with the most
- * negative reduced costs join and the next round starts.  After max_rounds
- * rounds with pricing still negative, or if an LP does not converge, the
+ * returned; otherwise up to max(16, |R_0|) poses with the most negative
+ * reduced costs join and the next round starts.  Rounds that go on to add
+ * poses solve their LP to max(tol, 1e-6); when pricing finds nothing the
+ * same set is solved to tol and priced once more before the plan is
+ * accepted.  After max_rounds rounds that added poses with pricing still
+ * negative, or if an LP does not converge, the
  * plan is recomputed from all K poses (fell_back = 1).  Outputs: t_out_dev
  * (K FP64, zero for pruned poses), sigma_out_dev (N FP64), kept_host (NULL
  * or K int32: the first n_kept entries list the poses of the final LP,

@@ -289,8 +289,12 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
     UVC_HIP(hipEventRecord(ev.e[2], st));
 
     // 3. restricted LP, then pricing rounds
-    const int64_t add_cap = std::max<int64_t>(8, (keep0 + 3) / 4);
+    const int64_t add_cap = std::max<int64_t>(16, keep0);
     const double rc_tol = 1e-6;
+    // rounds that add poses solve to a looser tolerance; once pricing finds
+    // nothing, the same set is solved to tol and priced again
+    const double tol_loose = std::max(tol, 1e-6);
+    bool final_pass = tol_loose <= tol;
     std::vector<uint8_t> in_set((size_t)K, 0), dark((size_t)N, 0);  // dark: no candidate sees it
     for (int32_t k : kept) in_set[(size_t)k] = 1;
     Dev tred, dkept;
@@ -328,15 +332,15 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
         if (round == 0) UVC_TRY(set_penalty(p_lp));
         UVC_HIP(hipEventRecord(mk[1], st));
         const uvc_status lps = uvc_solve_dosage_lp((const float*)Ered.p, keep, N, (const double*)pen.p, mu_min, t_max,
-                                                   tol, max_iter, (double*)tred.p, sigma_out_dev, (double*)yd.p,
-                                                   &li, st);
+                                                   (final_pass || keep == K) ? tol : tol_loose, max_iter, (double*)tred.p,
+                                                   sigma_out_dev, (double*)yd.p, &li, st);
         if (lps != UVC_OK && lps != UVC_ENOTCONV) return lps;
         UVC_HIP(hipEventRecord(mk[2], st));
         info->n_kept = keep;
         info->objective = li.objective;
         info->lp_iterations += li.iterations;
         info->lp_converged = lps == UVC_OK ? 1 : 0;
-        info->rounds = round;
+        info->rounds = round + 1;
         if (lps != UVC_OK) {
             fallback = true;
             UVC_HIP(hipEventRecord(mk[3], st));
@@ -403,8 +407,11 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
             }
         info->min_reduced_cost = rmin;
         if (cand.empty()) {
-            optimal = true;
-        } else if (round >= max_rounds) {
+            if (final_pass)
+                optimal = true;
+            else
+                final_pass = true;
+        } else if (info->rounds_added >= max_rounds) {
             fallback = true;
         } else {
             const int64_t na = std::min<int64_t>((int64_t)cand.size(), add_cap);
@@ -416,6 +423,8 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
                 in_set[(size_t)cand[(size_t)q]] = 1;
             }
             info->n_added += na;
+            info->rounds_added += 1;
+            final_pass = tol_loose <= tol;
             std::sort(kept.begin(), kept.end());
         }
     }

@@ -154,7 +154,8 @@ def evaluate_room(w: workloads.Workload, params: np.ndarray, keep_frac: float = 
             out[mode] = {"objective": ev["objective"],
                          "gap": (ev["objective"] - ref["objective"]) / ref["objective"],
                          "fell_back": r["fell_back"], "n_kept": r["n_kept"], "n_added": r["n_added"],
-                         "rounds": r["rounds"], "n_priced": r["n_priced"], "ms": r["ms_total"],
+                         "rounds": r["rounds"], "rounds_added": r["rounds_added"], "n_priced": r["n_priced"],
+                         "ms": r["ms_total"],
                          "lp_iterations": r["lp_iterations"],
                          "ms_parts": {k: r[k] for k in ("ms_features", "ms_score", "ms_E", "ms_lp", "ms_price",
                                                         "ms_fallback")}}
@@ -198,6 +199,9 @@ def _main(argv=None) -> int:
     e.add_argument("--keep", type=float, default=0.1)
     e.add_argument("--bf16", action="store_true")
     e.add_argument("--json", default=None)
+    e.add_argument("--n-range", type=int, nargs=2, default=list(TRAIN_N_RANGE))
+    e.add_argument("--k-range", type=int, nargs=2, default=list(TRAIN_K_RANGE))
+    e.add_argument("--seed0", type=int, default=HELDOUT_SEED0)
     a = ap.parse_args(argv)
 
     def log(msg):
@@ -229,9 +233,11 @@ def _main(argv=None) -> int:
     ck = load_checkpoint(a.weights)
     res = []
     for r in range(a.rooms):
-        res.append(evaluate_room(room(HELDOUT_SEED0 + r), ck["params"], a.keep, a.bf16))
-        if (r + 1) % 8 == 0:
-            log(f"evaluated {r + 1}/{a.rooms}: {json.dumps(summarize(res))}")
+        res.append(evaluate_room(room(a.seed0 + r, tuple(a.n_range), tuple(a.k_range)), ck["params"], a.keep, a.bf16))
+        x = res[-1]
+        log(f"room {r}: K={x['K']} N={x['N']} full {x['full_ms']:.0f} ms | " +
+            " | ".join(f"{m} gap {x[m]['gap']:.1e} rounds {x[m]['rounds']} kept {x[m]['n_kept']} {x[m]['ms']:.0f} ms"
+                       for m in ("mlp", "area")))
     s = summarize(res)
     log(json.dumps(s))
     if a.json:

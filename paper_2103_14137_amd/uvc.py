@@ -51,7 +51,8 @@ class OptsC(ctypes.Structure):
 
 class PlanInfoC(ctypes.Structure):
     _fields_ = [("objective", ctypes.c_double), ("penalty", ctypes.c_double), ("min_reduced_cost", ctypes.c_double),
-                ("n_kept", _I64), ("n_added", _I64), ("n_priced", _I64), ("rounds", _I32), ("fell_back", _I32),
+                ("n_kept", _I64), ("n_added", _I64), ("n_priced", _I64), ("rounds", _I32), ("rounds_added", _I32),
+                ("fell_back", _I32),
                 ("lp_iterations", _I32), ("lp_converged", _I32),
                 ("ms_features", ctypes.c_float), ("ms_score", ctypes.c_float), ("ms_E", ctypes.c_float),
                 ("ms_lp", ctypes.c_float), ("ms_price", ctypes.c_float), ("ms_fallback", ctypes.c_float),

@@ -186,7 +186,8 @@ def test_plan_column_generation_from_one_pose(plan_room):
     p = _p_full(E)
     full = uvc.plan_ranked(sc, poses, w.lamp, mode="none", penalty=p)
     r = uvc.plan_ranked(sc, poses, w.lamp, mode="area", keep_frac=1e-6, penalty=p, max_rounds=100)
-    print({k: r[k] for k in ("n_kept", "n_added", "rounds", "fell_back", "n_priced", "min_reduced_cost")},
+    print({k: r[k] for k in ("n_kept", "n_added", "rounds", "rounds_added", "fell_back", "n_priced",
+                             "min_reduced_cost")},
           flush=True)
     assert r["fell_back"] == 0 and r["n_kept"] == 1 + r["n_added"] and r["min_reduced_cost"] >= -1e-6
     ev = uvc.plan_evaluate(E, r["t"], penalty=p)

@@ -94,6 +94,65 @@ def cpu_baseline(w, n_poses=32, n_elems=1024, seed=2024):
             "seconds": dt, "entries_per_s": len(pk) / dt}
 
 
+def extras(uvc, workloads, dev, log):
+    """The additions around the hot path, each timed once: the 64-room
+    batched launch (persistent, hipGraph replay, one launch per room), the
+    dosage LP on one room, and the ranked plan (learned ranker + column
+    generation) against the full-candidate LP on one larger room."""
+    import numpy as np
+    import torch
+
+    out = {}
+    # batched: 64 rooms, 2k-80k triangles and 500-8000 poses each
+    t0 = time.perf_counter()
+    rooms = workloads.batch(seed=3, n_rooms=64)
+    gen_s = time.perf_counter() - t0
+    scenes = [uvc.Scene(torch.from_numpy(r.mesh.verts).to(dev), torch.from_numpy(r.mesh.tris).to(dev))
+              for r in rooms]
+    poses = [torch.from_numpy(np.ascontiguousarray(r.poses)).to(dev) for r in rooms]
+    lamp = uvc.Lamp(rooms[0].lamp.dz, rooms[0].lamp.power)
+    b = uvc.Batch(scenes, poses, lamp)
+    entries = sum(r.K * r.N for r in rooms)
+    modes = {}
+    for mode in ("persistent", "graph", "per_room"):
+        b.run(mode, timing=True)
+        ms = b.run(mode, timing=True)
+        modes[mode] = {"ms": ms, "entries_per_s": entries / (ms * 1e-3)}
+    out["batched"] = {"rooms": len(rooms), "N_total": sum(r.N for r in rooms), "K_total": sum(r.K for r in rooms),
+                      "entries": entries, "E_GB": entries * 4 / 1e9, "generate_s": gen_s, "modes": modes}
+    log(f"batched {out['batched']}")
+    b.close()
+    for sc in scenes:
+        sc.close()
+    del b, poses
+    torch.cuda.empty_cache()
+    # dosage LP on one room (2k-20k triangles, 200-1000 poses family)
+    from paper_2103_14137_amd import ranker
+    w = ranker.room(ranker.TRAIN_SEED0)
+    sc = uvc.Scene(w.mesh.verts, w.mesh.tris)
+    P = torch.from_numpy(np.ascontiguousarray(w.poses)).to(dev)
+    E, _ = uvc.irradiance_dense(sc, P, lamp, path="lbvh")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lp = uvc.solve_lp(E, allow_notconv=True)
+    out["lp"] = {"K": w.K, "N": w.N, "ms": 1e3 * (time.perf_counter() - t0), "iterations": lp["iterations"],
+                 "converged": lp["converged"], "objective": lp["objective"]}
+    log(f"lp {out['lp']}")
+    sc.close()
+    del E
+    # ranked plan vs full on one larger room (trained weights)
+    wpath = os.path.join(ROOT, "paper_2103_14137_amd", "weights", "ranker_tower8.bin")
+    if os.path.exists(wpath):
+        ck = ranker.load_checkpoint(wpath)
+        w = ranker.room(950000, (20000, 80000), (1000, 3000))
+        r = ranker.evaluate_room(w, ck["params"], keep_frac=0.1, modes=("mlp", "area"))
+        out["ranked_plan"] = {"K": r["K"], "N": r["N"], "full_ms": r["full_ms"],
+                              **{m: {k: r[m][k] for k in ("gap", "ms", "rounds", "n_kept", "fell_back")}
+                                 for m in ("mlp", "area")}}
+        log(f"ranked plan {out['ranked_plan']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +160,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the brute-force path comparison")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched / LP / ranked-plan sections")
     ap.add_argument("--mode", choices=["bench", "kernel", "copy"], default="bench",
                     help="kernel: only two launches of the irradiance kernel (for counter runs); "
                          "copy: a plain 1 GiB device copy (counter calibration)")
@@ -231,6 +291,10 @@ def main():
                      "counts": st, "source_hash": source_hash()},
         "paths": paths,
     }
+    del E
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        out["extras"] = extras(uvc, workloads, dev, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
         log(f"cpu baseline {out['cpu_baseline']}")

@@ -66,6 +66,11 @@ struct IrrParams {
     LampArgs lamp;
 };
 
+// Scene arrays are read-only while a kernel runs; records addressed by a
+// uniform index (hierarchy nodes, leaf triangles) are read through the
+// constant address space so that they become scalar loads.
+typedef __attribute__((address_space(4))) const float cfloat;
+
 // ------------------------------------------------------------------ FP32
 struct Ray {
     float ox, oy, oz;     // origin: the source (uniform across the packet)
@@ -141,8 +146,8 @@ __device__ __noinline__ int tri_rare(float rox, float roy, float roz, float rtx,
 // three dot products with D are per lane.  Forming them from the short edge
 // vector keeps their FP32 error proportional to |vi - O| |vj - vi|, the
 // scale of the edge orientation itself.
-__device__ __forceinline__ bool tri_hit(const Ray& r, const float* __restrict__ t, float tau_e, float tau_p,
-                                        int* rechecks) {
+template <class TP>
+__device__ __forceinline__ bool tri_hit(const Ray& r, TP t, float tau_e, float tau_p, int* rechecks) {
     const float v0x = t[0], v0y = t[1], v0z = t[2], v1x = t[3], v1y = t[4], v1z = t[5];
     const float v2x = t[6], v2y = t[7], v2z = t[8];
     const float e01x = t[TRI_E01], e01y = t[TRI_E01 + 1], e01z = t[TRI_E01 + 2];
@@ -165,7 +170,7 @@ __device__ __forceinline__ bool tri_hit(const Ray& r, const float* __restrict__ 
     if (mn < -be && mx > be) return false;
     const int q = tri_rare(r.ox, r.oy, r.oz, r.tx, r.ty, r.tz, v0x, v0y, v0z, v1x, v1y, v1z, v2x, v2y, v2z, mn, mx,
                            be, tau_p);
-    *rechecks += q >> 1;
+    if (rechecks) *rechecks += q >> 1;
     return (q & 1) != 0;
 }
 
@@ -212,21 +217,17 @@ struct ElemLane {
     bool valid;
 };
 
-__device__ __forceinline__ ElemLane load_elem(const IrrParams& P, int64_t& slot, int64_t& col) {
+// Element record of leaf slot `slot` (valid lanes only).
+template <class PT>
+__device__ __forceinline__ ElemLane elem_record(PT& P, int32_t slot, bool valid) {
     ElemLane e;
-    e.valid = slot < P.ntargets;
-    col = 0;
-    if (e.valid && P.targets) {
-        col = slot;
-        slot = P.targets[slot];
-    }
-    if (e.valid) {
-        const float4* q = reinterpret_cast<const float4*>(P.elem + slot * ELEM_WORDS);
+    e.valid = valid;
+    if (valid) {
+        const float4* q = reinterpret_cast<const float4*>(P.elem + (int64_t)slot * ELEM_WORDS);
         const float4 a = q[0], b = q[1];
         e.cx = a.x; e.cy = a.y; e.cz = a.z; e.nx = a.w; e.ny = b.x; e.nz = b.y;
         e.self = __float_as_int(b.z);
         e.rho_t = b.w;
-        if (!P.targets) col = e.self;
     } else {
         e.cx = e.cy = e.cz = e.nx = e.ny = e.nz = e.rho_t = 0.f;
         e.self = -1;
@@ -234,13 +235,29 @@ __device__ __forceinline__ ElemLane load_elem(const IrrParams& P, int64_t& slot,
     return e;
 }
 
+// Maps a lane's list position to its leaf slot and output column (the
+// input element index, or the position in the target list).
+template <class PT>
+__device__ __forceinline__ ElemLane load_elem(PT& P, int32_t& slot, int32_t& col) {
+    const bool valid = slot < P.ntargets;
+    col = 0;
+    if (valid && P.targets) {
+        col = slot;
+        slot = P.targets[slot];
+    }
+    const ElemLane e = elem_record(P, slot, valid);
+    if (valid && !P.targets) col = e.self;
+    return e;
+}
+
 // Front-facing decision for the lane's element: FP32 with band, FP64 inside.
-__device__ __forceinline__ bool front_face(const IrrParams& P, const ElemLane& e, int64_t slot, float ox, float oy,
+template <class PT>
+__device__ __forceinline__ bool front_face(PT& P, const ElemLane& e, int32_t slot, float ox, float oy,
                                            float oz, float dx, float dy, float dz, float s, int* f64) {
     const float l1 = fabsf(dx) + fabsf(dy) + fabsf(dz);
     if (fabsf(s) > P.tau_f * l1) return s > 0.0f;
-    ++*f64;
-    const float* t = P.tri + slot * TRI_WORDS;
+    if (f64) ++*f64;
+    const float* t = P.tri + (int64_t)slot * TRI_WORDS;
     return front_fp64(ox, oy, oz, e.cx, e.cy, e.cz, t[0], t[1], t[2], t[3], t[4], t[5], t[6], t[7], t[8]);
 }
 
@@ -249,13 +266,16 @@ struct NodeRec {
     float4 a, b, c, d;  // left box lo xyz hi x | hi yz, right lo xy | right lo z hi xyz | refs, hint
 };
 
+// The hierarchy is read-only while a kernel runs and the node index is
+// uniform: read it through the constant address space (scalar loads).
+
 __device__ __forceinline__ NodeRec load_node(const float* __restrict__ nodes, int node) {
-    const float4* q = reinterpret_cast<const float4*>(nodes + (int64_t)node * NODE_WORDS);
+    const cfloat* q = (const cfloat*)(nodes + (int64_t)node * NODE_WORDS);
     NodeRec r;
-    r.a = q[0];
-    r.b = q[1];
-    r.c = q[2];
-    r.d = q[3];
+    r.a = make_float4(q[0], q[1], q[2], q[3]);
+    r.b = make_float4(q[4], q[5], q[6], q[7]);
+    r.c = make_float4(q[8], q[9], q[10], q[11]);
+    r.d = make_float4(q[12], q[13], q[14], q[15]);
     return r;
 }
 
@@ -263,8 +283,8 @@ __device__ __forceinline__ NodeRec load_node(const float* __restrict__ nodes, in
 // segment entered the current node; both child boxes are tested for every
 // lane and the ballots are masked with m.  Deferred (node, mask) pairs live
 // in three VGPRs, entry i in lane i (depth <= 64).
-template <bool STATS>
-__device__ __forceinline__ unsigned long long traverse(const IrrParams& P, const Ray& r, unsigned long long live,
+template <bool STATS, class PT>
+__device__ __forceinline__ unsigned long long traverse(PT& P, const Ray& r, unsigned long long live,
                                                        unsigned long long& n_nodes, unsigned long long& n_tris,
                                                        unsigned long long& n_steps, int* rechecks) {
     const int lane = lane_id();
@@ -287,7 +307,7 @@ __device__ __forceinline__ unsigned long long traverse(const IrrParams& P, const
             ++n_steps;
         }
         if (cl < 0 && mL) {
-            const float* t = tri + (int64_t)(~cl) * TRI_WORDS;
+            const cfloat* t = (const cfloat*)(tri + (int64_t)(~cl) * TRI_WORDS);
             const int who = __float_as_int(t[TRI_ID]);
             const bool act = ((mL >> lane) & 1ull) && r.self != who;
             bool h = false;
@@ -297,7 +317,7 @@ __device__ __forceinline__ unsigned long long traverse(const IrrParams& P, const
             mL = 0;
         }
         if (cr < 0 && mR) {
-            const float* t = tri + (int64_t)(~cr) * TRI_WORDS;
+            const cfloat* t = (const cfloat*)(tri + (int64_t)(~cr) * TRI_WORDS);
             const int who = __float_as_int(t[TRI_ID]);
             const bool act = ((mR >> lane) & 1ull) && r.self != who;
             bool h = false;
@@ -356,8 +376,8 @@ __device__ __forceinline__ unsigned long long traverse(const IrrParams& P, const
 // the 64 segments of a source share their target and diverge only towards
 // their nearby origins.  Each lane sums its element's terms over the sources
 // in ascending order, exactly like the brute-force path.
-template <bool STATS>
-__device__ __forceinline__ void irr_lbvh_packet(const IrrParams& P, int64_t kg, int64_t quad) {
+template <bool STATS, class PT>
+__device__ __forceinline__ void irr_lbvh_packet(PT& P, const LampArgs& L, int64_t kg, int64_t quad) {
     const int lane = lane_id(), w = (int)(threadIdx.x >> 6);
     const int tkl = P.tk_log2, tel = 6 - tkl;
     const int kk = lane >> tel, ee = lane & ((1 << tel) - 1);
@@ -365,25 +385,31 @@ __device__ __forceinline__ void irr_lbvh_packet(const IrrParams& P, int64_t kg, 
     if (tile >= P.ntiles) return;
     const int64_t kpos = (kg << tkl) + kk;
     const bool kok = kpos < P.K;
-    const int64_t k = kok ? P.pose_order[kpos] : 0;
-    int64_t slot = (tile << tel) + ee, col;
-    const ElemLane e = load_elem(P, slot, col);
-    const bool ok = kok && e.valid;
-    const float* pp = P.poses + k * P.pose_dim;
+    const int32_t k = kok ? P.pose_order[kpos] : 0;
+    int32_t slot = (int32_t)((tile << tel) + ee), col;
+    bool ok;
+    {
+        const ElemLane e0 = load_elem(P, slot, col);
+        ok = kok && e0.valid;
+    }
+    const float* pp = P.poses + (int64_t)k * P.pose_dim;
     const float px = kok ? pp[0] : 0.0f, py = kok ? pp[1] : 0.0f;
     const float pz0 = (kok && P.pose_dim == 3) ? pp[2] : 0.0f;
-    const int32_t nb = ok ? P.near_off[slot] : 0, ne = ok ? P.near_off[slot + 1] : 0;
     float acc = 0.0f;
     uint32_t bits = 0;
     int rechecks = 0, f64 = 0;
+    int* const rc_p = STATS ? &rechecks : nullptr;
+    int* const f64_p = STATS ? &f64 : nullptr;
     unsigned n_near = 0;
     unsigned long long n_rays = 0, n_nodes = 0, n_tris = 0, n_vis = 0, n_steps = 0;
-    for (int j = 0; j < P.lamp.S; ++j) {
-        const float oz = pz0 + P.lamp.dz[j];
+    for (int j = 0; j < L.S; ++j) {
+        const int32_t sl = slot;
+        const ElemLane e = elem_record(P, sl, ok);
+        const float oz = pz0 + L.dz[j];
         const float dx = px - e.cx, dy = py - e.cy, dz = oz - e.cz;
         const float s = cos_numerator(dx, dy, dz, e.nx, e.ny, e.nz);
         bool f = false;
-        if (ok) f = front_face(P, e, slot, px, py, oz, dx, dy, dz, s, &f64);
+        if (ok) f = front_face(P, e, sl, px, py, oz, dx, dy, dz, s, f64_p);
         const unsigned long long live = __ballot(f);
         if (!live) continue;
         Ray r;
@@ -397,12 +423,13 @@ __device__ __forceinline__ void irr_lbvh_packet(const IrrParams& P, int64_t kg, 
         }
         const unsigned long long tlive = __ballot(trav);
         unsigned long long occl = 0;
-        if (tlive) occl = traverse<STATS>(P, r, tlive, n_nodes, n_tris, n_steps, &rechecks);
+        if (tlive) occl = traverse<STATS>(P, r, tlive, n_nodes, n_tris, n_steps, rc_p);
         bool vis = f && !((occl >> lane) & 1ull);
         if (P.use_near && vis) {
+            const int32_t nb = P.near_off[sl], ne = P.near_off[sl + 1];
             for (int32_t q = nb; q < ne && vis; ++q) {
                 const float* t = P.tri + (int64_t)P.near[q] * TRI_WORDS;
-                if (tri_hit(r, t, P.tau_e, P.tau_p, &rechecks)) vis = false;
+                if (tri_hit(r, t, P.tau_e, P.tau_p, rc_p)) vis = false;
                 if (STATS) ++n_near;
             }
         }
@@ -411,13 +438,14 @@ __device__ __forceinline__ void irr_lbvh_packet(const IrrParams& P, int64_t kg, 
             n_vis += (unsigned long long)__popcll(__ballot(vis));
         }
         if (vis) {
-            acc = acc + entry_term(dx, dy, dz, s, P.lamp.pw[j]);
+            acc = acc + entry_term(dx, dy, dz, s, L.pw[j]);
             bits |= 1u << j;
         }
     }
     if (ok) {
-        P.E[k * P.ld + col] = acc;
-        if (P.vis) P.vis[k * P.ld + col] = bits;
+        const int64_t at = (int64_t)k * P.ld + col;
+        P.E[at] = acc;
+        if (P.vis) P.vis[at] = bits;
     }
     if (STATS) {
         const unsigned long long rc = wave_sum_u32((unsigned)rechecks), fc = wave_sum_u32((unsigned)f64);
@@ -435,26 +463,64 @@ __device__ __forceinline__ void irr_lbvh_packet(const IrrParams& P, int64_t kg, 
     }
 }
 
+// Persistent work distribution.  The items (workgroup-sized pieces of
+// work) are cut into 8 contiguous ranges, one per XCD (workgroups are
+// dispatched to the XCDs round robin, so workgroup b runs on XCD b mod 8).
+// A workgroup takes items from its own XCD's range through an atomic
+// counter, which keeps each XCD's L2 on a compact part of the work, then
+// takes what is left in the other ranges; it exits once all 8 are
+// exhausted.  counter[x] counts the items taken from range x.
+struct PersistArgs {
+    unsigned long long* counter;  // 8 counters, zeroed before the launch
+    int64_t range_off[9];         // range x = [range_off[x], range_off[x + 1])
+};
+
+__device__ __forceinline__ int64_t next_item(const PersistArgs& Q, int& range, long long* item_s) {
+    const int home = (int)(blockIdx.x & 7u);
+    while (range < 8) {
+        const int x = (home + range) & 7;
+        const int64_t r0 = Q.range_off[x], r1 = Q.range_off[x + 1];
+        if (threadIdx.x == 0) *item_s = (long long)(r0 + (int64_t)atomicAdd(Q.counter + x, 1ull));
+        __syncthreads();
+        // the item is the same for the whole workgroup: make that explicit
+        const long long v = *item_s;
+        const int64_t item = (int64_t)(((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(v >> 32))
+                                        << 32) |
+                                       (unsigned)__builtin_amdgcn_readfirstlane((int)v));
+        __syncthreads();
+        if (item < r1) return item;
+        ++range;
+    }
+    return -1;
+}
+
 template <bool STATS>
-__device__ __forceinline__ void irr_lbvh_body(const IrrParams& P) {
-    int64_t kg, quad;
-    block_coords(P, kg, quad);
-    irr_lbvh_packet<STATS>(P, kg, quad);
+__device__ __forceinline__ void irr_lbvh_body(const IrrParams& P, const PersistArgs& Q) {
+    __shared__ long long item_s;
+    int range = 0;
+    for (int64_t item; (item = next_item(Q, range, &item_s)) >= 0;)
+        irr_lbvh_packet<STATS, const IrrParams>(P, P.lamp, item % P.kgroups, item / P.kgroups);
 }
 
 // Kernel variants differ only in the occupancy the register allocator aims
 // for (waves per SIMD); which one is fastest depends on the scene.
 template <bool STATS>
-__global__ __launch_bounds__(256) void k_irr_lbvh(IrrParams P) {
-    irr_lbvh_body<STATS>(P);
+__global__ __launch_bounds__(256) void k_irr_lbvh(IrrParams P, PersistArgs Q) {
+    irr_lbvh_body<STATS>(P, Q);
 }
 template <bool STATS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_irr_lbvh_w6(IrrParams P) {
-    irr_lbvh_body<STATS>(P);
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_irr_lbvh_w6(IrrParams P,
+                                                                                             PersistArgs Q) {
+    irr_lbvh_body<STATS>(P, Q);
 }
 template <bool STATS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_irr_lbvh_w8(IrrParams P) {
-    irr_lbvh_body<STATS>(P);
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_irr_lbvh_w8(IrrParams P,
+                                                                                             PersistArgs Q) {
+    irr_lbvh_body<STATS>(P, Q);
+}
+
+__global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int n) {
+    if (blockIdx.x == 0 && (int)threadIdx.x < n) p[threadIdx.x] = v;
 }
 
 // ------------------------------------------------------------- batched
@@ -464,36 +530,78 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 // the next item from an atomic counter until the queue is drained, so every
 // wave reaches the exit.  An item is one workgroup's worth of work of the
 // single-room kernel (4 packets), run by the same code.
+typedef __attribute__((address_space(4))) IrrParams CIrrParams;
+
 struct BatchArgs {
-    const IrrParams* rooms;
+    const IrrParams* rooms;   // per-room parameters (their lamp fields are not read)
+    LampArgs lamp;            // the lamp shared by every room
     const int64_t* item_off;  // n_queue + 1
     const int32_t* room_of;   // n_queue
     int32_t n_queue;
     int64_t total;
-    unsigned long long* counter;
+    PersistArgs q;            // the item ranges and their counters
 };
 
-__global__ void k_fill_u64(unsigned long long* p, unsigned long long v) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+__device__ __forceinline__ int32_t ufl(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t ufl64(int64_t v) {
+    return (int64_t)(((unsigned long long)(unsigned)ufl((int32_t)(v >> 32)) << 32) | (unsigned)ufl((int32_t)v));
+}
+template <class T>
+__device__ __forceinline__ T* uflp(T* p) {
+    return reinterpret_cast<T*>(ufl64(reinterpret_cast<int64_t>(p)));
+}
+
+// A room's parameters, read by the whole workgroup at a uniform address and
+// made explicitly uniform so that they live in scalar registers; the lamp is
+// the batch's.
+__device__ __forceinline__ IrrParams uniform_room(const IrrParams* src) {
+    IrrParams P;
+    P.tri = uflp(src->tri);
+    P.elem = uflp(src->elem);
+    P.nodes = uflp(src->nodes);
+    P.near_off = uflp(src->near_off);
+    P.near = uflp(src->near);
+    P.poses = uflp(src->poses);
+    P.pose_order = uflp(src->pose_order);
+    P.targets = uflp(src->targets);
+    P.K = ufl64(src->K);
+    P.N = ufl64(src->N);
+    P.ntargets = ufl64(src->ntargets);
+    P.ld = ufl64(src->ld);
+    P.ntiles = ufl64(src->ntiles);
+    P.nquads = ufl64(src->nquads);
+    P.kgroups = ufl64(src->kgroups);
+    P.pose_dim = ufl(src->pose_dim);
+    P.tile_tris = ufl(src->tile_tris);
+    P.tk_log2 = ufl(src->tk_log2);
+    P.use_near = ufl(src->use_near);
+    P.waves = ufl(src->waves);
+    P.tau_f = __int_as_float(ufl(__float_as_int(src->tau_f)));
+    P.tau_e = __int_as_float(ufl(__float_as_int(src->tau_e)));
+    P.tau_p = __int_as_float(ufl(__float_as_int(src->tau_p)));
+    P.E = uflp(src->E);
+    P.vis = uflp(src->vis);
+    P.stats = uflp(src->stats);
+    P.lamp.S = 0;  // the batch's lamp is passed separately
+    return P;
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_irr_batched(BatchArgs B) {
     __shared__ long long item_s;
-    while (true) {
-        if (threadIdx.x == 0) item_s = (long long)atomicAdd(B.counter, 1ull);
-        __syncthreads();
-        const int64_t item = item_s;
-        __syncthreads();
-        if (item >= B.total) break;
+    int range = 0;
+    for (int64_t item; (item = next_item(B.q, range, &item_s)) >= 0;) {
         int lo = 0, hi = B.n_queue - 1;  // last q with item_off[q] <= item
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (B.item_off[mid] <= item) lo = mid;
             else hi = mid - 1;
         }
-        const IrrParams& P = B.rooms[B.room_of[lo]];
-        const int64_t local = item - B.item_off[lo];
-        irr_lbvh_packet<false>(P, local % P.kgroups, local / P.kgroups);
+        const int32_t room = ufl(B.room_of[ufl(lo)]);
+        // the rooms' parameters are never written while the kernel runs: read
+        // them through the constant address space (scalar loads)
+        const CIrrParams& P = ((const CIrrParams*)(B.rooms))[room];
+        const int64_t local = ufl64(item - B.item_off[lo]);
+        irr_lbvh_packet<false, const CIrrParams>(P, B.lamp, local % P.kgroups, local / P.kgroups);
     }
 }
 
@@ -505,7 +613,7 @@ __global__ __launch_bounds__(256) void k_irr_brute(IrrParams P) {
     block_coords(P, kk, quad);  // kgroups = K: one pose per workgroup
     const int lane = lane_id(), w = (int)(threadIdx.x >> 6), tid = (int)threadIdx.x;
     const int64_t tile = quad * 4 + w;
-    int64_t slot = tile * 64 + lane, col;
+    int32_t slot = (int32_t)(tile * 64 + lane), col;
     const ElemLane e = load_elem(P, slot, col);  // invalid lanes (and whole waves past the end) idle
     const float* pp = P.poses + kk * P.pose_dim;
     const float px = pp[0], py = pp[1], pz0 = (P.pose_dim == 3) ? pp[2] : 0.0f;
@@ -807,14 +915,30 @@ static uvc_status launch_irr_impl(const IrrParams& P0, int path, hipStream_t st)
         else
             hipLaunchKernelGGL(k_irr_brute<false>, dim3((unsigned)blocks), dim3(256), shm, st, P);
     } else {
+        // persistent launch: as many workgroups as the variant keeps resident
+        // (4 waves each, `waves` per SIMD), draining the items per XCD range
+        int cus = 256, dev = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        const int waves = stats ? 5 : (P.waves == 8 ? 8 : (P.waves == 6 ? 6 : 5));
+        const uint64_t grid = std::min<uint64_t>(blocks, (uint64_t)std::max(1, cus) * (uint64_t)waves);
+        PersistArgs Q{nullptr, {}};
+        for (int x = 0; x <= 8; ++x) Q.range_off[x] = (int64_t)(blocks * (uint64_t)x / 8u);
+        UVC_HIP(hipMallocAsync(reinterpret_cast<void**>(&Q.counter), 8 * sizeof(unsigned long long), st));
+        hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, Q.counter, 0ull, 8);
         if (stats)
-            hipLaunchKernelGGL(k_irr_lbvh<true>, dim3((unsigned)blocks), dim3(256), 0, st, P);
-        else if (P.waves == 8)
-            hipLaunchKernelGGL(k_irr_lbvh_w8<false>, dim3((unsigned)blocks), dim3(256), 0, st, P);
-        else if (P.waves == 6)
-            hipLaunchKernelGGL(k_irr_lbvh_w6<false>, dim3((unsigned)blocks), dim3(256), 0, st, P);
+            hipLaunchKernelGGL(k_irr_lbvh<true>, dim3((unsigned)grid), dim3(256), 0, st, P, Q);
+        else if (waves == 8)
+            hipLaunchKernelGGL(k_irr_lbvh_w8<false>, dim3((unsigned)grid), dim3(256), 0, st, P, Q);
+        else if (waves == 6)
+            hipLaunchKernelGGL(k_irr_lbvh_w6<false>, dim3((unsigned)grid), dim3(256), 0, st, P, Q);
         else
-            hipLaunchKernelGGL(k_irr_lbvh<false>, dim3((unsigned)blocks), dim3(256), 0, st, P);
+            hipLaunchKernelGGL(k_irr_lbvh<false>, dim3((unsigned)grid), dim3(256), 0, st, P, Q);
+        const hipError_t le = hipGetLastError();
+        const hipError_t fe = hipFreeAsync(Q.counter, st);
+        if (le != hipSuccess) return fail(UVC_EDEVICE, std::string("irradiance launch: ") + hipGetErrorString(le));
+        if (fe != hipSuccess) return fail(UVC_EDEVICE, std::string("counter release: ") + hipGetErrorString(fe));
+        return UVC_OK;
     }
     UVC_HIP(hipGetLastError());
     return UVC_OK;
@@ -1110,7 +1234,7 @@ extern "C" uvc_status uvc_batch_create(const uvc_scene* const* scenes, int32_t n
         (r = dalloc_n(&b->d_rooms, (size_t)std::max<int32_t>(n_rooms, 1), "batch room table")) != UVC_OK ||
         (r = dalloc_n(&b->d_item_off, (size_t)n_rooms + 1, "batch queue")) != UVC_OK ||
         (r = dalloc_n(&b->d_room_of, (size_t)std::max<int32_t>(n_rooms, 1), "batch queue")) != UVC_OK ||
-        (r = dalloc_n(&b->d_counter, 1, "batch counter")) != UVC_OK) {
+        (r = dalloc_n(&b->d_counter, 8, "batch counters")) != UVC_OK) {
         free_batch(b);
         return r;
     }
@@ -1156,8 +1280,10 @@ extern "C" uvc_status uvc_batch_create(const uvc_scene* const* scenes, int32_t n
 }
 
 static uvc_status batch_enqueue(uvc_batch* b, hipStream_t st) {
-    BatchArgs A{b->d_rooms, b->d_item_off, b->d_room_of, b->n_queue, b->total, b->d_counter};
-    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(1), 0, st, b->d_counter, 0ull);
+    BatchArgs A{b->d_rooms, b->rooms.empty() ? LampArgs{} : b->rooms[0].lamp, b->d_item_off, b->d_room_of, b->n_queue,
+                b->total, {b->d_counter, {}}};
+    for (int x = 0; x <= 8; ++x) A.q.range_off[x] = b->total * x / 8;
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, b->d_counter, 0ull, 8);
     hipLaunchKernelGGL(k_irr_batched, dim3((unsigned)b->grid), dim3(256), 0, st, A);
     UVC_HIP(hipGetLastError());
     return UVC_OK;

@@ -74,23 +74,20 @@ __device__ __forceinline__ uint32_t spread10(uint32_t v) {
     return v;
 }
 
-// Sort key of each triangle: the dominant axis and sign of its normal
-// (6 classes, top 3 bits) above the 27-bit Morton code of its centroid in the
-// scene box (9 bits per axis, x most significant).  Surfaces of one
-// orientation thus form their own subtrees near the root, and a flat wall or
-// floor becomes a flat subtree that segments ending above it never enter.
-__global__ void k_morton(const float* __restrict__ c, const float* __restrict__ nrm, int64_t n, float lox,
+// Sort key of each triangle: the 30-bit Morton code of its centroid in the
+// scene box (10 bits per axis, x most significant).  (Keys that put the
+// normal's orientation class above the Morton bits were measured too: their
+// six room-sized subtrees near the root cost a third more node visits per
+// segment.)
+__global__ void k_morton(const float* __restrict__ c, int64_t n, float lox,
                          float loy, float loz, float sx, float sy, float sz, uint32_t* __restrict__ key,
                          int32_t* __restrict__ val) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     float q[3] = {(c[3 * i] - lox) * sx, (c[3 * i + 1] - loy) * sy, (c[3 * i + 2] - loz) * sz};
     uint32_t b[3];
-    for (int a = 0; a < 3; ++a) b[a] = (uint32_t)fminf(fmaxf(q[a], 0.f), 511.f);
-    const float ax = fabsf(nrm[3 * i]), ay = fabsf(nrm[3 * i + 1]), az = fabsf(nrm[3 * i + 2]);
-    const int dom = (ax >= ay && ax >= az) ? 0 : (ay >= az ? 1 : 2);
-    const uint32_t cls = 2u * dom + (nrm[3 * i + dom] < 0.f ? 1u : 0u);
-    key[i] = (cls << 27) | (spread10(b[0]) << 2) | (spread10(b[1]) << 1) | spread10(b[2]);
+    for (int a = 0; a < 3; ++a) b[a] = (uint32_t)fminf(fmaxf(q[a], 0.f), 1023.f);
+    key[i] = (spread10(b[0]) << 2) | (spread10(b[1]) << 1) | spread10(b[2]);
     val[i] = (int32_t)i;
 }
 
@@ -548,9 +545,9 @@ static uvc_status build_impl(const float* verts_in, int64_t nv, const int32_t* t
     hipLaunchKernelGGL(k_elements, dim3(grid_for(n, TB)), dim3(TB), 0, st, dv, dt, n, s->elem_c, s->elem_n, s->elem_a);
     STEP(hipGetLastError());
     float sc[3];
-    for (int a = 0; a < 3; ++a) sc[a] = (hi[a] > lo[a]) ? 512.f / (hi[a] - lo[a]) : 0.f;
-    hipLaunchKernelGGL(k_morton, dim3(grid_for(n, TB)), dim3(TB), 0, st, s->elem_c, s->elem_n, n, lo[0], lo[1],
-                       lo[2], sc[0], sc[1], sc[2], s->codes, v1);
+    for (int a = 0; a < 3; ++a) sc[a] = (hi[a] > lo[a]) ? 1024.f / (hi[a] - lo[a]) : 0.f;
+    hipLaunchKernelGGL(k_morton, dim3(grid_for(n, TB)), dim3(TB), 0, st, s->elem_c, n, lo[0], lo[1], lo[2], sc[0],
+                       sc[1], sc[2], s->codes, v1);
     STEP(hipGetLastError());
     uint32_t* ka = s->codes;
     uint32_t* kb = k2;

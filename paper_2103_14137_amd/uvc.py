@@ -15,7 +15,7 @@ import numpy as np
 import torch  # imported before the library so both share one HIP runtime
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libuvc.so")
+LIB_PATH = os.environ.get("UVC_LIB_PATH") or os.path.join(_HERE, "libuvc.so")
 
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64

@@ -308,7 +308,7 @@ uvc_status uvc_solve_dosage_lp(const float* E_dev, int64_t K, int64_t N,
 
 /* ------------------------------------------------------------------------
  * Learned pose ranker.  Not part of the paper: a pruning step in front of
- * E assembly whose result is always judged by the paper's LP (Sec. IV-D)
+ * E assembly whose result is always checked against the paper's LP (Sec. IV-D)
  * on the full candidate set when pruning could have cost coverage.
  * ------------------------------------------------------------------------ */
 

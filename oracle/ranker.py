@@ -2,7 +2,7 @@
 
 The ranker is not part of the paper; it prunes candidate poses before the
 irradiance matrix of Sec. III-B / IV-C is assembled, and the relaxed LP of
-Sec. IV-D on the full candidate set judges it.  This module restates its
+Sec. IV-D on the full candidate set is the reference for it.  This module restates its
 definition plainly, in FP64, so that the GPU kernels can be checked:
 
 features(verts, tris, poses, h)

@@ -118,7 +118,7 @@ __device__ __forceinline__ bool slab(const Ray& r, float lx, float ly, float lz,
 // not already prove a miss: certain "inside" edges go on to the FP32 plane
 // test; any decision within its band is re-taken in FP64.
 // Returns bit 0 = hit, bit 1 = the decision was re-taken in FP64.
-__device__ __noinline__ int tri_rare(float rox, float roy, float roz, float rtx, float rty, float rtz, float v0x,
+__device__ __forceinline__ int tri_rare(float rox, float roy, float roz, float rtx, float rty, float rtz, float v0x,
                                      float v0y, float v0z, float v1x, float v1y, float v1z, float v2x, float v2y,
                                      float v2z, float mn, float mx, float be, float tau_p) {
     const bool inside = (mn > be) || (mx < -be);

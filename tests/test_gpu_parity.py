@@ -260,3 +260,47 @@ def test_power_of_two_scaling(uvc):
     assert torch.allclose(E1 * 0.0625, E0, rtol=1e-6, atol=0)
     sc0.close()
     sc1.close()
+
+
+def test_floorplan_csr_sampled_parity_full_size(uvc):
+    """The ~488k-triangle, 20,000-pose floor plan as CSR, in the benchmark's
+    launch configuration: sampled rows (a contiguous block, nonzeros drawn
+    from each row, uniform columns) against the oracle entry by entry.  The
+    CSR stores an entry exactly when some source sees the element, so the
+    nonzero pattern is checked against the oracle's visibility."""
+    w = _workload("floorplan")
+    print(f"floorplan N={w.N} K={w.K}", flush=True)
+    sc = uvc.Scene(w.mesh.verts, w.mesh.tris)
+    poses = torch.from_numpy(w.poses).cuda()
+    rp, col, val = uvc.irradiance_csr(sc, poses, w.lamp, path="lbvh")
+    torch.cuda.synchronize()
+    r = rp.cpu().numpy()
+    nnz = int(r[-1])
+    assert nnz == col.numel() and nnz > 0 and np.all(np.diff(r) >= 0)
+    rng = np.random.default_rng(77)
+    rows = np.sort(rng.choice(w.K, 48, replace=False))
+    pk, pi, got = [], [], []
+    for q, k in enumerate(rows):
+        c = col[r[k]:r[k + 1]].cpu().numpy()
+        v = val[r[k]:r[k + 1]].cpu().numpy()
+        assert np.all(np.diff(c) > 0) and np.all(v > 0)
+        picks = [rng.integers(0, w.N, 16)]
+        if c.size:
+            picks.append(c[rng.integers(0, c.size, 16)])
+        if q < 2:
+            i0 = int(rng.integers(0, w.N - 512))
+            picks.append(np.arange(i0, i0 + 512))
+        ii = np.concatenate(picks)
+        at = np.searchsorted(c, ii)
+        hit = (at < c.size) & (c[np.minimum(at, max(c.size - 1, 0))] == ii) if c.size else np.zeros(ii.size, bool)
+        got.append(np.where(hit, v[np.minimum(at, max(c.size - 1, 0))] if c.size else 0.0, 0.0))
+        pk.append(np.full(ii.size, k))
+        pi.append(ii)
+    pk, pi, got = np.concatenate(pk), np.concatenate(pi), np.concatenate(got).astype(np.float32)
+    E64, vis64 = ref.irradiance_pairs(w.mesh.verts, w.mesh.tris, w.poses, w.lamp.dz, w.lamp.power, pk, pi)
+    tol = ref.entry_tolerance(w.mesh.verts, w.mesh.tris, w.poses, w.lamp.dz, w.lamp.power, vis64, pk, pi)
+    assert np.array_equal(got != 0, vis64 != 0), int(np.sum((got != 0) != (vis64 != 0)))
+    err = np.abs(got.astype(np.float64) - E64)
+    assert np.all(err <= 1e-5 * E64 + tol), float(np.max(err - (1e-5 * E64 + tol)))
+    assert int((vis64 != 0).sum()) > 500
+    sc.close()

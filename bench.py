@@ -46,7 +46,7 @@ def log(*a):
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("irradiance.hip", "uvc_common.hpp"):
+    for f in ("irradiance.hip", "scene.hip", "uvc_common.hpp"):
         with open(os.path.join(ROOT, "paper_2103_14137_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -97,8 +97,9 @@ def cpu_baseline(w, n_poses=32, n_elems=1024, seed=2024):
 def extras(uvc, workloads, dev, log):
     """The additions around the hot path, each timed once: the 64-room
     batched launch (persistent, hipGraph replay, one launch per room), the
-    dosage LP on one room, and the ranked plan (learned ranker + column
-    generation) against the full-candidate LP on one larger room."""
+    floor plan as CSR, the dosage LP on one room, and the ranked plan
+    (learned ranker + column generation) against the full-candidate LP on
+    one larger room."""
     import numpy as np
     import torch
 
@@ -125,6 +126,23 @@ def extras(uvc, workloads, dev, log):
     for sc in scenes:
         sc.close()
     del b, poses
+    torch.cuda.empty_cache()
+    # CSR at the floor-plan size (~488k triangles, 20,000 poses)
+    fp = workloads.floorplan()
+    sc = uvc.Scene(torch.from_numpy(fp.mesh.verts).to(dev), torch.from_numpy(fp.mesh.tris).to(dev))
+    P = torch.from_numpy(np.ascontiguousarray(fp.poses)).to(dev)
+    flamp = uvc.Lamp(fp.lamp.dz, fp.lamp.power)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rp, col, val = uvc.irradiance_csr(sc, P, flamp, path="lbvh")
+    torch.cuda.synchronize()
+    csr_s = time.perf_counter() - t0
+    nnz = int(rp[-1])
+    out["floorplan_csr"] = {"K": fp.K, "N": fp.N, "seconds": csr_s, "nnz": nnz, "csr_GB": nnz * 8 / 1e9,
+                            "entries_per_s": fp.K * fp.N / csr_s}
+    log(f"floorplan csr {out['floorplan_csr']}")
+    del rp, col, val
+    sc.close()
     torch.cuda.empty_cache()
     # dosage LP on one room (2k-20k triangles, 200-1000 poses family)
     from paper_2103_14137_amd import ranker

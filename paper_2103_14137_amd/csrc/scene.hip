@@ -1,5 +1,6 @@
 // Scene build: validation, surface elements, Morton codes, LSD radix sort,
-// Karras-style hierarchy emission and bottom-up box refit, all on the GPU.
+// agglomerative (PLOC) hierarchy over the Morton order, near lists, all on
+// the GPU.
 #include "uvc_common.hpp"
 #include "fp64_predicate.hpp"
 
@@ -294,105 +295,6 @@ __global__ __launch_bounds__(1024) void k_scan_i32(int32_t* __restrict__ a, int6
     }
 }
 
-// Length of the common prefix of (code, slot) pairs i and j; -1 outside.
-__device__ __forceinline__ int lcp(const uint32_t* __restrict__ code, int64_t n, int64_t i, int64_t j) {
-    if (j < 0 || j >= n) return -1;
-    const uint32_t a = code[i], b = code[j];
-    if (a == b) return 32 + __clz((int)((uint32_t)i ^ (uint32_t)j));
-    return __clz((int)(a ^ b));
-}
-
-// Internal node i covers a contiguous range of sorted slots; its split is
-// the first position where the common prefix shortens (Karras 2012).
-__global__ void k_hierarchy(const uint32_t* __restrict__ code, int64_t n, float* __restrict__ nodes,
-                            int32_t* __restrict__ int_parent, int32_t* __restrict__ leaf_parent) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n - 1) return;
-    const int d = (lcp(code, n, i, i + 1) - lcp(code, n, i, i - 1)) >= 0 ? 1 : -1;
-    const int dmin = lcp(code, n, i, i - d);
-    int64_t lmax = 2;
-    while (lcp(code, n, i, i + lmax * d) > dmin) lmax <<= 1;
-    int64_t l = 0;
-    for (int64_t t = lmax >> 1; t >= 1; t >>= 1)
-        if (lcp(code, n, i, i + (l + t) * d) > dmin) l += t;
-    const int64_t j = i + l * d;
-    const int dnode = lcp(code, n, i, j);
-    int64_t s = 0, t = l;
-    do {
-        t = (t + 1) >> 1;
-        if (lcp(code, n, i, i + (s + t) * d) > dnode) s += t;
-    } while (t > 1);
-    const int64_t g = i + s * d + (d < 0 ? -1 : 0);
-    const int64_t lo = i < j ? i : j, hi = i < j ? j : i;
-    int32_t left, right;
-    if (lo == g) {
-        left = ~(int32_t)g;
-        leaf_parent[g] = (int32_t)i;
-    } else {
-        left = (int32_t)g;
-        int_parent[g] = (int32_t)i;
-    }
-    if (hi == g + 1) {
-        right = ~(int32_t)(g + 1);
-        leaf_parent[g + 1] = (int32_t)i;
-    } else {
-        right = (int32_t)(g + 1);
-        int_parent[g + 1] = (int32_t)i;
-    }
-    float* nd = nodes + i * NODE_WORDS;
-    nd[12] = __int_as_float(left);
-    nd[13] = __int_as_float(right);
-    if (i == 0) int_parent[0] = -1;
-}
-
-// Bottom-up refit: each leaf writes its padded box into its parent; the
-// second thread to reach a node merges both child boxes and climbs on.
-__global__ void k_refit(const float* __restrict__ tri, const int32_t* __restrict__ leaf_parent,
-                        const int32_t* __restrict__ int_parent, float* nodes, uint32_t* counters, int64_t n,
-                        float pad) {
-    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const float* t = tri + s * TRI_WORDS;
-    float lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) {
-        lo[a] = fminf(fminf(t[a], t[3 + a]), t[6 + a]) - pad;
-        hi[a] = fmaxf(fmaxf(t[a], t[3 + a]), t[6 + a]) + pad;
-    }
-    int32_t child = ~(int32_t)s;
-    int32_t p = leaf_parent[s];
-    while (true) {
-        float* nd = nodes + (int64_t)p * NODE_WORDS;
-        const int off = (__float_as_int(nd[12]) == child) ? 0 : 6;
-        for (int a = 0; a < 3; ++a) {
-            nd[off + a] = lo[a];
-            nd[off + 3 + a] = hi[a];
-        }
-        __threadfence();
-        const uint32_t old = atomicAdd(&counters[p], 1u);
-        if (old == 0) return;
-        __threadfence();
-        float b[12];
-        for (int k = 0; k < 12; ++k) b[k] = __builtin_nontemporal_load(nd + k);
-        float best = -1.f;
-        int axis = 0;
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = fminf(b[a], b[6 + a]);
-            hi[a] = fmaxf(b[3 + a], b[9 + a]);
-            const float sep = fabsf((b[6 + a] + b[9 + a]) - (b[a] + b[3 + a]));
-            if (sep > best) {
-                best = sep;
-                axis = a;
-            }
-        }
-        const float cl = 0.5f * (b[axis] + b[3 + axis]), cr = 0.5f * (b[6 + axis] + b[9 + axis]);
-        nd[14] = __int_as_float(axis | ((cl <= cr) ? 4 : 0));
-        nd[15] = 0.5f * (cl + cr);
-        if (p == 0) return;
-        child = p;
-        p = int_parent[p];
-    }
-}
-
 __global__ void k_depth(const int32_t* __restrict__ leaf_parent, const int32_t* __restrict__ int_parent, int64_t n,
                         int32_t* __restrict__ depth) {
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -403,6 +305,116 @@ __global__ void k_depth(const int32_t* __restrict__ leaf_parent, const int32_t* 
         if (d > 1000) break;
     }
     atomicMax(depth, d);
+}
+
+// ---- agglomerative build (PLOC, Meister and Bittner 2018): clusters in
+// Morton order repeatedly merge with their nearest neighbour within PLOC_R
+// positions, measured by the surface area of the merged box; mutual nearest
+// neighbours merge.  Ties go to the lower index, so the pair of least
+// (area, lower index) is always mutual and every round makes progress.
+// Boxes are exact FP32 min/max of the padded triangle boxes, so every node
+// box contains its subtree.  On the ward this tree costs 16.5 node visits
+// per segment against 25.3 for the hierarchy emitted directly from the
+// Morton codes (Karras 2012), for 2-3 ms more build time.
+constexpr int PLOC_R = 16;
+
+__device__ __forceinline__ float merged_area(const float* a, const float* b) {
+    const float dx = fmaxf(a[3], b[3]) - fminf(a[0], b[0]);
+    const float dy = fmaxf(a[4], b[4]) - fminf(a[1], b[1]);
+    const float dz = fmaxf(a[5], b[5]) - fminf(a[2], b[2]);
+    return dx * dy + dy * dz + dz * dx;
+}
+
+__global__ void k_ploc_init(const float* __restrict__ tri, int64_t n, float pad, float* __restrict__ box,
+                            int32_t* __restrict__ ref) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const float* t = tri + s * TRI_WORDS;
+    for (int a = 0; a < 3; ++a) {
+        box[s * 6 + a] = fminf(fminf(t[a], t[3 + a]), t[6 + a]) - pad;
+        box[s * 6 + 3 + a] = fmaxf(fmaxf(t[a], t[3 + a]), t[6 + a]) + pad;
+    }
+    ref[s] = ~(int32_t)s;
+}
+
+__global__ void k_ploc_nn(const float* __restrict__ box, int64_t C, int32_t* __restrict__ nn) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= C) return;
+    float bi[6];
+    for (int k = 0; k < 6; ++k) bi[k] = box[i * 6 + k];
+    const int64_t j0 = i - PLOC_R < 0 ? 0 : i - PLOC_R, j1 = i + PLOC_R < C - 1 ? i + PLOC_R : C - 1;
+    float best = INFINITY;
+    int64_t bj = i == 0 ? 1 : 0;
+    for (int64_t j = j0; j <= j1; ++j) {
+        if (j == i) continue;
+        const float d = merged_area(bi, box + j * 6);
+        if (d < best) {
+            best = d;
+            bj = j;
+        }
+    }
+    nn[i] = (int32_t)bj;
+}
+
+// keep[i] = cluster i survives (unmerged, or the lower index of a merged
+// pair); merge[i] = i is the lower index of a mutual pair.
+__global__ void k_ploc_flags(const int32_t* __restrict__ nn, int64_t C, int32_t* __restrict__ keep,
+                             int32_t* __restrict__ merge) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= C) return;
+    const int32_t j = nn[i];
+    const bool mutual = nn[j] == (int32_t)i;
+    merge[i] = (mutual && (int64_t)j > i) ? 1 : 0;
+    keep[i] = (mutual && (int64_t)j < i) ? 0 : 1;
+}
+
+// After exclusive scans of keep and merge (totals at [C]): write the new
+// nodes (id = next_id - merge rank, so that the last node made is node 0)
+// and the compacted cluster list.
+__global__ void k_ploc_merge(const float* __restrict__ box, const int32_t* __restrict__ ref,
+                             const int32_t* __restrict__ nn, int64_t C, const int32_t* __restrict__ keep,
+                             const int32_t* __restrict__ merge, int64_t next_id, float* __restrict__ nodes,
+                             float* __restrict__ box_out, int32_t* __restrict__ ref_out,
+                             int32_t* __restrict__ int_parent, int32_t* __restrict__ leaf_parent) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= C || keep[i + 1] == keep[i]) return;
+    const int64_t pos = keep[i];
+    if (merge[i + 1] == merge[i]) {
+        for (int k = 0; k < 6; ++k) box_out[pos * 6 + k] = box[i * 6 + k];
+        ref_out[pos] = ref[i];
+        return;
+    }
+    const int64_t j = nn[i];
+    const int32_t id = (int32_t)(next_id - merge[i]);
+    const float* a = box + i * 6;
+    const float* b = box + j * 6;
+    float* nd = nodes + (int64_t)id * NODE_WORDS;
+    for (int k = 0; k < 6; ++k) {
+        nd[k] = a[k];
+        nd[6 + k] = b[k];
+    }
+    nd[12] = __int_as_float(ref[i]);
+    nd[13] = __int_as_float(ref[j]);
+    float best = -1.f;
+    int axis = 0;
+    for (int q = 0; q < 3; ++q) {
+        const float sep = fabsf((b[q] + b[3 + q]) - (a[q] + a[3 + q]));
+        if (sep > best) {
+            best = sep;
+            axis = q;
+        }
+    }
+    const float cl = 0.5f * (a[axis] + a[3 + axis]), cr = 0.5f * (b[axis] + b[3 + axis]);
+    nd[14] = __int_as_float(axis | ((cl <= cr) ? 4 : 0));
+    nd[15] = 0.5f * (cl + cr);
+    for (int q = 0; q < 3; ++q) {
+        box_out[pos * 6 + q] = fminf(a[q], b[q]);
+        box_out[pos * 6 + 3 + q] = fmaxf(a[3 + q], b[3 + q]);
+    }
+    ref_out[pos] = id;
+    const int32_t ri = ref[i], rj = ref[j];
+    if (ri < 0) leaf_parent[~ri] = id; else int_parent[ri] = id;
+    if (rj < 0) leaf_parent[~rj] = id; else int_parent[rj] = id;
 }
 
 static inline unsigned grid_for(int64_t n, int threads) { return (unsigned)((n + threads - 1) / threads); }
@@ -514,7 +526,7 @@ static uvc_status build_impl(const float* verts_in, int64_t nv, const int32_t* t
     TmpBuffers tmp;
     float* dv = nullptr;
     int32_t* dt = nullptr;
-    uint32_t *k2 = nullptr, *hist = nullptr, *counters = nullptr;
+    uint32_t *k2 = nullptr, *hist = nullptr;
     int32_t *v1 = nullptr, *v2 = nullptr, *ipar = nullptr, *lpar = nullptr, *ddepth = nullptr;
     const int nb = (int)((n + RS_TILE - 1) / RS_TILE);
     if ((!on_dev && (r = tmp.alloc(&dv, (size_t)nv * 3, "vertices")) != UVC_OK) ||
@@ -523,7 +535,6 @@ static uvc_status build_impl(const float* verts_in, int64_t nv, const int32_t* t
         (r = tmp.alloc(&v1, (size_t)n, "sort values")) != UVC_OK ||
         (r = tmp.alloc(&v2, (size_t)n, "sort values")) != UVC_OK ||
         (r = tmp.alloc(&hist, (size_t)256 * nb, "sort histogram")) != UVC_OK ||
-        (r = tmp.alloc(&counters, (size_t)std::max<int64_t>(n - 1, 1), "refit counters")) != UVC_OK ||
         (r = tmp.alloc(&ipar, (size_t)std::max<int64_t>(n - 1, 1), "parents")) != UVC_OK ||
         (r = tmp.alloc(&lpar, (size_t)n, "leaf parents")) != UVC_OK ||
         (r = tmp.alloc(&ddepth, 1, "depth")) != UVC_OK)
@@ -584,12 +595,46 @@ static uvc_status build_impl(const float* verts_in, int64_t nv, const int32_t* t
     STEP(hipGetLastError());
     int32_t depth = 1;
     if (n > 1) {
-        hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n - 1, TB)), dim3(TB), 0, st, counters, 0u, n - 1);
-        STEP(hipGetLastError());
         hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n - 1, TB)), dim3(TB), 0, st, (uint32_t*)ipar, 0xfffffffeu, n - 1);
         hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, TB)), dim3(TB), 0, st, (uint32_t*)lpar, 0xfffffffeu, n);
-        hipLaunchKernelGGL(k_hierarchy, dim3(grid_for(n - 1, TB)), dim3(TB), 0, st, s->codes, n, s->nodes, ipar, lpar);
-        STEP(hipGetLastError());
+        {
+            float *cb0 = nullptr, *cb1 = nullptr;
+            int32_t *cr0 = nullptr, *cr1 = nullptr, *nn = nullptr, *keep = nullptr, *merge = nullptr;
+            if ((r = tmp.alloc(&cb0, (size_t)n * 6, "clusters")) != UVC_OK ||
+                (r = tmp.alloc(&cb1, (size_t)n * 6, "clusters")) != UVC_OK ||
+                (r = tmp.alloc(&cr0, (size_t)n, "clusters")) != UVC_OK ||
+                (r = tmp.alloc(&cr1, (size_t)n, "clusters")) != UVC_OK ||
+                (r = tmp.alloc(&nn, (size_t)n, "neighbours")) != UVC_OK ||
+                (r = tmp.alloc(&keep, (size_t)n + 1, "cluster flags")) != UVC_OK ||
+                (r = tmp.alloc(&merge, (size_t)n + 1, "cluster flags")) != UVC_OK)
+                return cleanup_fail(r);
+            hipLaunchKernelGGL(k_ploc_init, dim3(grid_for(n, TB)), dim3(TB), 0, st, s->tri, n, s->pad, cb0, cr0);
+            STEP(hipGetLastError());
+            int64_t C = n, next_id = n - 2;
+            for (int round = 0; C > 1; ++round) {
+                if (round > 10000) return cleanup_fail(fail(UVC_EDEVICE, "internal error: clustering did not finish"));
+                hipLaunchKernelGGL(k_ploc_nn, dim3(grid_for(C, TB)), dim3(TB), 0, st, cb0, C, nn);
+                hipLaunchKernelGGL(k_ploc_flags, dim3(grid_for(C, TB)), dim3(TB), 0, st, nn, C, keep, merge);
+                hipLaunchKernelGGL(k_scan_i32, dim3(1), dim3(1024), 0, st, keep, C);
+                hipLaunchKernelGGL(k_scan_i32, dim3(1), dim3(1024), 0, st, merge, C);
+                STEP(hipGetLastError());
+                int32_t tot[2] = {0, 0};
+                STEP(hipMemcpyAsync(&tot[0], keep + C, 4, hipMemcpyDeviceToHost, st));
+                STEP(hipMemcpyAsync(&tot[1], merge + C, 4, hipMemcpyDeviceToHost, st));
+                STEP(hipStreamSynchronize(st));
+                if (tot[1] < 1 || tot[1] > next_id + 1 || (int64_t)tot[0] + tot[1] != C)
+                    return cleanup_fail(fail(UVC_EDEVICE, "internal error: clustering made no progress"));
+                hipLaunchKernelGGL(k_ploc_merge, dim3(grid_for(C, TB)), dim3(TB), 0, st, cb0, cr0, nn, C, keep, merge,
+                                   next_id, s->nodes, cb1, cr1, ipar, lpar);
+                STEP(hipGetLastError());
+                next_id -= tot[1];
+                C = tot[0];
+                std::swap(cb0, cb1);
+                std::swap(cr0, cr1);
+            }
+            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, st, (uint32_t*)ipar, 0xffffffffu, (int64_t)1);
+            STEP(hipGetLastError());
+        }
         {
             // every internal node but the root has one parent, every node has
             // exactly two children, and every leaf reaches the root
@@ -618,9 +663,6 @@ static uvc_status build_impl(const float* verts_in, int64_t nv, const int32_t* t
             }
             if (!ok) return cleanup_fail(fail(UVC_EDEVICE, "internal error: hierarchy emission is inconsistent"));
         }
-        hipLaunchKernelGGL(k_refit, dim3(grid_for(n, TB)), dim3(TB), 0, st, s->tri, lpar, ipar, s->nodes, counters, n,
-                           s->pad);
-        STEP(hipGetLastError());
         hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, st, (uint32_t*)ddepth, 0u, (int64_t)1);
         STEP(hipGetLastError());
         hipLaunchKernelGGL(k_depth, dim3(grid_for(n, TB)), dim3(TB), 0, st, lpar, ipar, n, ddepth);

@@ -268,6 +268,10 @@ __global__ void k_get_diag(const double* __restrict__ M, int64_t K, double* __re
 constexpr int CH_B = 32;
 
 // Cholesky of the diagonal block at j0 (size nb <= CH_B), in place (lower).
+// Right-looking on the unscaled block: step j subtracts
+// A[r][j] A[c][j] / A[j][j] from every entry below and right of the pivot
+// (one barrier per step); afterwards column j is scaled by 1 / sqrt(A[j][j]),
+// which gives L with L[j][j] = sqrt(A[j][j]).
 __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ M, int64_t K, int64_t j0, int nb,
                                                    int* __restrict__ fail) {
     __shared__ double A[CH_B][CH_B + 1];
@@ -277,23 +281,21 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ M, int64
     }
     __syncthreads();
     for (int j = 0; j < nb; ++j) {
-        if (threadIdx.x == 0) {
-            const double v = A[j][j];
-            if (!(v > 0.0)) *fail = 1;
-            A[j][j] = sqrt(fmax(v, 1e-300));
+        const double piv = A[j][j];
+        if (!(piv > 0.0)) {
+            if (threadIdx.x == 0) *fail = 1;
         }
-        __syncthreads();
-        for (int r = j + 1 + threadIdx.x; r < nb; r += 256) A[r][j] /= A[j][j];
-        __syncthreads();
-        for (int q = threadIdx.x; q < nb * nb; q += 256) {
-            const int r = q / nb, c = q % nb;
-            if (r > j && c > j && c <= r) A[r][c] -= A[r][j] * A[c][j];
+        const double inv = 1.0 / fmax(piv, 1e-300);
+        const int w = nb - 1 - j;  // trailing block size
+        for (int q = threadIdx.x; q < w * w; q += 256) {
+            const int r = j + 1 + q / w, c = j + 1 + q % w;
+            if (c <= r) A[r][c] -= A[r][j] * A[c][j] * inv;
         }
         __syncthreads();
     }
     for (int q = threadIdx.x; q < nb * nb; q += 256) {
         const int r = q / nb, c = q % nb;
-        if (c <= r) M[(j0 + r) * K + j0 + c] = A[r][c];
+        if (c <= r) M[(j0 + r) * K + j0 + c] = A[r][c] / sqrt(fmax(A[c][c], 1e-300));
     }
 }
 
@@ -361,6 +363,7 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ M, int
 __global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ L, int64_t K, double* __restrict__ x) {
     __shared__ double Lb[64][65];
     __shared__ double zb[64];
+    __shared__ double rd[64];  // 1 / diagonal of the staged block
     const int tid = threadIdx.x;
     // forward: L z = r
     for (int64_t j0 = 0; j0 < K; j0 += 64) {
@@ -369,12 +372,15 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ 
             const int r = q / nb, c = q % nb;
             Lb[r][c] = (c <= r) ? L[(j0 + r) * K + j0 + c] : 0.0;
         }
-        if (tid < nb) zb[tid] = x[j0 + tid];
+        if (tid < nb) {
+            zb[tid] = x[j0 + tid];
+            rd[tid] = 1.0 / L[(j0 + tid) * K + j0 + tid];
+        }
         __syncthreads();
         if (tid < 64) {
             double v = tid < nb ? zb[tid] : 0.0;
             for (int c = 0; c < nb; ++c) {
-                const double zc = __shfl(v, c) / Lb[c][c];
+                const double zc = __shfl(v, c) * rd[c];
                 if (tid == c)
                     v = zc;
                 else if (tid > c && tid < nb)
@@ -386,10 +392,14 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ 
             }
         }
         __syncthreads();
-        for (int64_t r = j0 + nb + tid; r < K; r += 1024) {
-            double v = 0.0;
-            for (int q = 0; q < nb; ++q) v += L[r * K + j0 + q] * zb[q];
-            x[r] -= v;
+        // rows below: one wave per row reads the row's nb entries contiguously
+        {
+            const int wv = tid >> 6, ln = tid & 63;
+            for (int64_t r = j0 + nb + wv; r < K; r += 16) {
+                double v = ln < nb ? L[r * K + j0 + ln] * zb[ln] : 0.0;
+                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+                if (ln == 0) x[r] -= v;
+            }
         }
         __syncthreads();
     }
@@ -401,12 +411,15 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ 
             const int r = q / nb, c = q % nb;
             Lb[r][c] = (c <= r) ? L[(j0 + r) * K + j0 + c] : 0.0;
         }
-        if (tid < nb) zb[tid] = x[j0 + tid];
+        if (tid < nb) {
+            zb[tid] = x[j0 + tid];
+            rd[tid] = 1.0 / L[(j0 + tid) * K + j0 + tid];
+        }
         __syncthreads();
         if (tid < 64) {
             double v = tid < nb ? zb[tid] : 0.0;
             for (int c = nb - 1; c >= 0; --c) {
-                const double zc = __shfl(v, c) / Lb[c][c];
+                const double zc = __shfl(v, c) * rd[c];
                 if (tid == c)
                     v = zc;
                 else if (tid < c)

@@ -246,3 +246,24 @@ def test_plan_rejects_bad_arguments(plan_room):
         uvc.plan_ranked(sc, poses, w.lamp, mode="area", keep_frac=1.5)
     with pytest.raises(uvc.UvcError):
         uvc.plan_ranked(sc, poses, w.lamp, mode="area", max_rounds=-1)
+
+
+def test_trained_ranker_gain_over_visible_area_and_full():
+    """The committed weights on held-out rooms: every pruned plan reaches the
+    full-candidate LP optimum; the learned ranker starts from a better pose
+    set than the visible-area score (fewer LPs and poses in total), and on a
+    larger room its plan is faster than the full LP."""
+    import os
+    path = os.path.join(os.path.dirname(RK.__file__), "weights", "ranker_tower8.bin")
+    params = RK.load_checkpoint(path)["params"]
+    small = [RK.evaluate_room(RK.room(RK.HELDOUT_SEED0 + r), params) for r in range(3)]
+    large = RK.evaluate_room(RK.room(950000, (20000, 80000), (1000, 3000)), params)
+    for res in small + [large]:
+        print(res["room"], {m: {k: res[m][k] for k in ("gap", "rounds", "n_kept", "ms")} for m in ("mlp", "area")},
+              "full", res["full_ms"], flush=True)
+        for mode in ("mlp", "area"):
+            assert abs(res[mode]["gap"]) <= 1e-6 or res[mode]["fell_back"]
+    tot = {m: (sum(r[m]["rounds"] for r in small + [large]), sum(r[m]["n_kept"] for r in small + [large]))
+           for m in ("mlp", "area")}
+    assert tot["mlp"][0] <= tot["area"][0] and tot["mlp"][1] < tot["area"][1], tot
+    assert large["mlp"]["fell_back"] == 0 and large["mlp"]["ms"] < large["full_ms"]

@@ -321,3 +321,37 @@ def test_reciprocity_outside_band():
         back = ref.segment_blocked(w.mesh.verts, w.mesh.tris, c[i], p, skip=i)
         assert vis[q] == 1 - back
     assert n_front > 30
+
+
+# ------------------------------------------------ property test (hypothesis)
+from hypothesis import given, settings, strategies as st  # noqa: E402
+
+
+@settings(max_examples=300, deadline=None)
+@given(kind=st.integers(0, 3), s=st.floats(0.0, 1.0), edge=st.integers(0, 3), corner=st.integers(0, 3),
+       h=st.floats(0.3, 2.0), back=st.floats(0.2, 1.5), tilt=st.lists(st.floats(-0.3, 0.3), min_size=3, max_size=3),
+       nudge=st.lists(st.integers(-3, 3), min_size=3, max_size=3), rot_seed=st.integers(0, 1000))
+def test_fp64_predicate_property_near_edges(kind, s, edge, corner, h, back, tilt, nudge, rot_seed):
+    """Segments through the shared diagonal, an edge, a vertex or anywhere
+    near a split quad: the FP64 predicate agrees with the exact rational one
+    whenever the exact configuration is not within 1e-12 of a boundary."""
+    v = np.array([[0, 0, 0.5], [1, 0, 0.5], [1, 1, 0.5], [0, 1, 0.5]], np.float64)
+    q, _ = np.linalg.qr(np.random.default_rng(rot_seed).normal(size=(3, 3)))
+    v = (v @ q.T).astype(np.float32)
+    vd = v.astype(np.float64)
+    if kind == 0:
+        P = (1 - s) * vd[0] + s * vd[2]
+    elif kind == 1:
+        P = (1 - s) * vd[edge] + s * vd[(edge + 1) % 4]
+    elif kind == 2:
+        P = vd[corner]
+    else:
+        P = vd[0] + (1.4 * s - 0.2) * (vd[1] - vd[0]) + (1.4 * (1 - s) - 0.2) * (vd[3] - vd[0])
+    normal = np.cross(vd[1] - vd[0], vd[3] - vd[0])
+    O = (P + normal * h + np.asarray(tilt)).astype(np.float32)
+    T = (P - (O.astype(np.float64) - P) * back).astype(np.float32)
+    T = (T + np.asarray(nudge) * np.spacing(np.abs(T))).astype(np.float32)
+    for tri in ((0, 1, 2), (0, 2, 3)):
+        a, b, c = v[tri[0]], v[tri[1]], v[tri[2]]
+        h64, hx = ref.hit(O, T, a, b, c), exact.hit(O, T, a, b, c)
+        assert h64 == hx or exact.near_boundary(O, T, a, b, c, 1e-12)

@@ -53,7 +53,9 @@ constexpr int ELEM_WORDS = 8;
 // centroid is exactly zero (the predicate can never report those).  The
 // traversal may then stop each segment rho_t = rho_n (1 - 2^-10) short of its
 // target: every point it skips lies inside the ball.
-constexpr float NEAR_SCALE = 1.0f;
+// (Measured on the ward: 0.25 costs 0.07 near-list tests per segment and
+// is 3 % faster than 1.0, which costs 1.25; 2.0 is 28 % slower.)
+constexpr float NEAR_SCALE = 0.25f;
 // Hierarchy node, 64 bytes: left box lo xyz hi xyz, right box lo xyz hi xyz,
 // left ref, right ref (>= 0 internal, < 0 leaf slot ~ref), hint axis/order,
 // hint split coordinate.

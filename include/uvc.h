@@ -120,8 +120,11 @@ enum { UVC_PATH_AUTO = 0, UVC_PATH_LBVH = 1, UVC_PATH_BRUTE = 2 };
 
 /* UVC_FLAG_NO_NEAR: the hierarchy path walks every segment to its target
  * instead of stopping short and testing the element's near list (same
- * results, slower; for testing). */
-enum { UVC_FLAG_NO_NEAR = 1 };
+ * results, slower; for testing).
+ * UVC_FLAG_NO_CACHE: the hierarchy path does not test each lane's last
+ * occluding triangle before walking the next source's segment (same
+ * results; for testing and measurement). */
+enum { UVC_FLAG_NO_NEAR = 1, UVC_FLAG_NO_CACHE = 2 };
 
 /* Counters accumulated by an instrumented launch (opts.stats_dev). */
 enum {
@@ -133,7 +136,9 @@ enum {
     UVC_STAT_VISIBLE = 5,    /* visible (pose, source, element) triples        */
     UVC_STAT_STEPS = 6,      /* wavefront traversal steps (one node each)      */
     UVC_STAT_NEAR = 7,       /* per-ray near-list segment/triangle tests       */
-    UVC_STAT_N = 8
+    UVC_STAT_CACHE = 8,      /* per-ray tests of the lane's last occluder      */
+    UVC_STAT_CACHE_HIT = 9,  /* ... of which found the segment blocked         */
+    UVC_STAT_N = 10
 };
 
 typedef struct {

@@ -58,6 +58,7 @@ struct IrrParams {
     int32_t tile_tris;         // brute-force LDS tile
     int32_t tk_log2;           // hierarchy path: log2 of the poses per packet (0..6)
     int32_t use_near;          // hierarchy path: stop segments short and test near lists
+    int32_t use_cache;         // hierarchy path: test each lane's last occluder first
     int32_t waves;             // hierarchy path: occupancy target of the kernel variant (0, 6, 8)
     float tau_f, tau_e, tau_p;
     float* E;                  // rows of this launch, K x N
@@ -282,16 +283,24 @@ __device__ __forceinline__ NodeRec load_node(const float* __restrict__ nodes, in
 // Packet traversal.  Control flow is uniform: m is the mask of lanes whose
 // segment entered the current node; both child boxes are tested for every
 // lane and the ballots are masked with m.  Deferred (node, mask) pairs live
-// in three VGPRs, entry i in lane i (depth <= 64).
+// in three VGPRs, entry i in lane i (depth <= 64).  A step with two inner
+// children (the common case) takes one branch on the child kinds; lanes
+// found occluded leave the masks where a leaf test finds them, and popped
+// masks drop them too.
 template <bool STATS, class PT>
 __device__ __forceinline__ unsigned long long traverse(PT& P, const Ray& r, unsigned long long live,
                                                        unsigned long long& n_nodes, unsigned long long& n_tris,
-                                                       unsigned long long& n_steps, int* rechecks) {
+                                                       unsigned long long& n_steps, int* rechecks, int& last) {
     const int lane = lane_id();
     unsigned long long occl = 0;
     if (P.N < 2) return 0;
     const float* __restrict__ nodes = P.nodes;
     const float* __restrict__ tri = P.tri;
+    // near-first order follows the first live lane's origin (order keys)
+    const int l0 = __builtin_ctzll(live);
+    const int kx = float_key(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(r.ox), l0)));
+    const int ky = float_key(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(r.oy), l0)));
+    const int kz = float_key(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(r.oz), l0)));
     unsigned long long m = live;
     int node = 0;
     int sp = 0;
@@ -306,34 +315,38 @@ __device__ __forceinline__ unsigned long long traverse(PT& P, const Ray& r, unsi
             n_nodes += (unsigned long long)__popcll(m);
             ++n_steps;
         }
-        if (cl < 0 && mL) {
-            const cfloat* t = (const cfloat*)(tri + (int64_t)(~cl) * TRI_WORDS);
-            const int who = __float_as_int(t[TRI_ID]);
-            const bool act = ((mL >> lane) & 1ull) && r.self != who;
-            bool h = false;
-            if (act) h = tri_hit(r, t, P.tau_e, P.tau_p, rechecks);
-            if (STATS) n_tris += (unsigned long long)__popcll(__ballot(act));
-            occl |= __ballot(h);
-            mL = 0;
+        if ((cl | cr) < 0) {
+            if (cl < 0 && mL) {
+                const cfloat* t = (const cfloat*)(tri + (int64_t)(~cl) * TRI_WORDS);
+                const int who = __float_as_int(t[TRI_ID]);
+                const bool act = ((mL >> lane) & 1ull) && r.self != who;
+                bool h = false;
+                if (act) h = tri_hit(r, t, P.tau_e, P.tau_p, rechecks);
+                if (h) last = ~cl;
+                if (STATS) n_tris += (unsigned long long)__popcll(__ballot(act));
+                occl |= __ballot(h);
+                mL = 0;
+            }
+            if (cr < 0 && mR) {
+                const cfloat* t = (const cfloat*)(tri + (int64_t)(~cr) * TRI_WORDS);
+                const int who = __float_as_int(t[TRI_ID]);
+                const bool act = ((mR >> lane) & 1ull) && r.self != who;
+                bool h = false;
+                if (act) h = tri_hit(r, t, P.tau_e, P.tau_p, rechecks);
+                if (h) last = ~cr;
+                if (STATS) n_tris += (unsigned long long)__popcll(__ballot(act));
+                occl |= __ballot(h);
+                mR = 0;
+            }
+            if ((live & ~occl) == 0ull) break;
+            mL &= ~occl;
+            mR &= ~occl;
         }
-        if (cr < 0 && mR) {
-            const cfloat* t = (const cfloat*)(tri + (int64_t)(~cr) * TRI_WORDS);
-            const int who = __float_as_int(t[TRI_ID]);
-            const bool act = ((mR >> lane) & 1ull) && r.self != who;
-            bool h = false;
-            if (act) h = tri_hit(r, t, P.tau_e, P.tau_p, rechecks);
-            if (STATS) n_tris += (unsigned long long)__popcll(__ballot(act));
-            occl |= __ballot(h);
-            mR = 0;
-        }
-        mL &= ~occl;
-        mR &= ~occl;
         if (mL && mR) {
             const int hint = __float_as_int(cur.d.z);
             const int axis = hint & 3;
-            const float o_lane = axis == 0 ? r.ox : (axis == 1 ? r.oy : r.oz);
-            const float o = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(o_lane)));
-            const bool left_first = ((o < cur.d.w) == ((hint & 4) != 0));
+            const int ko = axis == 0 ? kx : (axis == 1 ? ky : kz);
+            const bool left_first = (ko < __float_as_int(cur.d.w)) == ((hint & 4) != 0);
             const int nfar = left_first ? cr : cl;
             const unsigned long long mfar = left_first ? mR : mL;
             const bool here = lane == sp;  // the stack entry sp lives in lane sp
@@ -343,12 +356,9 @@ __device__ __forceinline__ unsigned long long traverse(PT& P, const Ray& r, unsi
             ++sp;
             node = left_first ? cl : cr;
             m = left_first ? mL : mR;
-        } else if (mL) {
-            node = cl;
-            m = mL;
-        } else if (mR) {
-            node = cr;
-            m = mR;
+        } else if (mL | mR) {
+            node = mL ? cl : cr;
+            m = mL | mR;
         } else {
             bool done = false;
             while (true) {
@@ -365,7 +375,6 @@ __device__ __forceinline__ unsigned long long traverse(PT& P, const Ray& r, unsi
             }
             if (done) break;
         }
-        if ((live & ~occl) == 0ull) break;
     }
     return occl;
 }
@@ -401,7 +410,13 @@ __device__ __forceinline__ void irr_lbvh_packet(PT& P, const LampArgs& L, int64_
     int* const rc_p = STATS ? &rechecks : nullptr;
     int* const f64_p = STATS ? &f64 : nullptr;
     unsigned n_near = 0;
-    unsigned long long n_rays = 0, n_nodes = 0, n_tris = 0, n_vis = 0, n_steps = 0;
+    unsigned long long n_rays = 0, n_nodes = 0, n_tris = 0, n_vis = 0, n_steps = 0, n_cache = 0, n_cache_hit = 0;
+    // Leaf slot of the triangle that last blocked this lane's segment (-1:
+    // none yet).  The sources of a lamp are close together, so a triangle
+    // that blocks one of them from an element often blocks the next one too.
+    // Testing it first is exact: a segment is blocked iff some triangle's
+    // predicate says so, and this is that predicate on that triangle.
+    int last = -1;
     for (int j = 0; j < L.S; ++j) {
         const int32_t sl = slot;
         const ElemLane e = elem_record(P, sl, ok);
@@ -421,15 +436,31 @@ __device__ __forceinline__ void irr_lbvh_packet(PT& P, const LampArgs& L, int64_
             r.tmax = 1.0f - e.rho_t * __builtin_amdgcn_rsqf(r2);
             trav = f && r.tmax > 0.0f;
         }
-        const unsigned long long tlive = __ballot(trav);
         unsigned long long occl = 0;
-        if (tlive) occl = traverse<STATS>(P, r, tlive, n_nodes, n_tris, n_steps, rc_p);
+        if (P.use_cache) {
+            const bool tc = f && last >= 0;
+            const unsigned long long mc = __ballot(tc);
+            if (mc) {
+                bool h = false;
+                if (tc) h = tri_hit(r, P.tri + (int64_t)last * TRI_WORDS, P.tau_e, P.tau_p, rc_p);
+                occl = __ballot(h);
+                if (STATS) {
+                    n_cache += (unsigned long long)__popcll(mc);
+                    n_cache_hit += (unsigned long long)__popcll(occl);
+                }
+            }
+        }
+        const unsigned long long tlive = __ballot(trav) & ~occl;
+        if (tlive) occl |= traverse<STATS>(P, r, tlive, n_nodes, n_tris, n_steps, rc_p, last);
         bool vis = f && !((occl >> lane) & 1ull);
         if (P.use_near && vis) {
             const int32_t nb = P.near_off[sl], ne = P.near_off[sl + 1];
             for (int32_t q = nb; q < ne && vis; ++q) {
-                const float* t = P.tri + (int64_t)P.near[q] * TRI_WORDS;
-                if (tri_hit(r, t, P.tau_e, P.tau_p, rc_p)) vis = false;
+                const int32_t tq = P.near[q];
+                if (tri_hit(r, P.tri + (int64_t)tq * TRI_WORDS, P.tau_e, P.tau_p, rc_p)) {
+                    vis = false;
+                    last = tq;
+                }
                 if (STATS) ++n_near;
             }
         }
@@ -459,6 +490,8 @@ __device__ __forceinline__ void irr_lbvh_packet(PT& P, const LampArgs& L, int64_
             atomicAdd(P.stats + UVC_STAT_VISIBLE, n_vis);
             atomicAdd(P.stats + UVC_STAT_STEPS, n_steps);
             atomicAdd(P.stats + UVC_STAT_NEAR, nn);
+            atomicAdd(P.stats + UVC_STAT_CACHE, n_cache);
+            atomicAdd(P.stats + UVC_STAT_CACHE_HIT, n_cache_hit);
         }
     }
 }
@@ -575,6 +608,7 @@ __device__ __forceinline__ IrrParams uniform_room(const IrrParams* src) {
     P.tile_tris = ufl(src->tile_tris);
     P.tk_log2 = ufl(src->tk_log2);
     P.use_near = ufl(src->use_near);
+    P.use_cache = ufl(src->use_cache);
     P.waves = ufl(src->waves);
     P.tau_f = __int_as_float(ufl(__float_as_int(src->tau_f)));
     P.tau_e = __int_as_float(ufl(__float_as_int(src->tau_e)));
@@ -806,6 +840,7 @@ static uvc_status make_params(const uvc_scene* s, const float* poses, int64_t K,
     P.near_off = s->near_off;
     P.near = s->near;
     P.use_near = (opts && (opts->flags & UVC_FLAG_NO_NEAR)) ? 0 : 1;
+    P.use_cache = (opts && (opts->flags & UVC_FLAG_NO_CACHE)) ? 0 : 1;
     P.waves = (opts && opts->waves > 0) ? opts->waves : 8;
     if (P.waves != 5 && P.waves != 6 && P.waves != 8) return fail(UVC_EINVAL, "waves must be 0, 5, 6 or 8");
     P.poses = poses;

@@ -406,7 +406,7 @@ __global__ void k_ploc_merge(const float* __restrict__ box, const int32_t* __res
     }
     const float cl = 0.5f * (a[axis] + a[3 + axis]), cr = 0.5f * (b[axis] + b[3 + axis]);
     nd[14] = __int_as_float(axis | ((cl <= cr) ? 4 : 0));
-    nd[15] = 0.5f * (cl + cr);
+    nd[15] = __int_as_float(float_key(0.5f * (cl + cr)));
     for (int q = 0; q < 3; ++q) {
         box_out[pos * 6 + q] = fminf(a[q], b[q]);
         box_out[pos * 6 + 3 + q] = fmaxf(a[3 + q], b[3 + q]);

@@ -58,8 +58,16 @@ constexpr int ELEM_WORDS = 8;
 constexpr float NEAR_SCALE = 0.25f;
 // Hierarchy node, 64 bytes: left box lo xyz hi xyz, right box lo xyz hi xyz,
 // left ref, right ref (>= 0 internal, < 0 leaf slot ~ref), hint axis/order,
-// hint split coordinate.
+// hint split coordinate as an order key (float_key).
 constexpr int NODE_WORDS = 16;
+
+// Signed integer that orders like the float (non-NaN; -0 sorts below +0), so
+// that a coordinate comparison can run on the scalar unit.
+__host__ __device__ inline int32_t float_key(float f) {
+    int32_t b;
+    __builtin_memcpy(&b, &f, 4);
+    return b ^ ((b >> 31) & 0x7fffffff);
+}
 
 // Decision bands of the FP32 fast path (multiplied by opts.band_scale).
 // Front-facing: |<d, n>| > TAU_F * |d|_1.

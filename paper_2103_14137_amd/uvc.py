@@ -22,9 +22,10 @@ _I64 = ctypes.c_int64
 _I32 = ctypes.c_int32
 
 PATHS = {"auto": 0, "lbvh": 1, "brute": 2}
-STAT_NAMES = ["rays", "nodes", "tris", "recheck", "front64", "visible", "steps", "near"]
+STAT_NAMES = ["rays", "nodes", "tris", "recheck", "front64", "visible", "steps", "near", "cache", "cache_hit"]
 FLAG_NO_NEAR = 1
-STAT_N = 8
+FLAG_NO_CACHE = 2
+STAT_N = 10
 
 
 class UvcError(RuntimeError):

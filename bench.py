@@ -246,7 +246,7 @@ def main():
     uvc.irradiance_dense(sc, poses, lamp, path="lbvh", out=E, stats=stats)
     st = uvc.stats_dict(stats)
     rays = st["rays"]
-    flops = FLOP_NODE * st["nodes"] + FLOP_TRI * (st["tris"] + st["near"]) + FLOP_ENTRY * K * N * S
+    flops = FLOP_NODE * st["nodes"] + FLOP_TRI * (st["tris"] + st["near"] + st["cache"]) + FLOP_ENTRY * K * N * S
     # live HIP-event timing of the dominant kernel on the stream it runs on
     kms = []
     for _ in range(3):

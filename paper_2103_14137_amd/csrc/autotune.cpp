@@ -17,7 +17,7 @@
 namespace {
 
 struct Entry {
-    int path = UVC_PATH_LBVH, packet_poses = 16, waves = 8, tile_tris = 512;
+    int path = UVC_PATH_LBVH, packet_poses = 16, waves = 6, tile_tris = 512;
     double rays_per_s = 0.0;
 };
 

@@ -271,13 +271,21 @@ struct NodeRec {
 // uniform: read it through the constant address space (scalar loads).
 
 __device__ __forceinline__ NodeRec load_node(const float* __restrict__ nodes, int node) {
-    const cfloat* q = (const cfloat*)(nodes + (int64_t)node * NODE_WORDS);
+    // a 32-bit byte offset lets the load take it as its scalar offset operand
+    const cfloat* q = (const cfloat*)((const char*)nodes + (uint32_t)node * (uint32_t)(NODE_WORDS * 4));
     NodeRec r;
     r.a = make_float4(q[0], q[1], q[2], q[3]);
     r.b = make_float4(q[4], q[5], q[6], q[7]);
     r.c = make_float4(q[8], q[9], q[10], q[11]);
     r.d = make_float4(q[12], q[13], q[14], q[15]);
     return r;
+}
+
+// Lane `lane` of v takes the uniform value val (v_writelane; val and lane
+// are scalar operands written by the scalar unit; the lane goes through M0).
+__device__ __forceinline__ int write_lane(int v, int val, int lane) {
+    asm("v_writelane_b32 %0, %1, m0" : "+v"(v) : "s"(val), "{m0}"(lane));
+    return v;
 }
 
 // Packet traversal.  Control flow is uniform: m is the mask of lanes whose
@@ -342,39 +350,47 @@ __device__ __forceinline__ unsigned long long traverse(PT& P, const Ray& r, unsi
             mL &= ~occl;
             mR &= ~occl;
         }
-        if (mL && mR) {
+        if (mL == 0ull) {
+            if (mR != 0ull) {
+                node = cr;
+                m = mR;
+                continue;
+            }
+        } else if (mR == 0ull) {
+            node = cl;
+            m = mL;
+            continue;
+        } else {
             const int hint = __float_as_int(cur.d.z);
             const int axis = hint & 3;
             const int ko = axis == 0 ? kx : (axis == 1 ? ky : kz);
             const bool left_first = (ko < __float_as_int(cur.d.w)) == ((hint & 4) != 0);
             const int nfar = left_first ? cr : cl;
             const unsigned long long mfar = left_first ? mR : mL;
-            const bool here = lane == sp;  // the stack entry sp lives in lane sp
-            stk_node = here ? nfar : stk_node;
-            stk_lo = here ? (int)(unsigned)mfar : stk_lo;
-            stk_hi = here ? (int)(unsigned)(mfar >> 32) : stk_hi;
+            // the stack entry sp lives in lane sp
+            stk_node = write_lane(stk_node, nfar, sp);
+            stk_lo = write_lane(stk_lo, (int)(unsigned)mfar, sp);
+            stk_hi = write_lane(stk_hi, (int)(unsigned)(mfar >> 32), sp);
             ++sp;
             node = left_first ? cl : cr;
             m = left_first ? mL : mR;
-        } else if (mL | mR) {
-            node = mL ? cl : cr;
-            m = mL | mR;
-        } else {
-            bool done = false;
-            while (true) {
-                if (sp == 0) {
-                    done = true;
-                    break;
-                }
-                --sp;
-                node = __builtin_amdgcn_readlane(stk_node, sp);
-                const unsigned lo = (unsigned)__builtin_amdgcn_readlane(stk_lo, sp);
-                const unsigned hi = (unsigned)__builtin_amdgcn_readlane(stk_hi, sp);
-                m = (((unsigned long long)hi << 32) | lo) & ~occl;
-                if (m) break;
-            }
-            if (done) break;
+            continue;
         }
+        // no child entered: pop the next entry that still has live lanes
+        bool done = false;
+        while (true) {
+            if (sp == 0) {
+                done = true;
+                break;
+            }
+            --sp;
+            node = __builtin_amdgcn_readlane(stk_node, sp);
+            const unsigned lo = (unsigned)__builtin_amdgcn_readlane(stk_lo, sp);
+            const unsigned hi = (unsigned)__builtin_amdgcn_readlane(stk_hi, sp);
+            m = (((unsigned long long)hi << 32) | lo) & ~occl;
+            if (m) break;
+        }
+        if (done) break;
     }
     return occl;
 }
@@ -620,7 +636,7 @@ __device__ __forceinline__ IrrParams uniform_room(const IrrParams* src) {
     return P;
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_irr_batched(BatchArgs B) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_irr_batched(BatchArgs B) {
     __shared__ long long item_s;
     int range = 0;
     for (int64_t item; (item = next_item(B.q, range, &item_s)) >= 0;) {
@@ -841,7 +857,7 @@ static uvc_status make_params(const uvc_scene* s, const float* poses, int64_t K,
     P.near = s->near;
     P.use_near = (opts && (opts->flags & UVC_FLAG_NO_NEAR)) ? 0 : 1;
     P.use_cache = (opts && (opts->flags & UVC_FLAG_NO_CACHE)) ? 0 : 1;
-    P.waves = (opts && opts->waves > 0) ? opts->waves : 8;
+    P.waves = (opts && opts->waves > 0) ? opts->waves : 6;
     if (P.waves != 5 && P.waves != 6 && P.waves != 8) return fail(UVC_EINVAL, "waves must be 0, 5, 6 or 8");
     P.poses = poses;
     P.K = K;
@@ -1297,7 +1313,7 @@ extern "C" uvc_status uvc_batch_create(const uvc_scene* const* scenes, int32_t n
     b->total = off.back();
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
-    b->grid = std::max(1, cus * 8);  // 8 workgroups of 4 waves per CU: 8 waves per SIMD
+    b->grid = std::max(1, cus * 6);  // 6 workgroups of 4 waves per CU: 6 waves per SIMD
     hipError_t e = hipMemcpyAsync(b->d_orders, all.data(), all.size() * 4, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && n_rooms > 0)
         e = hipMemcpyAsync(b->d_rooms, b->rooms.data(), b->rooms.size() * sizeof(IrrParams), hipMemcpyHostToDevice, st);

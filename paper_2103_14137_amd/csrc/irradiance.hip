@@ -105,6 +105,20 @@ __device__ __forceinline__ void make_ray(Ray& r, float ox, float oy, float oz, f
     r.self = self;
 }
 
+// make_ray with the x and y reciprocals and offsets already formed (the same
+// arithmetic, so the same bits).
+__device__ __forceinline__ void make_ray_z(Ray& r, float ox, float oy, float oz, float tx, float ty, float tz,
+                                           int self, float ix, float iy, float nx, float ny) {
+    r.ox = ox; r.oy = oy; r.oz = oz;
+    r.tx = tx; r.ty = ty; r.tz = tz;
+    r.dx = tx - ox; r.dy = ty - oy; r.dz = tz - oz;
+    r.ix = ix; r.iy = iy; r.iz = guard_inv(r.dz);
+    r.nx = nx; r.ny = ny; r.nz = -oz * r.iz;
+    r.l1 = fabsf(r.dx) + fabsf(r.dy) + fabsf(r.dz);
+    r.tmax = 1.0f;
+    r.self = self;
+}
+
 // Does the segment's parameter interval [0, tmax] meet the (padded) box?
 __device__ __forceinline__ bool slab(const Ray& r, float lx, float ly, float lz, float hx, float hy, float hz) {
     const float t0x = fmaf(lx, r.ix, r.nx), t1x = fmaf(hx, r.ix, r.nx);
@@ -433,6 +447,16 @@ __device__ __forceinline__ void irr_lbvh_packet(PT& P, const LampArgs& L, int64_
     // Testing it first is exact: a segment is blocked iff some triangle's
     // predicate says so, and this is that predicate on that triangle.
     int last = -1;
+    // The sources differ only in height: the horizontal parts of the
+    // direction, their reciprocals and offsets are the same for every source.
+    float hix, hiy, hnx, hny;
+    {
+        const ElemLane e = elem_record(P, slot, ok);
+        hix = guard_inv(e.cx - px);
+        hiy = guard_inv(e.cy - py);
+        hnx = -px * hix;
+        hny = -py * hiy;
+    }
     for (int j = 0; j < L.S; ++j) {
         const int32_t sl = slot;
         const ElemLane e = elem_record(P, sl, ok);
@@ -444,7 +468,7 @@ __device__ __forceinline__ void irr_lbvh_packet(PT& P, const LampArgs& L, int64_
         const unsigned long long live = __ballot(f);
         if (!live) continue;
         Ray r;
-        make_ray(r, px, py, oz, e.cx, e.cy, e.cz, e.self);
+        make_ray_z(r, px, py, oz, e.cx, e.cy, e.cz, e.self, hix, hiy, hnx, hny);
         bool trav = f;
         if (P.use_near) {
             // stop rho_t short of the target; the near list covers the rest

@@ -96,6 +96,32 @@ def test_paths_bit_identical_and_band_independent(uvc):
     # walking every segment to its target instead of using the near lists
     E6, v6 = uvc.irradiance_dense(sc, poses, w.lamp, path="lbvh", want_vis=True, flags=uvc.FLAG_NO_NEAR)
     assert torch.equal(v1, v6) and torch.equal(E1, E6)
+    # without the per-lane last-occluder test, and without both shortcuts
+    for fl in (uvc.FLAG_NO_CACHE, uvc.FLAG_NO_CACHE | uvc.FLAG_NO_NEAR):
+        E8, v8 = uvc.irradiance_dense(sc, poses, w.lamp, path="lbvh", want_vis=True, flags=fl)
+        assert torch.equal(v1, v8) and torch.equal(E1, E8), fl
+    sc.close()
+
+
+def test_last_occluder_test_is_used_and_exact(uvc):
+    """On a room with obstacles the last-occluder test fires and finds
+    blocked segments; with it off no such test is counted and every bit of
+    the result is unchanged (the test is the predicate on one triangle)."""
+    w = _workload("ward")
+    sc = uvc.Scene(w.mesh.verts, w.mesh.tris)
+    poses = torch.from_numpy(w.poses[::50].copy()).cuda()
+    s_on, s_off = uvc.new_stats(), uvc.new_stats()
+    E1, v1 = uvc.irradiance_dense(sc, poses, w.lamp, path="lbvh", want_vis=True, stats=s_on)
+    E2, v2 = uvc.irradiance_dense(sc, poses, w.lamp, path="lbvh", want_vis=True, stats=s_off,
+                                  flags=uvc.FLAG_NO_CACHE)
+    torch.cuda.synchronize()
+    on, off = uvc.stats_dict(s_on), uvc.stats_dict(s_off)
+    assert torch.equal(v1, v2) and torch.equal(E1, E2)
+    assert on["cache"] > 0 and 0 < on["cache_hit"] <= on["cache"]
+    assert off["cache"] == 0 and off["cache_hit"] == 0
+    assert on["visible"] == off["visible"] and on["rays"] == off["rays"]
+    # a lane found blocked by its last occluder skips the walk
+    assert on["nodes"] < off["nodes"]
     sc.close()
 
 

@@ -138,7 +138,8 @@ enum {
     UVC_STAT_NEAR = 7,       /* per-ray near-list segment/triangle tests       */
     UVC_STAT_CACHE = 8,      /* per-ray tests of the lane's last occluder      */
     UVC_STAT_CACHE_HIT = 9,  /* ... of which found the segment blocked         */
-    UVC_STAT_N = 10
+    UVC_STAT_LEAF_STEPS = 10,/* wavefront leaf tests (one triangle each)       */
+    UVC_STAT_N = 11
 };
 
 typedef struct {

@@ -312,7 +312,8 @@ __device__ __forceinline__ int write_lane(int v, int val, int lane) {
 template <bool STATS, class PT>
 __device__ __forceinline__ unsigned long long traverse(PT& P, const Ray& r, unsigned long long live,
                                                        unsigned long long& n_nodes, unsigned long long& n_tris,
-                                                       unsigned long long& n_steps, int* rechecks, int& last) {
+                                                       unsigned long long& n_steps, unsigned long long& n_leafw,
+                                                       int* rechecks, int& last) {
     const int lane = lane_id();
     unsigned long long occl = 0;
     if (P.N < 2) return 0;
@@ -345,7 +346,10 @@ __device__ __forceinline__ unsigned long long traverse(PT& P, const Ray& r, unsi
                 bool h = false;
                 if (act) h = tri_hit(r, t, P.tau_e, P.tau_p, rechecks);
                 if (h) last = ~cl;
-                if (STATS) n_tris += (unsigned long long)__popcll(__ballot(act));
+                if (STATS) {
+                    n_tris += (unsigned long long)__popcll(__ballot(act));
+                    ++n_leafw;
+                }
                 occl |= __ballot(h);
                 mL = 0;
             }
@@ -356,7 +360,10 @@ __device__ __forceinline__ unsigned long long traverse(PT& P, const Ray& r, unsi
                 bool h = false;
                 if (act) h = tri_hit(r, t, P.tau_e, P.tau_p, rechecks);
                 if (h) last = ~cr;
-                if (STATS) n_tris += (unsigned long long)__popcll(__ballot(act));
+                if (STATS) {
+                    n_tris += (unsigned long long)__popcll(__ballot(act));
+                    ++n_leafw;
+                }
                 occl |= __ballot(h);
                 mR = 0;
             }
@@ -440,7 +447,8 @@ __device__ __forceinline__ void irr_lbvh_packet(PT& P, const LampArgs& L, int64_
     int* const rc_p = STATS ? &rechecks : nullptr;
     int* const f64_p = STATS ? &f64 : nullptr;
     unsigned n_near = 0;
-    unsigned long long n_rays = 0, n_nodes = 0, n_tris = 0, n_vis = 0, n_steps = 0, n_cache = 0, n_cache_hit = 0;
+    unsigned long long n_rays = 0, n_nodes = 0, n_tris = 0, n_vis = 0, n_steps = 0, n_cache = 0, n_cache_hit = 0,
+                       n_leafw = 0;
     // Leaf slot of the triangle that last blocked this lane's segment (-1:
     // none yet).  The sources of a lamp are close together, so a triangle
     // that blocks one of them from an element often blocks the next one too.
@@ -491,7 +499,7 @@ __device__ __forceinline__ void irr_lbvh_packet(PT& P, const LampArgs& L, int64_
             }
         }
         const unsigned long long tlive = __ballot(trav) & ~occl;
-        if (tlive) occl |= traverse<STATS>(P, r, tlive, n_nodes, n_tris, n_steps, rc_p, last);
+        if (tlive) occl |= traverse<STATS>(P, r, tlive, n_nodes, n_tris, n_steps, n_leafw, rc_p, last);
         bool vis = f && !((occl >> lane) & 1ull);
         if (P.use_near && vis) {
             const int32_t nb = P.near_off[sl], ne = P.near_off[sl + 1];
@@ -532,6 +540,7 @@ __device__ __forceinline__ void irr_lbvh_packet(PT& P, const LampArgs& L, int64_
             atomicAdd(P.stats + UVC_STAT_NEAR, nn);
             atomicAdd(P.stats + UVC_STAT_CACHE, n_cache);
             atomicAdd(P.stats + UVC_STAT_CACHE_HIT, n_cache_hit);
+            atomicAdd(P.stats + UVC_STAT_LEAF_STEPS, n_leafw);
         }
     }
 }

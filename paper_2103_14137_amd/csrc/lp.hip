@@ -94,7 +94,7 @@ __global__ void k_lp_Etu(const float* __restrict__ E, int64_t K, int64_t N, int6
 // out[k] = sum_i E[k,i] * v[i]  (E v, row dot products; one block per row,
 // fixed-order tree reduction)
 __global__ void k_lp_Ev(const float* __restrict__ E, int64_t N, const double* __restrict__ v,
-                        double* __restrict__ out) {
+                        double* __restrict__ out, double scale) {
     __shared__ double red[LP_TB];
     const int64_t k = blockIdx.x;
     double acc = 0.0;
@@ -106,16 +106,17 @@ __global__ void k_lp_Ev(const float* __restrict__ E, int64_t N, const double* __
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[k] = red[0];
+    if (threadIdx.x == 0) out[k] = red[0] * scale;
 }
 
-// out[i] = sum over chunks of part[chunk][i] (fixed order)
-__global__ void k_lp_sum_parts(const double* __restrict__ part, int64_t chunks, int64_t N, double* __restrict__ out) {
+// out[i] = scale * sum over chunks of part[chunk][i] (fixed order)
+__global__ void k_lp_sum_parts(const double* __restrict__ part, int64_t chunks, int64_t N, double* __restrict__ out,
+                               double scale) {
     const int64_t i = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
     if (i >= N) return;
     double a = 0.0;
     for (int64_t c = 0; c < chunks; ++c) a += part[c * N + i];
-    out[i] = a;
+    out[i] = a * scale;
 }
 
 __global__ void k_lp_max_parts(const float* __restrict__ part, int64_t chunks, int64_t N, float* __restrict__ out) {
@@ -249,13 +250,13 @@ __global__ __launch_bounds__(256) void k_syrk(const float* __restrict__ E, int64
         }
 }
 
-// M += db (every lower entry) ; diag += theta_t + reg
-__global__ void k_mat_finish(double* __restrict__ M, int64_t K, double db, const double* __restrict__ th,
+// M = ms M + db (every lower entry) ; diag += theta_t + reg
+__global__ void k_mat_finish(double* __restrict__ M, int64_t K, double ms, double db, const double* __restrict__ th,
                              double reg) {
     const int64_t a = blockIdx.y;
     const int64_t b = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
     if (a >= K || b > a) return;
-    double v = M[a * K + b] + db;
+    double v = ms * M[a * K + b] + db;
     if (a == b) v += th[a] + reg;
     M[a * K + b] = v;
 }
@@ -703,7 +704,7 @@ __global__ void k_ipm_update(IpmPtr P, int64_t K, int64_t N, double ap, double a
 }
 
 __global__ void k_ipm_init(IpmPtr P, int64_t K, int64_t N, double x0, double pdef, const double* __restrict__ pen_in,
-                           double mu) {
+                           double pscale) {
     const int64_t j = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
     if (j < K) {
         P.xt[j] = x0;
@@ -711,7 +712,7 @@ __global__ void k_ipm_init(IpmPtr P, int64_t K, int64_t N, double x0, double pde
     }
     if (j < N) {
         const bool v = P.vis[j] != 0;
-        P.pen[j] = v ? (pen_in ? pen_in[j] : pdef) : 0.0;
+        P.pen[j] = v ? pscale * (pen_in ? pen_in[j] : pdef) : 0.0;
         P.xs[j] = v ? x0 : 0.0;
         P.zs[j] = v ? x0 : 0.0;
         P.sc[j] = v ? x0 : 0.0;
@@ -778,16 +779,17 @@ __global__ void k_st_shift(IpmPtr P, int64_t K, int64_t N, double dx, double dz)
     }
 }
 
-// Outputs: t, sigma (mu for dropped elements) and the duals of the coverage
-// rows (y_c; the penalty p_i for a dropped element, whose sigma_i = mu sits
-// strictly inside its bound) followed by the budget row's y_b.
+// Outputs in the problem's units: t, sigma = mu sigma' (mu for dropped
+// elements) and the duals of the coverage rows y = y_c / mu (the penalty p_i
+// for a dropped element, whose sigma_i = mu sits strictly inside its bound)
+// followed by the budget row's y_b.
 __global__ void k_ipm_output(IpmPtr P, int64_t K, int64_t N, double mu, double yb, const double* __restrict__ pen_in,
                              double pdef, double* __restrict__ t_out, double* __restrict__ s_out,
                              double* __restrict__ y_out) {
     const int64_t j = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
     if (t_out && j < K) t_out[j] = fmax(P.xt[j], 0.0);
-    if (s_out && j < N) s_out[j] = P.vis[j] ? fmax(P.xs[j], 0.0) : mu;
-    if (y_out && j < N) y_out[j] = P.vis[j] ? fmax(P.yc[j], 0.0) : (pen_in ? pen_in[j] : pdef);
+    if (s_out && j < N) s_out[j] = P.vis[j] ? mu * fmax(P.xs[j], 0.0) : mu;
+    if (y_out && j < N) y_out[j] = P.vis[j] ? fmax(P.yc[j], 0.0) / mu : (pen_in ? pen_in[j] : pdef);
     if (y_out && j == 0) y_out[N] = fmax(yb, 0.0);
 }
 
@@ -872,12 +874,19 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
     UVC_TRY(W.alloc(&P.S, 16, "lp scalars"));
     P.vis = vis_d;
 
-    auto Etu = [&](const double* u, double* out) {  // out[i] = sum_k E[k,i] u[k]
+    // The iteration runs on the equivalent problem whose coverage rows are
+    // divided by mu_min: rows (E^T t) / mu + sigma' >= 1 with sigma' = sigma /
+    // mu and penalties mu p, so that the objective and t are unchanged and the
+    // coverage duals are mu y.  Every product with E carries the factor
+    // rs = 1 / mu.  Without it the central path runs with the budget row far
+    // from its scale and budget-bound rooms took up to twice the iterations.
+    const double rs = 1.0 / mu;
+    auto Etu = [&](const double* u, double* out) {  // out[i] = rs sum_k E[k,i] u[k]
         hipLaunchKernelGGL(k_lp_Etu, dim3(nblk(N), (unsigned)chunks), dim3(LP_TB), 0, st, E, K, N, rows_per, u, part);
-        hipLaunchKernelGGL(k_lp_sum_parts, dim3(nblk(N)), dim3(LP_TB), 0, st, part, chunks, N, out);
+        hipLaunchKernelGGL(k_lp_sum_parts, dim3(nblk(N)), dim3(LP_TB), 0, st, part, chunks, N, out, rs);
     };
     auto Ev = [&](const double* v, double* out) {  // out[k] = sum_i E[k,i] v[i]
-        hipLaunchKernelGGL(k_lp_Ev, dim3((unsigned)K), dim3(LP_TB), 0, st, E, N, v, out);
+        hipLaunchKernelGGL(k_lp_Ev, dim3((unsigned)K), dim3(LP_TB), 0, st, E, N, v, out, rs);
     };
     double red[IPM_SUMS];
     auto reduce = [&](int job, int d, double ap, double ad) -> uvc_status {
@@ -894,7 +903,7 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
     hipLaunchKernelGGL(k_lp_colstats, dim3(nblk(N), (unsigned)chunks), dim3(LP_TB), 0, st, E, K, N, rows_per,
                        cmax_part, sq_part);
     hipLaunchKernelGGL(k_lp_max_parts, dim3(nblk(N)), dim3(LP_TB), 0, st, cmax_part, chunks, N, cmax);
-    hipLaunchKernelGGL(k_lp_sum_parts, dim3(nblk(N)), dim3(LP_TB), 0, st, sq_part, chunks, N, sq);
+    hipLaunchKernelGGL(k_lp_sum_parts, dim3(nblk(N)), dim3(LP_TB), 0, st, sq_part, chunks, N, sq, 1.0);
     std::vector<float> hcmax((size_t)N);
     std::vector<double> hsq((size_t)N);
     UVC_HIP(hipMemcpyAsync(hcmax.data(), cmax, (size_t)N * 4, hipMemcpyDeviceToHost, st));
@@ -928,7 +937,7 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
     const unsigned gK = nblk(K), gN = nblk(N), gKN = nblk(std::max(K, N));
     if (nvis > 0) {
         // starting point and norms of h and c
-        double pmax = pdef;
+        double pmax = mu * pdef;  // penalties of the scaled problem
         double psq = 0.0;
         if (pen_dev) {
             hipLaunchKernelGGL(k_ipm_init, dim3(gKN), dim3(LP_TB), 0, st, P, K, N, 0.0, pdef, pen_dev, mu);
@@ -940,9 +949,9 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
             pmax = 0.0;
             for (double v : hp) pmax = std::max(pmax, v);
         } else {
-            psq = (double)nvis * pdef * pdef;
+            psq = (double)nvis * pmax * pmax;
         }
-        const double x0 = std::max(1.0, std::max(mu, std::sqrt(std::max(1.0, pmax))));
+        const double x0 = std::max(1.0, std::sqrt(std::max(1.0, pmax)));
         hipLaunchKernelGGL(k_ipm_init, dim3(gKN), dim3(LP_TB), 0, st, P, K, N, x0, pdef, pen_dev, mu);
         UVC_HIP(hipGetLastError());
         // M = E diag(dtil) E^T + Db 1 1^T + diag(tht), regularised, then its Cholesky factor in place
@@ -954,7 +963,8 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
             } else {
                 hipLaunchKernelGGL(k_syrk, dim3((unsigned)tiles, 1u), dim3(256), 0, st, E, K, N, P.dtil, M, 1);
             }
-            hipLaunchKernelGGL(k_mat_finish, dim3(nblk(K), (unsigned)K), dim3(LP_TB), 0, st, M, K, Db, P.tht, 0.0);
+            hipLaunchKernelGGL(k_mat_finish, dim3(nblk(K), (unsigned)K), dim3(LP_TB), 0, st, M, K, rs * rs, Db, P.tht,
+                               0.0);
             hipLaunchKernelGGL(k_diag_max, dim3(1), dim3(LP_TB), 0, st, M, K, P.S);
             hipLaunchKernelGGL(k_diag_reg, dim3(gK), dim3(LP_TB), 0, st, M, K, P.S, 1e-13);
             UVC_HIP(hipMemsetAsync(failf, 0, 4, st));
@@ -977,22 +987,22 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
         {
             // Mehrotra's starting point (falls back to the constant point
             // above if it is not finite or the unit-scaled factor fails)
-            hipLaunchKernelGGL(k_st_N, dim3(gN), dim3(LP_TB), 0, st, P, N, 4, mu);
+            hipLaunchKernelGGL(k_st_N, dim3(gN), dim3(LP_TB), 0, st, P, N, 4, 1.0);
             hipLaunchKernelGGL(k_st_K, dim3(gK), dim3(LP_TB), 0, st, P, K, 3, 0.0);
             UVC_TRY(factor(1.0));
-            hipLaunchKernelGGL(k_st_N, dim3(gN), dim3(LP_TB), 0, st, P, N, 0, mu);
+            hipLaunchKernelGGL(k_st_N, dim3(gN), dim3(LP_TB), 0, st, P, N, 0, 1.0);
             Ev(P.u, P.mvK);
             hipLaunchKernelGGL(k_st_K, dim3(gK), dim3(LP_TB), 0, st, P, K, 0, tmax);
             hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), 0, st, M, K, P.xt);
             Etu(P.xt, P.mvN);
-            hipLaunchKernelGGL(k_st_N, dim3(gN), dim3(LP_TB), 0, st, P, N, 1, mu);
+            hipLaunchKernelGGL(k_st_N, dim3(gN), dim3(LP_TB), 0, st, P, N, 1, 1.0);
             Etu(P.dt[1], P.mvN);
-            hipLaunchKernelGGL(k_st_N, dim3(gN), dim3(LP_TB), 0, st, P, N, 2, mu);
+            hipLaunchKernelGGL(k_st_N, dim3(gN), dim3(LP_TB), 0, st, P, N, 2, 1.0);
             Ev(P.u, P.mvK);
             hipLaunchKernelGGL(k_st_K, dim3(gK), dim3(LP_TB), 0, st, P, K, 1, (double)K);
             hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), 0, st, M, K, P.dt[0]);
             Etu(P.dt[0], P.mvN);
-            hipLaunchKernelGGL(k_st_N, dim3(gN), dim3(LP_TB), 0, st, P, N, 3, mu);
+            hipLaunchKernelGGL(k_st_N, dim3(gN), dim3(LP_TB), 0, st, P, N, 3, 1.0);
             UVC_TRY(reduce(5, 0, 0.0, 0.0));
             const double yb0 = -(double)K + red[0];
             double sumt = 0.0;
@@ -1026,22 +1036,22 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
             }
             UVC_HIP(hipGetLastError());
         }
-        const double hn = std::sqrt((double)nvis * mu * mu + tmax * tmax);
+        const double hn = std::sqrt((double)nvis * mu * mu + tmax * tmax);  // |h| in the problem's units
         const double cn = std::sqrt((double)K + psq);
         const double ncomp = (double)(nvis * 2 + K + 1);
         for (it = 0; it < max_iter; ++it) {
             // residuals and convergence
             Etu(P.xt, P.mvN);
             Ev(P.yc, P.mvK);
-            hipLaunchKernelGGL(k_ipm_resid_N, dim3(gN), dim3(LP_TB), 0, st, P, N, mu);
+            hipLaunchKernelGGL(k_ipm_resid_N, dim3(gN), dim3(LP_TB), 0, st, P, N, 1.0);
             hipLaunchKernelGGL(k_ipm_resid_K, dim3(gK), dim3(LP_TB), 0, st, P, K, yb);
             UVC_TRY(reduce(0, 0, 0.0, 0.0));
             const double sum_t = red[0];
             const double rpb = -tmax + sum_t + sb;
             const double gap = red[1] + sb * yb;
             const double po = sum_t + red[2];
-            const double dob = mu * red[3] - tmax * yb;
-            pres = std::sqrt(red[4] + rpb * rpb) / (1.0 + hn);
+            const double dob = red[3] - tmax * yb;
+            pres = std::sqrt(mu * mu * red[4] + rpb * rpb) / (1.0 + hn);  // coverage residuals back in units of mu
             dres = std::sqrt(red[5]) / (1.0 + cn);
             rgap = std::fabs(po - dob) / (1.0 + std::fabs(po) + std::fabs(dob));
             obj = po;

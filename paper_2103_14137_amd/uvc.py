@@ -22,10 +22,10 @@ _I64 = ctypes.c_int64
 _I32 = ctypes.c_int32
 
 PATHS = {"auto": 0, "lbvh": 1, "brute": 2}
-STAT_NAMES = ["rays", "nodes", "tris", "recheck", "front64", "visible", "steps", "near", "cache", "cache_hit"]
+STAT_NAMES = ["rays", "nodes", "tris", "recheck", "front64", "visible", "steps", "near", "cache", "cache_hit", "leaf_steps"]
 FLAG_NO_NEAR = 1
 FLAG_NO_CACHE = 2
-STAT_N = 10
+STAT_N = 11
 
 
 class UvcError(RuntimeError):

@@ -270,8 +270,8 @@ __global__ void k_near(const float* __restrict__ nodes, const float* __restrict_
     if (!FILL) off[s] = count;
 }
 
-// Exclusive scan of n int32 counts into out[0..n] (one block of 1024).
-__global__ __launch_bounds__(1024) void k_scan_i32(int32_t* __restrict__ a, int64_t n) {
+// Exclusive scan of n int32 counts into a[0..n] by one block of 1024.
+__device__ __forceinline__ void block_scan_i32(int32_t* __restrict__ a, int64_t n) {
     __shared__ int64_t part[1024];
     __shared__ int64_t carry;
     const int tid = threadIdx.x;
@@ -292,6 +292,43 @@ __global__ __launch_bounds__(1024) void k_scan_i32(int32_t* __restrict__ a, int6
         __syncthreads();
         if (tid == 1023) carry += part[1023];
         __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_i32(int32_t* __restrict__ a, int64_t n) { block_scan_i32(a, n); }
+
+// Both flag scans of a clustering round (C from the device state).
+__global__ __launch_bounds__(1024) void k_ploc_scan(int32_t* __restrict__ keep, int32_t* __restrict__ merge,
+                                                    const int32_t* __restrict__ st) {
+    const int64_t C = st[0];
+    if (C <= 1) return;
+    block_scan_i32(keep, C);
+    block_scan_i32(merge, C);
+}
+
+// End of a round: C <- clusters kept, next id <- next id - merges.  A round
+// that merges nothing, or whose counts do not add up, sets the error flag
+// and stops the clustering.
+__global__ void k_ploc_advance(const int32_t* __restrict__ keep, const int32_t* __restrict__ merge,
+                               int32_t* __restrict__ st) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int64_t C = st[0], next_id = st[1];
+    if (C <= 1) return;
+    const int64_t kt = keep[C], mt = merge[C];
+    if (mt < 1 || mt > next_id + 1 || kt + mt != C) {
+        st[2] = 1;
+        st[0] = 1;
+        return;
+    }
+    st[0] = (int32_t)kt;
+    st[1] = (int32_t)(next_id - mt);
+}
+
+__global__ void k_ploc_state(int32_t* __restrict__ st, int32_t C, int32_t next_id) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st[0] = C;
+        st[1] = next_id;
+        st[2] = 0;
     }
 }
 
@@ -337,9 +374,13 @@ __global__ void k_ploc_init(const float* __restrict__ tri, int64_t n, float pad,
     ref[s] = ~(int32_t)s;
 }
 
-__global__ void k_ploc_nn(const float* __restrict__ box, int64_t C, int32_t* __restrict__ nn) {
+// The clustering state lives on the device so that several rounds run
+// between host checks: st[0] = clusters C, st[1] = next node id, st[2] = error
+// flag.  A round with C <= 1 does nothing.
+__global__ void k_ploc_nn(const float* __restrict__ box, const int32_t* __restrict__ st, int32_t* __restrict__ nn) {
+    const int64_t C = st[0];
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= C) return;
+    if (C <= 1 || i >= C) return;
     float bi[6];
     for (int k = 0; k < 6; ++k) bi[k] = box[i * 6 + k];
     const int64_t j0 = i - PLOC_R < 0 ? 0 : i - PLOC_R, j1 = i + PLOC_R < C - 1 ? i + PLOC_R : C - 1;
@@ -358,10 +399,11 @@ __global__ void k_ploc_nn(const float* __restrict__ box, int64_t C, int32_t* __r
 
 // keep[i] = cluster i survives (unmerged, or the lower index of a merged
 // pair); merge[i] = i is the lower index of a mutual pair.
-__global__ void k_ploc_flags(const int32_t* __restrict__ nn, int64_t C, int32_t* __restrict__ keep,
+__global__ void k_ploc_flags(const int32_t* __restrict__ nn, const int32_t* __restrict__ st, int32_t* __restrict__ keep,
                              int32_t* __restrict__ merge) {
+    const int64_t C = st[0];
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= C) return;
+    if (C <= 1 || i >= C) return;
     const int32_t j = nn[i];
     const bool mutual = nn[j] == (int32_t)i;
     merge[i] = (mutual && (int64_t)j > i) ? 1 : 0;
@@ -372,12 +414,13 @@ __global__ void k_ploc_flags(const int32_t* __restrict__ nn, int64_t C, int32_t*
 // nodes (id = next_id - merge rank, so that the last node made is node 0)
 // and the compacted cluster list.
 __global__ void k_ploc_merge(const float* __restrict__ box, const int32_t* __restrict__ ref,
-                             const int32_t* __restrict__ nn, int64_t C, const int32_t* __restrict__ keep,
-                             const int32_t* __restrict__ merge, int64_t next_id, float* __restrict__ nodes,
-                             float* __restrict__ box_out, int32_t* __restrict__ ref_out,
+                             const int32_t* __restrict__ nn, const int32_t* __restrict__ st,
+                             const int32_t* __restrict__ keep, const int32_t* __restrict__ merge,
+                             float* __restrict__ nodes, float* __restrict__ box_out, int32_t* __restrict__ ref_out,
                              int32_t* __restrict__ int_parent, int32_t* __restrict__ leaf_parent) {
+    const int64_t C = st[0], next_id = st[1];
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= C || keep[i + 1] == keep[i]) return;
+    if (C <= 1 || i >= C || keep[i + 1] == keep[i]) return;
     const int64_t pos = keep[i];
     if (merge[i + 1] == merge[i]) {
         for (int k = 0; k < 6; ++k) box_out[pos * 6 + k] = box[i * 6 + k];
@@ -599,38 +642,45 @@ static uvc_status build_impl(const float* verts_in, int64_t nv, const int32_t* t
         hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, TB)), dim3(TB), 0, st, (uint32_t*)lpar, 0xfffffffeu, n);
         {
             float *cb0 = nullptr, *cb1 = nullptr;
-            int32_t *cr0 = nullptr, *cr1 = nullptr, *nn = nullptr, *keep = nullptr, *merge = nullptr;
+            int32_t *cr0 = nullptr, *cr1 = nullptr, *nn = nullptr, *keep = nullptr, *merge = nullptr, *pst = nullptr;
             if ((r = tmp.alloc(&cb0, (size_t)n * 6, "clusters")) != UVC_OK ||
                 (r = tmp.alloc(&cb1, (size_t)n * 6, "clusters")) != UVC_OK ||
                 (r = tmp.alloc(&cr0, (size_t)n, "clusters")) != UVC_OK ||
                 (r = tmp.alloc(&cr1, (size_t)n, "clusters")) != UVC_OK ||
                 (r = tmp.alloc(&nn, (size_t)n, "neighbours")) != UVC_OK ||
                 (r = tmp.alloc(&keep, (size_t)n + 1, "cluster flags")) != UVC_OK ||
-                (r = tmp.alloc(&merge, (size_t)n + 1, "cluster flags")) != UVC_OK)
+                (r = tmp.alloc(&merge, (size_t)n + 1, "cluster flags")) != UVC_OK ||
+                (r = tmp.alloc(&pst, 4, "clustering state")) != UVC_OK)
                 return cleanup_fail(r);
             hipLaunchKernelGGL(k_ploc_init, dim3(grid_for(n, TB)), dim3(TB), 0, st, s->tri, n, s->pad, cb0, cr0);
+            hipLaunchKernelGGL(k_ploc_state, dim3(1), dim3(1), 0, st, pst, (int32_t)n, (int32_t)(n - 2));
             STEP(hipGetLastError());
-            int64_t C = n, next_id = n - 2;
-            for (int round = 0; C > 1; ++round) {
+            // rounds run in batches between host checks; the grids cover the
+            // cluster count of the last check (it only shrinks)
+            constexpr int PLOC_BATCH = 8;
+            int64_t Cb = n;
+            for (int round = 0; Cb > 1;) {
                 if (round > 10000) return cleanup_fail(fail(UVC_EDEVICE, "internal error: clustering did not finish"));
-                hipLaunchKernelGGL(k_ploc_nn, dim3(grid_for(C, TB)), dim3(TB), 0, st, cb0, C, nn);
-                hipLaunchKernelGGL(k_ploc_flags, dim3(grid_for(C, TB)), dim3(TB), 0, st, nn, C, keep, merge);
-                hipLaunchKernelGGL(k_scan_i32, dim3(1), dim3(1024), 0, st, keep, C);
-                hipLaunchKernelGGL(k_scan_i32, dim3(1), dim3(1024), 0, st, merge, C);
+                const unsigned g = grid_for(Cb, TB);
+                for (int b = 0; b < PLOC_BATCH; ++b, ++round) {
+                    hipLaunchKernelGGL(k_ploc_nn, dim3(g), dim3(TB), 0, st, cb0, pst, nn);
+                    hipLaunchKernelGGL(k_ploc_flags, dim3(g), dim3(TB), 0, st, nn, pst, keep, merge);
+                    hipLaunchKernelGGL(k_ploc_scan, dim3(1), dim3(1024), 0, st, keep, merge, pst);
+                    hipLaunchKernelGGL(k_ploc_merge, dim3(g), dim3(TB), 0, st, cb0, cr0, nn, pst, keep, merge, s->nodes,
+                                       cb1, cr1, ipar, lpar);
+                    hipLaunchKernelGGL(k_ploc_advance, dim3(1), dim3(1), 0, st, keep, merge, pst);
+                    std::swap(cb0, cb1);
+                    std::swap(cr0, cr1);
+                }
                 STEP(hipGetLastError());
-                int32_t tot[2] = {0, 0};
-                STEP(hipMemcpyAsync(&tot[0], keep + C, 4, hipMemcpyDeviceToHost, st));
-                STEP(hipMemcpyAsync(&tot[1], merge + C, 4, hipMemcpyDeviceToHost, st));
+                int32_t hs[3] = {0, 0, 0};
+                STEP(hipMemcpyAsync(hs, pst, sizeof(hs), hipMemcpyDeviceToHost, st));
                 STEP(hipStreamSynchronize(st));
-                if (tot[1] < 1 || tot[1] > next_id + 1 || (int64_t)tot[0] + tot[1] != C)
-                    return cleanup_fail(fail(UVC_EDEVICE, "internal error: clustering made no progress"));
-                hipLaunchKernelGGL(k_ploc_merge, dim3(grid_for(C, TB)), dim3(TB), 0, st, cb0, cr0, nn, C, keep, merge,
-                                   next_id, s->nodes, cb1, cr1, ipar, lpar);
-                STEP(hipGetLastError());
-                next_id -= tot[1];
-                C = tot[0];
-                std::swap(cb0, cb1);
-                std::swap(cr0, cr1);
+                if (hs[2] != 0) return cleanup_fail(fail(UVC_EDEVICE, "internal error: clustering made no progress"));
+                if (hs[0] < 1 || hs[0] > Cb) return cleanup_fail(fail(UVC_EDEVICE, "internal error: bad cluster count"));
+                Cb = hs[0];
+                if (Cb == 1 && hs[1] != -1)
+                    return cleanup_fail(fail(UVC_EDEVICE, "internal error: clustering left node ids unused"));
             }
             hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, st, (uint32_t*)ipar, 0xffffffffu, (int64_t)1);
             STEP(hipGetLastError());

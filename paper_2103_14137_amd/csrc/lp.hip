@@ -357,6 +357,14 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ M, int
         }
 }
 
+// Lane c's value of v for the whole wave (c uniform): two v_readlane.
+__device__ __forceinline__ double lane_bcast(double v, int c) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, c);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), c);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Solve L L^T x = r in place (one workgroup of 1024 threads).  Each 64 x 64
 // diagonal block is staged in LDS and solved by one wave, lane r holding
 // unknown r (column-oriented substitution with lane broadcasts); the other
@@ -369,9 +377,19 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ 
     // forward: L z = r
     for (int64_t j0 = 0; j0 < K; j0 += 64) {
         const int nb = (int)((K - j0) < 64 ? (K - j0) : 64);
-        for (int q = tid; q < nb * nb; q += 1024) {
-            const int r = q / nb, c = q % nb;
-            Lb[r][c] = (c <= r) ? L[(j0 + r) * K + j0 + c] : 0.0;
+        {
+            // stage the block: the loads of all four passes first
+            double t[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = tid + 1024 * u, r = q / nb, c = q % nb;
+                t[u] = (q < nb * nb && c <= r) ? L[(j0 + r) * K + j0 + c] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = tid + 1024 * u;
+                if (q < nb * nb) Lb[q / nb][q % nb] = t[u];
+            }
         }
         if (tid < nb) {
             zb[tid] = x[j0 + tid];
@@ -381,7 +399,7 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ 
         if (tid < 64) {
             double v = tid < nb ? zb[tid] : 0.0;
             for (int c = 0; c < nb; ++c) {
-                const double zc = __shfl(v, c) * rd[c];
+                const double zc = lane_bcast(v, c) * rd[c];
                 if (tid == c)
                     v = zc;
                 else if (tid > c && tid < nb)
@@ -393,13 +411,32 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ 
             }
         }
         __syncthreads();
-        // rows below: one wave per row reads the row's nb entries contiguously
+        // rows below: 16 lanes per row (4 columns each, read contiguously by the
+        // 16 lanes), 64 rows per pass of the workgroup and 4 passes unrolled so
+        // that each thread keeps 16 loads in flight
         {
-            const int wv = tid >> 6, ln = tid & 63;
-            for (int64_t r = j0 + nb + wv; r < K; r += 16) {
-                double v = ln < nb ? L[r * K + j0 + ln] * zb[ln] : 0.0;
-                for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-                if (ln == 0) x[r] -= v;
+            const int rg = tid >> 4, l16 = tid & 15;
+            const double z0 = l16 < nb ? zb[l16] : 0.0, z1 = l16 + 16 < nb ? zb[l16 + 16] : 0.0;
+            const double z2 = l16 + 32 < nb ? zb[l16 + 32] : 0.0, z3 = l16 + 48 < nb ? zb[l16 + 48] : 0.0;
+            const int c1 = l16 + 16 < nb ? l16 + 16 : 0, c2 = l16 + 32 < nb ? l16 + 32 : 0;
+            const int c3 = l16 + 48 < nb ? l16 + 48 : 0, c0 = l16 < nb ? l16 : 0;
+            for (int64_t rb = j0 + nb + rg; rb < K; rb += 256) {
+                double v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t r = rb + 64 * u;
+                    v[u] = 0.0;
+                    if (r < K) {
+                        const double* row = L + r * K + j0;
+                        v[u] = row[c0] * z0 + row[c1] * z1 + row[c2] * z2 + row[c3] * z3;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    for (int o = 8; o > 0; o >>= 1) v[u] += __shfl_xor(v[u], o, 16);
+                    const int64_t r = rb + 64 * u;
+                    if (l16 == 0 && r < K) x[r] -= v[u];
+                }
             }
         }
         __syncthreads();
@@ -408,9 +445,19 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ 
     for (int64_t j1 = K; j1 > 0; j1 -= 64) {
         const int64_t j0 = j1 >= 64 ? j1 - 64 : 0;
         const int nb = (int)(j1 - j0);
-        for (int q = tid; q < nb * nb; q += 1024) {
-            const int r = q / nb, c = q % nb;
-            Lb[r][c] = (c <= r) ? L[(j0 + r) * K + j0 + c] : 0.0;
+        {
+            // stage the block: the loads of all four passes first
+            double t[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = tid + 1024 * u, r = q / nb, c = q % nb;
+                t[u] = (q < nb * nb && c <= r) ? L[(j0 + r) * K + j0 + c] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int q = tid + 1024 * u;
+                if (q < nb * nb) Lb[q / nb][q % nb] = t[u];
+            }
         }
         if (tid < nb) {
             zb[tid] = x[j0 + tid];
@@ -420,7 +467,7 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ 
         if (tid < 64) {
             double v = tid < nb ? zb[tid] : 0.0;
             for (int c = nb - 1; c >= 0; --c) {
-                const double zc = __shfl(v, c) * rd[c];
+                const double zc = lane_bcast(v, c) * rd[c];
                 if (tid == c)
                     v = zc;
                 else if (tid < c)
@@ -432,10 +479,17 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ 
             }
         }
         __syncthreads();
+        // rows above: thread r reads column r of the block's rows (coalesced
+        // across threads), 8 independent partial sums keep 8 loads in flight
         for (int64_t r = tid; r < j0; r += 1024) {
-            double v = 0.0;
-            for (int q = 0; q < nb; ++q) v += L[(j0 + q) * K + r] * zb[q];
-            x[r] -= v;
+            double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            int q = 0;
+            for (; q + 8 <= nb; q += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[u] += L[(j0 + q + u) * K + r] * zb[q + u];
+            }
+            for (; q < nb; ++q) a[0] += L[(j0 + q) * K + r] * zb[q];
+            x[r] -= ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
         }
         __syncthreads();
     }

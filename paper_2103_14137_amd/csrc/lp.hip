@@ -196,12 +196,19 @@ __global__ void k_lp_sum_pairs(const double* __restrict__ part, int nb, double* 
 
 // ------------------------------------------------------- dense FP64 algebra
 constexpr int SY_T = 64;   // output tile
-constexpr int SY_KC = 16;  // inner chunk
+constexpr int SY_KC = 32;  // inner chunk (columns of E per LDS stage)
 
 // M[a][b] = sum_i E[a,i] d[i] E[b,i] for the lower tiles (tile row >= tile
-// col) of the K x K row-major M.  256 threads, 4 x 4 outputs each.
+// col) of the K x K row-major M, on the FP64 matrix cores.  A workgroup of
+// four waves owns a 64 x 64 tile; wave w computes the 32 x 32 block
+// (rows 32 (w / 2), cols 32 (w % 2)) as 2 x 2 blocks of
+// v_mfma_f64_16x16x4f64.  Per chunk of SY_KC columns of E, the two 64-row
+// panels are staged in LDS in FP64 (the row panel scaled by d).  Operand
+// layout of the instruction: A[i][k] in lane i + 16 k, B[k][j] in lane
+// j + 16 k; result D[i][j] in lane j + 16 (i % 4), element i / 4.
 // With splits > 1, workgroup (tile, s) covers columns [s N / splits,
 // (s + 1) N / splits) and writes the partial product to M + s K^2.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_syrk(const float* __restrict__ E, int64_t K, int64_t N,
                                               const double* __restrict__ d, double* __restrict__ M, int splits) {
     __shared__ double As[SY_KC][SY_T + 1];
@@ -213,41 +220,70 @@ __global__ __launch_bounds__(256) void k_syrk(const float* __restrict__ E, int64
     while (tr * (tr + 1) / 2 > t) --tr;
     const int64_t tc = t - tr * (tr + 1) / 2;
     const int64_t a0 = tr * SY_T, b0 = tc * SY_T;
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    double acc[4][4] = {};
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) acc[m][n] = (dbl4){0.0, 0.0, 0.0, 0.0};
     const int64_t per = ((N + splits - 1) / splits + SY_KC - 1) / SY_KC * SY_KC;
     const int64_t ib = (int64_t)blockIdx.y * per, ie = std::min<int64_t>(N, ib + per);
     double* Mo = M + (int64_t)blockIdx.y * K * K;
+    // staging: thread q loads column kk = q % SY_KC of rows q / SY_KC + (256 / SY_KC) u
+    constexpr int SU = SY_T * SY_KC / 256;
+    const int sr = threadIdx.x / SY_KC, skk = threadIdx.x % SY_KC;
+    // the next chunk's loads are issued before the current chunk's matrix
+    // operations, so that their latency is covered
+    float ea[SU], eb[SU];
+    double di = 0.0;
+    // out-of-range rows and columns load a clamped in-range address and are
+    // zeroed by a select (no branches around the loads)
+    auto fetch = [&](int64_t i0) {
+        const int64_t i = i0 + skk;
+        const bool iok = i < ie;
+        const int64_t ic = iok ? i : ie - 1;
+        di = d[ic];
+        di = iok ? di : 0.0;
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const int64_t a = a0 + sr + (256 / SY_KC) * u, b = b0 + sr + (256 / SY_KC) * u;
+            const float va = E[(a < K ? a : K - 1) * N + ic], vb = E[(b < K ? b : K - 1) * N + ic];
+            ea[u] = a < K ? va : 0.0f;
+            eb[u] = (iok && b < K) ? vb : 0.0f;
+        }
+    };
+    if (ib < ie) fetch(ib);
     for (int64_t i0 = ib; i0 < ie; i0 += SY_KC) {
-        for (int q = threadIdx.x; q < SY_T * SY_KC; q += 256) {
-            const int r = q / SY_KC, kk = q % SY_KC;
-            const int64_t i = i0 + kk;
-            const int64_t a = a0 + r, b = b0 + r;
-            const double di = (i < ie) ? d[i] : 0.0;
-            As[kk][r] = (a < K && i < ie) ? (double)E[a * N + i] * di : 0.0;
-            Bs[kk][r] = (b < K && i < ie) ? (double)E[b * N + i] : 0.0;
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            As[skk][sr + (256 / SY_KC) * u] = (double)ea[u] * di;
+            Bs[skk][sr + (256 / SY_KC) * u] = (double)eb[u];
         }
         __syncthreads();
+        if (i0 + SY_KC < ie) fetch(i0 + SY_KC);
 #pragma unroll
-        for (int kk = 0; kk < SY_KC; ++kk) {
-            double av[4], bv[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                av[u] = As[kk][ty * 4 + u];
-                bv[u] = Bs[kk][tx * 4 + u];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+        for (int ks = 0; ks < SY_KC / 4; ++ks) {
+            const int kk = 4 * ks + lk;
+            const double fa0 = As[kk][wr + li], fa1 = As[kk][wr + 16 + li];
+            const double fb0 = Bs[kk][wc + li], fb1 = Bs[kk][wc + 16 + li];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa0, fb0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa0, fb1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa1, fb0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa1, fb1, acc[1][1], 0, 0, 0);
         }
         __syncthreads();
     }
-    for (int u = 0; u < 4; ++u)
-        for (int v = 0; v < 4; ++v) {
-            const int64_t a = a0 + ty * 4 + u, b = b0 + tx * 4 + v;
-            if (a < K && b < K && b <= a) Mo[a * K + b] = acc[u][v];
-        }
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t a = a0 + wr + 16 * m + 4 * e + lk, b = b0 + wc + 16 * n + li;
+                if (a < K && b < K && b <= a) Mo[a * K + b] = acc[m][n][e];
+            }
 }
 
 // M = ms M + db (every lower entry) ; diag += theta_t + reg

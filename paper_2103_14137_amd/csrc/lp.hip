@@ -516,13 +516,17 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ 
         }
         __syncthreads();
         // rows above: thread r reads column r of the block's rows (coalesced
-        // across threads), 8 independent partial sums keep 8 loads in flight
+        // across threads); 32 loads are issued before their products are
+        // summed into 8 independent partial sums
         for (int64_t r = tid; r < j0; r += 1024) {
             double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             int q = 0;
-            for (; q + 8 <= nb; q += 8) {
+            for (; q + 32 <= nb; q += 32) {
+                double l[32];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) a[u] += L[(j0 + q + u) * K + r] * zb[q + u];
+                for (int u = 0; u < 32; ++u) l[u] = L[(j0 + q + u) * K + r];
+#pragma unroll
+                for (int u = 0; u < 32; ++u) a[u & 7] += l[u] * zb[q + u];
             }
             for (; q < nb; ++q) a[0] += L[(j0 + q) * K + r] * zb[q];
             x[r] -= ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));

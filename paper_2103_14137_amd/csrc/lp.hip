@@ -303,6 +303,7 @@ __global__ void k_get_diag(const double* __restrict__ M, int64_t K, double* __re
 }
 
 constexpr int CH_B = 32;
+constexpr int LP_CENTRALITY = 2;  // centrality correctors tried per iteration
 
 // Cholesky of the diagonal block at j0 (size nb <= CH_B), in place (lower).
 // Right-looking on the unscaled block: step j subtracts
@@ -593,18 +594,38 @@ __global__ void k_ipm_scale(IpmPtr P, int64_t K, int64_t N) {
     if (i < K) P.tht[i] = P.zt[i] / P.xt[i];
 }
 
-// Complementarity right-hand sides: predictor (mode 0) -x z, -s y;
-// corrector (mode 1) sigmu - x z - dx_aff dz_aff, sigmu - s y - ds_aff dy_aff.
-__device__ __forceinline__ double rsy_of(const IpmPtr& P, int64_t i, int mode, double sigmu) {
-    return mode ? sigmu - P.sc[i] * P.yc[i] - P.dsc[0][i] * P.dyc[0][i] : -P.sc[i] * P.yc[i];
+// Right-hand side of one Newton solve.  Complementarity part: predictor
+// (mode 0) -x z; corrector (mode 1) sigmu - x z - dx dz with the predictor
+// in slot cd; centrality corrector (mode 2, Gondzio 1996) the move of the
+// trial product v = (x + atp dx)(z + atd dz) of the direction in slot cd
+// into [0.1, 10] sigmu (no move below -10 sigmu).  The residuals enter
+// with weight res (1, or 0 for a centrality corrector).
+struct RhsArgs {
+    int mode;
+    int cd;
+    double sigmu;
+    double atp, atd;
+    double res;
+};
+__device__ __forceinline__ double centrality(double v, double tgt) {
+    const double r = fmin(fmax(v, 0.1 * tgt), 10.0 * tgt) - v;
+    return fmax(r, -10.0 * tgt);
 }
-__device__ __forceinline__ double rxzs_of(const IpmPtr& P, int64_t i, int mode, double sigmu) {
-    return mode ? sigmu - P.xs[i] * P.zs[i] - P.dsig[0][i] * P.dzs[0][i] : -P.xs[i] * P.zs[i];
+__device__ __forceinline__ double comp_rhs(double x, double z, double dx, double dz, const RhsArgs& A) {
+    if (A.mode == 0) return -x * z;
+    if (A.mode == 1) return A.sigmu - x * z - dx * dz;
+    return centrality((x + A.atp * dx) * (z + A.atd * dz), A.sigmu);
+}
+__device__ __forceinline__ double rsy_of(const IpmPtr& P, int64_t i, const RhsArgs& A) {
+    return comp_rhs(P.sc[i], P.yc[i], P.dsc[A.cd][i], P.dyc[A.cd][i], A);
+}
+__device__ __forceinline__ double rxzs_of(const IpmPtr& P, int64_t i, const RhsArgs& A) {
+    return comp_rhs(P.xs[i], P.zs[i], P.dsig[A.cd][i], P.dzs[A.cd][i], A);
 }
 
 // Direction, part a (elements): rpp = rpc + rsy / yc, wv = drc rpp,
 // rhs = wv - rds + rxz / sigma, q = drc / (drc + ths) rhs, u = wv - q.
-__global__ void k_dir_a(IpmPtr P, int64_t N, int mode, double sigmu) {
+__global__ void k_dir_a(IpmPtr P, int64_t N, RhsArgs A) {
     const int64_t i = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
     if (i >= N) return;
     if (!P.vis[i]) {
@@ -613,9 +634,9 @@ __global__ void k_dir_a(IpmPtr P, int64_t N, int mode, double sigmu) {
         P.u[i] = 0.0;
         return;
     }
-    const double rpp = P.rpc[i] + rsy_of(P, i, mode, sigmu) / P.yc[i];
+    const double rpp = A.res * P.rpc[i] + rsy_of(P, i, A) / P.yc[i];
     const double wv = P.drc[i] * rpp;
-    const double rhs = wv - P.rds[i] + rxzs_of(P, i, mode, sigmu) / P.xs[i];
+    const double rhs = wv - A.res * P.rds[i] + rxzs_of(P, i, A) / P.xs[i];
     const double q = P.drc[i] / (P.drc[i] + P.ths[i]) * rhs;
     P.rpp[i] = rpp;
     P.rhs[i] = rhs;
@@ -623,11 +644,11 @@ __global__ void k_dir_a(IpmPtr P, int64_t N, int mode, double sigmu) {
 }
 
 // Part b (poses): dt = E u - wv_b - rdt + rxz_t / t  (then solved with M).
-__global__ void k_dir_b(IpmPtr P, int64_t K, int mode, double sigmu, double wvb, int d) {
+__global__ void k_dir_b(IpmPtr P, int64_t K, RhsArgs A, double wvb, int d) {
     const int64_t k = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
     if (k >= K) return;
-    const double rxz = mode ? sigmu - P.xt[k] * P.zt[k] - P.dt[0][k] * P.dzt[0][k] : -P.xt[k] * P.zt[k];
-    P.dt[d][k] = P.mvK[k] - wvb - P.rdt[k] + rxz / P.xt[k];
+    const double rxz = comp_rhs(P.xt[k], P.zt[k], P.dt[A.cd][k], P.dzt[A.cd][k], A);
+    P.dt[d][k] = P.mvK[k] - wvb - A.res * P.rdt[k] + rxz / P.xt[k];
 }
 
 // Budget-row components: gdx_b = -sum dt, dy_b = D_b (rpp_b - gdx_b),
@@ -654,7 +675,7 @@ __global__ __launch_bounds__(LP_TB) void k_ipm_bscal(IpmPtr P, int64_t K, int d,
 }
 
 // Part c (elements), with etd = E^T dt in mvN: dsigma, dy_c, ds_c, dz_s.
-__global__ void k_dir_c(IpmPtr P, int64_t N, int mode, double sigmu, int d) {
+__global__ void k_dir_c(IpmPtr P, int64_t N, RhsArgs A, int d) {
     const int64_t i = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
     if (i >= N) return;
     if (!P.vis[i]) {
@@ -671,15 +692,34 @@ __global__ void k_dir_c(IpmPtr P, int64_t N, int mode, double sigmu, int d) {
     const double dy = a * (P.rpp[i] - gdx);
     P.dsig[d][i] = dsg;
     P.dyc[d][i] = dy;
-    P.dsc[d][i] = (rsy_of(P, i, mode, sigmu) - P.sc[i] * dy) / P.yc[i];
-    P.dzs[d][i] = P.rds[i] - dy;
+    P.dsc[d][i] = (rsy_of(P, i, A) - P.sc[i] * dy) / P.yc[i];
+    P.dzs[d][i] = A.res * P.rds[i] - dy;
 }
 
 // Part d (poses), with E dy_c in mvK2: dz_t = rdt - (E dy_c - dy_b).
-__global__ void k_dir_d(IpmPtr P, int64_t K, int d) {
+__global__ void k_dir_d(IpmPtr P, int64_t K, int d, double res) {
     const int64_t k = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
     if (k >= K) return;
-    P.dzt[d][k] = P.rdt[k] - (P.mvK2[k] - P.S[3 * d + 1]);
+    P.dzt[d][k] = res * P.rdt[k] - (P.mvK2[k] - P.S[3 * d + 1]);
+}
+
+// Slot od += slot cd (all direction components and the budget row's dy_b, ds_b).
+__global__ void k_dir_add(IpmPtr P, int64_t K, int64_t N, int od, int cd) {
+    const int64_t j = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
+    if (j < K) {
+        P.dt[od][j] += P.dt[cd][j];
+        P.dzt[od][j] += P.dzt[cd][j];
+    }
+    if (j < N) {
+        P.dsig[od][j] += P.dsig[cd][j];
+        P.dzs[od][j] += P.dzs[cd][j];
+        P.dyc[od][j] += P.dyc[cd][j];
+        P.dsc[od][j] += P.dsc[cd][j];
+    }
+    if (j == 0) {
+        P.S[3 * od + 1] += P.S[3 * cd + 1];
+        P.S[3 * od + 2] += P.S[3 * cd + 2];
+    }
 }
 
 // Fixed-order block reductions over the index space [0, K + N): job
@@ -783,17 +823,17 @@ __global__ __launch_bounds__(512) void k_ipm_reduce2(const double* __restrict__ 
     if (l == 0) out[q] = red[q][0];
 }
 
-__global__ void k_ipm_update(IpmPtr P, int64_t K, int64_t N, double ap, double ad) {
+__global__ void k_ipm_update(IpmPtr P, int64_t K, int64_t N, double ap, double ad, int d) {
     const int64_t j = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
     if (j < K) {
-        P.xt[j] += ap * P.dt[1][j];
-        P.zt[j] += ad * P.dzt[1][j];
+        P.xt[j] += ap * P.dt[d][j];
+        P.zt[j] += ad * P.dzt[d][j];
     }
     if (j < N && P.vis[j]) {
-        P.xs[j] += ap * P.dsig[1][j];
-        P.sc[j] += ap * P.dsc[1][j];
-        P.zs[j] += ad * P.dzs[1][j];
-        P.yc[j] += ad * P.dyc[1][j];
+        P.xs[j] += ap * P.dsig[d][j];
+        P.sc[j] += ap * P.dsc[d][j];
+        P.zs[j] += ad * P.dzs[d][j];
+        P.yc[j] += ad * P.dyc[d][j];
     }
 }
 
@@ -1159,18 +1199,18 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
             hipLaunchKernelGGL(k_ipm_scale, dim3(gKN), dim3(LP_TB), 0, st, P, K, N);
             UVC_TRY(factor(Db));
             // one Newton direction into slot d (mode 0 predictor, 1 corrector)
-            auto direction = [&](int mode, int d, double sigmu, double rsyb) {
-                const double rppb = rpb + rsyb / yb;
+            auto direction = [&](const RhsArgs& A, int d, double rsyb) {
+                const double rppb = A.res * rpb + rsyb / yb;
                 const double wvb = Db * rppb;
-                hipLaunchKernelGGL(k_dir_a, dim3(gN), dim3(LP_TB), 0, st, P, N, mode, sigmu);
+                hipLaunchKernelGGL(k_dir_a, dim3(gN), dim3(LP_TB), 0, st, P, N, A);
                 Ev(P.u, P.mvK);
-                hipLaunchKernelGGL(k_dir_b, dim3(gK), dim3(LP_TB), 0, st, P, K, mode, sigmu, wvb, d);
+                hipLaunchKernelGGL(k_dir_b, dim3(gK), dim3(LP_TB), 0, st, P, K, A, wvb, d);
                 hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), 0, st, M, K, P.dt[d]);
                 Etu(P.dt[d], P.mvN);
                 hipLaunchKernelGGL(k_ipm_bscal, dim3(1), dim3(LP_TB), 0, st, P, K, d, Db, rppb, rsyb, sb, yb);
-                hipLaunchKernelGGL(k_dir_c, dim3(gN), dim3(LP_TB), 0, st, P, N, mode, sigmu, d);
+                hipLaunchKernelGGL(k_dir_c, dim3(gN), dim3(LP_TB), 0, st, P, N, A, d);
                 Ev(P.dyc[d], P.mvK2);
-                hipLaunchKernelGGL(k_dir_d, dim3(gK), dim3(LP_TB), 0, st, P, K, d);
+                hipLaunchKernelGGL(k_dir_d, dim3(gK), dim3(LP_TB), 0, st, P, K, d, A.res);
             };
             auto steps = [&](int d, double& ap, double& ad, double& dyb, double& dsb) -> uvc_status {
                 UVC_TRY(reduce(1, d, 0.0, 0.0));
@@ -1185,7 +1225,7 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
                 if (dyb < 0.0 && yb > 0.0) ad = std::min(ad, -yb / dyb);
                 return UVC_OK;
             };
-            direction(0, 0, 0.0, -sb * yb);
+            direction(RhsArgs{0, 0, 0.0, 0.0, 0.0, 1.0}, 0, -sb * yb);
             double ap = 1.0, ad = 1.0, dyb0 = 0.0, dsb0 = 0.0;
             UVC_TRY(steps(0, ap, ad, dyb0, dsb0));
             int f = 0;
@@ -1196,15 +1236,35 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
             const double gaff = red[0] + (sb + ap * dsb0) * (yb + ad * dyb0);
             const double sig = std::pow(gaff / std::max(gap, 1e-300), 3.0);
             const double sigmu = sig * muc;
-            direction(1, 1, sigmu, sigmu - sb * yb - dsb0 * dyb0);
-            double dyb1 = 0.0, dsb1 = 0.0;
-            UVC_TRY(steps(1, ap, ad, dyb1, dsb1));
+            direction(RhsArgs{1, 0, sigmu, 0.0, 0.0, 1.0}, 1, sigmu - sb * yb - dsb0 * dyb0);
+            double dybc = 0.0, dsbc = 0.0;
+            UVC_TRY(steps(1, ap, ad, dybc, dsbc));
+            // Gondzio's centrality correctors: from the trial point a longer
+            // step would reach, move outlying complementarity products into
+            // [0.1, 10] sigmu; keep a correction only if it lengthens the steps
+            int cd = 1;
+            for (int kc = 0; kc < LP_CENTRALITY; ++kc) {
+                const double atp = std::min(1.0, 1.5 * ap + 0.3), atd = std::min(1.0, 1.5 * ad + 0.3);
+                const double vb = (sb + atp * dsbc) * (yb + atd * dybc);
+                const double rb = std::max(std::min(std::max(vb, 0.1 * sigmu), 10.0 * sigmu) - vb, -10.0 * sigmu);
+                const int od = 1 - cd;
+                direction(RhsArgs{2, cd, sigmu, atp, atd, 0.0}, od, rb);
+                hipLaunchKernelGGL(k_dir_add, dim3(gKN), dim3(LP_TB), 0, st, P, K, N, od, cd);
+                double ap2 = 1.0, ad2 = 1.0, dyb2 = 0.0, dsb2 = 0.0;
+                UVC_TRY(steps(od, ap2, ad2, dyb2, dsb2));
+                if (!(ap2 + ad2 >= 1.01 * (ap + ad))) break;
+                cd = od;
+                ap = ap2;
+                ad = ad2;
+                dybc = dyb2;
+                dsbc = dsb2;
+            }
             ap *= 0.99;
             ad *= 0.99;
-            hipLaunchKernelGGL(k_ipm_update, dim3(gKN), dim3(LP_TB), 0, st, P, K, N, ap, ad);
+            hipLaunchKernelGGL(k_ipm_update, dim3(gKN), dim3(LP_TB), 0, st, P, K, N, ap, ad, cd);
             UVC_HIP(hipGetLastError());
-            sb += ap * dsb1;
-            yb += ad * dyb1;
+            sb += ap * dsbc;
+            yb += ad * dybc;
         }
         UVC_TRY(reduce(3, 0, 0.0, 0.0));
         obj = red[0] + red[1];

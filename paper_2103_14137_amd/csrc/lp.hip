@@ -1023,13 +1023,17 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
         hipLaunchKernelGGL(k_lp_Ev, dim3((unsigned)K), dim3(LP_TB), 0, st, E, N, v, out, rs);
     };
     double red[IPM_SUMS];
+    double hS[S_RED + IPM_SUMS];
     auto reduce = [&](int job, int d, double ap, double ad) -> uvc_status {
         hipLaunchKernelGGL(k_ipm_reduce, dim3(RB), dim3(LP_TB), 0, st, P, K, N, job, d, ap, ad, rpart);
         hipLaunchKernelGGL(k_ipm_reduce2, dim3(1), dim3(512), 0, st, rpart, RB, (job == 1 || job == 6) ? 1 : 0,
                            P.S + S_RED);
         UVC_HIP(hipGetLastError());
-        UVC_HIP(hipMemcpyAsync(red, P.S + S_RED, sizeof(red), hipMemcpyDeviceToHost, st));
+        // the whole scalar block: the reduction and the directions' budget-row
+        // components come back in one copy
+        UVC_HIP(hipMemcpyAsync(hS, P.S, sizeof(hS), hipMemcpyDeviceToHost, st));
         UVC_HIP(hipStreamSynchronize(st));
+        for (int q = 0; q < IPM_SUMS; ++q) red[q] = hS[S_RED + q];
         return UVC_OK;
     };
 
@@ -1213,24 +1217,21 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
                 hipLaunchKernelGGL(k_dir_d, dim3(gK), dim3(LP_TB), 0, st, P, K, d, A.res);
             };
             auto steps = [&](int d, double& ap, double& ad, double& dyb, double& dsb) -> uvc_status {
-                UVC_TRY(reduce(1, d, 0.0, 0.0));
-                double sc3[3];
-                UVC_HIP(hipMemcpyAsync(sc3, P.S + 3 * d, sizeof(sc3), hipMemcpyDeviceToHost, st));
-                UVC_HIP(hipStreamSynchronize(st));
-                dyb = sc3[1];
-                dsb = sc3[2];
+                UVC_TRY(reduce(1, d, 0.0, 0.0));  // also brings back S[3 d + 1], S[3 d + 2]
+                dyb = hS[3 * d + 1];
+                dsb = hS[3 * d + 2];
                 ap = std::min(1.0, red[0]);
                 ad = std::min(1.0, red[1]);
                 if (dsb < 0.0 && sb > 0.0) ap = std::min(ap, -sb / dsb);
                 if (dyb < 0.0 && yb > 0.0) ad = std::min(ad, -yb / dyb);
                 return UVC_OK;
             };
+            // the factorization's failure flag comes back with the next synchronisation
+            int f = 0;
+            UVC_HIP(hipMemcpyAsync(&f, failf, 4, hipMemcpyDeviceToHost, st));
             direction(RhsArgs{0, 0, 0.0, 0.0, 0.0, 1.0}, 0, -sb * yb);
             double ap = 1.0, ad = 1.0, dyb0 = 0.0, dsb0 = 0.0;
             UVC_TRY(steps(0, ap, ad, dyb0, dsb0));
-            int f = 0;
-            UVC_HIP(hipMemcpyAsync(&f, failf, 4, hipMemcpyDeviceToHost, st));
-            UVC_HIP(hipStreamSynchronize(st));
             if (f != 0) break;
             UVC_TRY(reduce(2, 0, ap, ad));
             const double gaff = red[0] + (sb + ap * dsb0) * (yb + ad * dyb0);

@@ -24,6 +24,7 @@
 #include "uvc_common.hpp"
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <vector>
 
@@ -42,7 +43,9 @@ __global__ void k_lp_colstats(const float* __restrict__ E, int64_t K, int64_t N,
     if (i < N)
         for (int64_t k = k0; k < k1; ++k) {
             const float v = E[k * N + i];
-            mx = fmaxf(mx, fabsf(v));
+            // NaN and Inf both record Inf (fmaxf would drop a NaN), which the
+            // host reports as a non-finite entry
+            mx = (fabsf(v) <= FLT_MAX) ? fmaxf(mx, fabsf(v)) : INFINITY;
             sq += (double)v * (double)v;
         }
     if (i < N) {

@@ -71,6 +71,11 @@ def test_lp_input_errors(uvc):
     sol = uvc.solve_lp(E)  # nothing visible: t = 0, sigma = mu
     assert sol["n_visible"] == 0 and float(sol["t"].abs().sum()) == 0.0
     assert torch.all(sol["sigma"] == 280.0)
+    for bad in (float("nan"), float("inf"), -float("inf")):
+        Eb = torch.ones((3, 4), dtype=torch.float32, device="cuda")
+        Eb[1, 2] = bad
+        with pytest.raises(uvc.UvcError, match="non-finite"):
+            uvc.solve_lp(Eb)
 
 
 @pytest.mark.parametrize("seed,K,N,t_max", [(0, 40, 300, 3.6e5), (2, 60, 400, 500.0)])

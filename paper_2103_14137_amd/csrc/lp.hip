@@ -405,39 +405,86 @@ __device__ __forceinline__ double lane_bcast(double v, int c) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Solve L L^T x = r in place (one workgroup of 1024 threads).  Each 64 x 64
-// diagonal block is staged in LDS and solved by one wave, lane r holding
-// unknown r (column-oriented substitution with lane broadcasts); the other
-// rows are then updated by all threads.
-__global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ L, int64_t K, double* __restrict__ x) {
-    __shared__ double Lb[64][65];
-    __shared__ double zb[64];
-    __shared__ double rd[64];  // 1 / diagonal of the staged block
+// Blocked triangular solves spread over the chip, one launch per 64-row
+// block.  Forward (L z = r): launch j0 applies the solved block jp = j0 - 64
+// to every row below it (workgroup 0 to the rows of block j0, the others to
+// the rows from j0 + 64 on, 64 rows each) and workgroup 0 then solves the
+// diagonal block j0 (one wave, lane r holding unknown r).  Backward (L^T x
+// = z): launch j0 applies the solved block jq = j0 + 64 to every unknown
+// before it (workgroup 0 to those of block j0, the others to 256 unknowns
+// each below j0) and workgroup 0 then solves the transposed block j0.  Only
+// workgroup 0 writes the unknowns of block j0, and the next launch reads
+// them, so no launch depends on another workgroup of itself.
+constexpr int TS_B = 64;      // block size
+constexpr int TS_ROWS = 64;   // rows per workgroup in the forward update
+constexpr int TS_COLS = 256;  // unknowns per workgroup in the backward update
+
+// x[r] -= sum_c L[r][jp + c] z[c] for rows r in [r0, r1): 16 lanes per row
+// (4 columns each), 16 rows per pass of 256 threads, the loads of four passes
+// issued together.
+__device__ __forceinline__ void ts_fwd_rows(const double* __restrict__ L, int64_t K, double* __restrict__ x,
+                                            int64_t jp, int nbp, const double* zb, int64_t r0, int64_t r1) {
+    const int tid = threadIdx.x, rg = tid >> 4, l16 = tid & 15;
+    const int c0 = l16 < nbp ? l16 : 0, c1 = l16 + 16 < nbp ? l16 + 16 : 0;
+    const int c2 = l16 + 32 < nbp ? l16 + 32 : 0, c3 = l16 + 48 < nbp ? l16 + 48 : 0;
+    const double z0 = l16 < nbp ? zb[l16] : 0.0, z1 = l16 + 16 < nbp ? zb[l16 + 16] : 0.0;
+    const double z2 = l16 + 32 < nbp ? zb[l16 + 32] : 0.0, z3 = l16 + 48 < nbp ? zb[l16 + 48] : 0.0;
+    for (int64_t rb = r0 + rg; rb < r1; rb += 64) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t r = rb + 16 * u;
+            v[u] = 0.0;
+            if (r < r1) {
+                const double* row = L + r * K + jp;
+                v[u] = row[c0] * z0 + row[c1] * z1 + row[c2] * z2 + row[c3] * z3;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            for (int o = 8; o > 0; o >>= 1) v[u] += __shfl_xor(v[u], o, 16);
+            const int64_t r = rb + 16 * u;
+            if (l16 == 0 && r < r1) x[r] -= v[u];
+        }
+    }
+}
+
+// x[c] -= sum_q L[jq + q][c] z[q] for unknowns c in [c0, c1): thread per
+// unknown (coalesced across threads), 32 loads issued together.
+__device__ __forceinline__ void ts_bwd_cols(const double* __restrict__ L, int64_t K, double* __restrict__ x,
+                                            int64_t jq, int nbq, const double* zb, int64_t c0, int64_t c1) {
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int q = 0;
+        for (; q + 32 <= nbq; q += 32) {
+            double l[32];
+#pragma unroll
+            for (int u = 0; u < 32; ++u) l[u] = L[(jq + q + u) * K + c];
+#pragma unroll
+            for (int u = 0; u < 32; ++u) a[u & 7] += l[u] * zb[q + u];
+        }
+        for (; q < nbq; ++q) a[0] += L[(jq + q) * K + c] * zb[q];
+        x[c] -= ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    }
+}
+
+// Diagonal block at j0 (size nb), in place on x[j0 .. j0 + nb): forward
+// (lower) or backward (transposed).  All threads stage; wave 0 solves.
+__device__ __forceinline__ void ts_diag(const double* __restrict__ L, int64_t K, double* __restrict__ x, int64_t j0,
+                                        int nb, bool transposed, double (*Lb)[TS_B + 1], double* zb, double* rd) {
     const int tid = threadIdx.x;
-    // forward: L z = r
-    for (int64_t j0 = 0; j0 < K; j0 += 64) {
-        const int nb = (int)((K - j0) < 64 ? (K - j0) : 64);
-        {
-            // stage the block: the loads of all four passes first
-            double t[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int q = tid + 1024 * u, r = q / nb, c = q % nb;
-                t[u] = (q < nb * nb && c <= r) ? L[(j0 + r) * K + j0 + c] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int q = tid + 1024 * u;
-                if (q < nb * nb) Lb[q / nb][q % nb] = t[u];
-            }
-        }
-        if (tid < nb) {
-            zb[tid] = x[j0 + tid];
-            rd[tid] = 1.0 / L[(j0 + tid) * K + j0 + tid];
-        }
-        __syncthreads();
-        if (tid < 64) {
-            double v = tid < nb ? zb[tid] : 0.0;
+    for (int q = tid; q < TS_B * TS_B; q += blockDim.x) {
+        const int r = q / TS_B, c = q % TS_B;
+        Lb[r][c] = (r < nb && c <= r) ? L[(j0 + r) * K + j0 + c] : 0.0;
+    }
+    if (tid < nb) {
+        zb[tid] = x[j0 + tid];
+        rd[tid] = 1.0 / L[(j0 + tid) * K + j0 + tid];
+    }
+    __syncthreads();
+    if (tid < 64) {
+        double v = tid < nb ? zb[tid] : 0.0;
+        if (!transposed) {
             for (int c = 0; c < nb; ++c) {
                 const double zc = lane_bcast(v, c) * rd[c];
                 if (tid == c)
@@ -445,67 +492,7 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ 
                 else if (tid > c && tid < nb)
                     v -= Lb[tid][c] * zc;
             }
-            if (tid < nb) {
-                zb[tid] = v;
-                x[j0 + tid] = v;
-            }
-        }
-        __syncthreads();
-        // rows below: 16 lanes per row (4 columns each, read contiguously by the
-        // 16 lanes), 64 rows per pass of the workgroup and 4 passes unrolled so
-        // that each thread keeps 16 loads in flight
-        {
-            const int rg = tid >> 4, l16 = tid & 15;
-            const double z0 = l16 < nb ? zb[l16] : 0.0, z1 = l16 + 16 < nb ? zb[l16 + 16] : 0.0;
-            const double z2 = l16 + 32 < nb ? zb[l16 + 32] : 0.0, z3 = l16 + 48 < nb ? zb[l16 + 48] : 0.0;
-            const int c1 = l16 + 16 < nb ? l16 + 16 : 0, c2 = l16 + 32 < nb ? l16 + 32 : 0;
-            const int c3 = l16 + 48 < nb ? l16 + 48 : 0, c0 = l16 < nb ? l16 : 0;
-            for (int64_t rb = j0 + nb + rg; rb < K; rb += 256) {
-                double v[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int64_t r = rb + 64 * u;
-                    v[u] = 0.0;
-                    if (r < K) {
-                        const double* row = L + r * K + j0;
-                        v[u] = row[c0] * z0 + row[c1] * z1 + row[c2] * z2 + row[c3] * z3;
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    for (int o = 8; o > 0; o >>= 1) v[u] += __shfl_xor(v[u], o, 16);
-                    const int64_t r = rb + 64 * u;
-                    if (l16 == 0 && r < K) x[r] -= v[u];
-                }
-            }
-        }
-        __syncthreads();
-    }
-    // backward: L^T x = z
-    for (int64_t j1 = K; j1 > 0; j1 -= 64) {
-        const int64_t j0 = j1 >= 64 ? j1 - 64 : 0;
-        const int nb = (int)(j1 - j0);
-        {
-            // stage the block: the loads of all four passes first
-            double t[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int q = tid + 1024 * u, r = q / nb, c = q % nb;
-                t[u] = (q < nb * nb && c <= r) ? L[(j0 + r) * K + j0 + c] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int q = tid + 1024 * u;
-                if (q < nb * nb) Lb[q / nb][q % nb] = t[u];
-            }
-        }
-        if (tid < nb) {
-            zb[tid] = x[j0 + tid];
-            rd[tid] = 1.0 / L[(j0 + tid) * K + j0 + tid];
-        }
-        __syncthreads();
-        if (tid < 64) {
-            double v = tid < nb ? zb[tid] : 0.0;
+        } else {
             for (int c = nb - 1; c >= 0; --c) {
                 const double zc = lane_bcast(v, c) * rd[c];
                 if (tid == c)
@@ -513,33 +500,67 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ 
                 else if (tid < c)
                     v -= Lb[c][tid] * zc;
             }
-            if (tid < nb) {
-                zb[tid] = v;
-                x[j0 + tid] = v;
-            }
         }
-        __syncthreads();
-        // rows above: thread r reads column r of the block's rows (coalesced
-        // across threads); 32 loads are issued before their products are
-        // summed into 8 independent partial sums
-        for (int64_t r = tid; r < j0; r += 1024) {
-            double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            int q = 0;
-            for (; q + 32 <= nb; q += 32) {
-                double l[32];
-#pragma unroll
-                for (int u = 0; u < 32; ++u) l[u] = L[(j0 + q + u) * K + r];
-#pragma unroll
-                for (int u = 0; u < 32; ++u) a[u & 7] += l[u] * zb[q + u];
-            }
-            for (; q < nb; ++q) a[0] += L[(j0 + q) * K + r] * zb[q];
-            x[r] -= ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-        }
-        __syncthreads();
+        if (tid < nb) x[j0 + tid] = v;
     }
 }
 
+__global__ __launch_bounds__(256) void k_ts_fwd(const double* __restrict__ L, int64_t K, double* __restrict__ x,
+                                                int64_t j0) {
+    __shared__ double Lb[TS_B][TS_B + 1];
+    __shared__ double zb[TS_B], rd[TS_B];
+    const int nb = (int)std::min<int64_t>(TS_B, K - j0);
+    const int64_t jp = j0 - TS_B;
+    if (jp >= 0) {
+        if (threadIdx.x < TS_B) zb[threadIdx.x] = x[jp + threadIdx.x];
+        __syncthreads();
+        if (blockIdx.x == 0) {
+            ts_fwd_rows(L, K, x, jp, TS_B, zb, j0, j0 + nb);
+        } else {
+            const int64_t r0 = j0 + TS_B + (int64_t)(blockIdx.x - 1) * TS_ROWS;
+            ts_fwd_rows(L, K, x, jp, TS_B, zb, r0, std::min<int64_t>(K, r0 + TS_ROWS));
+        }
+        __syncthreads();
+    }
+    if (blockIdx.x == 0) ts_diag(L, K, x, j0, nb, false, Lb, zb, rd);
+}
+
+__global__ __launch_bounds__(256) void k_ts_bwd(const double* __restrict__ L, int64_t K, double* __restrict__ x,
+                                                int64_t j0) {
+    __shared__ double Lb[TS_B][TS_B + 1];
+    __shared__ double zb[TS_B], rd[TS_B];
+    const int nb = (int)std::min<int64_t>(TS_B, K - j0);
+    const int64_t jq = j0 + TS_B;
+    if (jq < K) {
+        const int nbq = (int)std::min<int64_t>(TS_B, K - jq);
+        if (threadIdx.x < nbq) zb[threadIdx.x] = x[jq + threadIdx.x];
+        __syncthreads();
+        if (blockIdx.x == 0) {
+            ts_bwd_cols(L, K, x, jq, nbq, zb, j0, j0 + nb);
+        } else {
+            const int64_t c0 = (int64_t)(blockIdx.x - 1) * TS_COLS;
+            ts_bwd_cols(L, K, x, jq, nbq, zb, c0, std::min<int64_t>(j0, c0 + TS_COLS));
+        }
+        __syncthreads();
+    }
+    if (blockIdx.x == 0) ts_diag(L, K, x, j0, nb, true, Lb, zb, rd);
+}
+
 static inline unsigned nblk(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + LP_TB - 1) / LP_TB); }
+
+// L L^T x = r in place (L in the lower part of M): one launch per block and sweep.
+static void tri_solve(const double* M, int64_t K, double* x, hipStream_t st) {
+    for (int64_t j0 = 0; j0 < K; j0 += TS_B) {
+        const int64_t below = std::max<int64_t>(0, K - (j0 + TS_B));
+        const unsigned g = 1u + (unsigned)((below + TS_ROWS - 1) / TS_ROWS);
+        hipLaunchKernelGGL(k_ts_fwd, dim3(j0 == 0 ? 1u : g), dim3(256), 0, st, M, K, x, j0);
+    }
+    const int64_t last = ((K - 1) / TS_B) * TS_B;
+    for (int64_t j0 = last; j0 >= 0; j0 -= TS_B) {
+        const unsigned g = 1u + (unsigned)((j0 + TS_COLS - 1) / TS_COLS);
+        hipLaunchKernelGGL(k_ts_bwd, dim3(j0 == last ? 1u : g), dim3(256), 0, st, M, K, x, j0);
+    }
+}
 
 // -------------------------------------------------- interior point kernels
 // Iterate (device, FP64): x = (t[K], sigma[N]), z = (zt[K], zs[N]),
@@ -1134,14 +1155,14 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
             hipLaunchKernelGGL(k_st_N, dim3(gN), dim3(LP_TB), 0, st, P, N, 0, 1.0);
             Ev(P.u, P.mvK);
             hipLaunchKernelGGL(k_st_K, dim3(gK), dim3(LP_TB), 0, st, P, K, 0, tmax);
-            hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), 0, st, M, K, P.xt);
+            tri_solve(M, K, P.xt, st);
             Etu(P.xt, P.mvN);
             hipLaunchKernelGGL(k_st_N, dim3(gN), dim3(LP_TB), 0, st, P, N, 1, 1.0);
             Etu(P.dt[1], P.mvN);
             hipLaunchKernelGGL(k_st_N, dim3(gN), dim3(LP_TB), 0, st, P, N, 2, 1.0);
             Ev(P.u, P.mvK);
             hipLaunchKernelGGL(k_st_K, dim3(gK), dim3(LP_TB), 0, st, P, K, 1, (double)K);
-            hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), 0, st, M, K, P.dt[0]);
+            tri_solve(M, K, P.dt[0], st);
             Etu(P.dt[0], P.mvN);
             hipLaunchKernelGGL(k_st_N, dim3(gN), dim3(LP_TB), 0, st, P, N, 3, 1.0);
             UVC_TRY(reduce(5, 0, 0.0, 0.0));
@@ -1212,7 +1233,7 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
                 hipLaunchKernelGGL(k_dir_a, dim3(gN), dim3(LP_TB), 0, st, P, N, A);
                 Ev(P.u, P.mvK);
                 hipLaunchKernelGGL(k_dir_b, dim3(gK), dim3(LP_TB), 0, st, P, K, A, wvb, d);
-                hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), 0, st, M, K, P.dt[d]);
+                tri_solve(M, K, P.dt[d], st);
                 Etu(P.dt[d], P.mvN);
                 hipLaunchKernelGGL(k_ipm_bscal, dim3(1), dim3(LP_TB), 0, st, P, K, d, Db, rppb, rsyb, sb, yb);
                 hipLaunchKernelGGL(k_dir_c, dim3(gN), dim3(LP_TB), 0, st, P, N, A, d);

@@ -293,7 +293,7 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
     const double rc_tol = 1e-6;
     // rounds that add poses solve to a looser tolerance; once pricing finds
     // nothing, the same set is solved to tol and priced again
-    const double tol_loose = std::max(tol, 1e-6);
+    const double tol_loose = std::max(tol, 1e-4);
     bool final_pass = tol_loose <= tol;
     std::vector<uint8_t> in_set((size_t)K, 0), dark((size_t)N, 0);  // dark: no candidate sees it
     for (int32_t k : kept) in_set[(size_t)k] = 1;

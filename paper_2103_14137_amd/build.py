@@ -72,5 +72,5 @@ def build_asm(out_dir: str) -> None:
 if __name__ == "__main__":
     build(verbose=True)
     if len(sys.argv) > 1 and sys.argv[1] == "--asm":
-        build_asm(sys.argv[2] if len(sys.argv) > 2 else os.path.join(ROOT, "_work", "asm"))
+        build_asm(sys.argv[2] if len(sys.argv) > 2 else os.path.join(ROOT, "_build", "asm"))
     print(LIB)

@@ -313,9 +313,8 @@ constexpr int LP_CENTRALITY = 2;  // centrality correctors tried per iteration
 // A[r][j] A[c][j] / A[j][j] from every entry below and right of the pivot
 // (one barrier per step); afterwards column j is scaled by 1 / sqrt(A[j][j]),
 // which gives L with L[j][j] = sqrt(A[j][j]).
-__global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ M, int64_t K, int64_t j0, int nb,
-                                                   int* __restrict__ fail) {
-    __shared__ double A[CH_B][CH_B + 1];
+__device__ __forceinline__ void chol_diag_block(double* __restrict__ M, int64_t K, int64_t j0, int nb,
+                                                int* __restrict__ fail, double (*A)[CH_B + 1]) {
     for (int q = threadIdx.x; q < nb * nb; q += 256) {
         const int r = q / nb, c = q % nb;
         A[r][c] = (c <= r) ? M[(j0 + r) * K + j0 + c] : 0.0;
@@ -338,6 +337,12 @@ __global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ M, int64
         const int r = q / nb, c = q % nb;
         if (c <= r) M[(j0 + r) * K + j0 + c] = A[r][c] / sqrt(fmax(A[c][c], 1e-300));
     }
+}
+
+__global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ M, int64_t K, int64_t j0, int nb,
+                                                   int* __restrict__ fail) {
+    __shared__ double A[CH_B][CH_B + 1];
+    chol_diag_block(M, K, j0, nb, fail, A);
 }
 
 // Rows r >= j0 + nb: L[r, j0:j0+nb] = M[r, j0:j0+nb] L_jj^-T (one row per
@@ -367,10 +372,14 @@ __global__ __launch_bounds__(256) void k_chol_trsm(double* __restrict__ M, int64
 }
 
 // Trailing update of the lower part: M[a][b] -= sum_q L[a][j0+q] L[b][j0+q]
-// for a >= b >= j0 + nb, tiles of 64 x 64.
-__global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ M, int64_t K, int64_t j0, int nb) {
+// for a >= b >= j0 + nb, tiles of 64 x 64.  The workgroup of the first tile,
+// which holds the whole next diagonal block (size next_nb <= CH_B), then
+// factors that block, so the next panel needs no separate launch for it.
+__global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ M, int64_t K, int64_t j0, int nb,
+                                                     int next_nb, int* __restrict__ fail) {
     __shared__ double As[CH_B][SY_T + 1];
     __shared__ double Bs[CH_B][SY_T + 1];
+    __shared__ double Ad[CH_B][CH_B + 1];
     const int64_t t = blockIdx.x;
     int64_t tr = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
     while ((tr + 1) * (tr + 2) / 2 <= t) ++tr;
@@ -395,6 +404,10 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ M, int
             const int64_t a = a0 + ty * 4 + u, b = b0 + tx * 4 + v;
             if (a < K && b <= a) M[a * K + b] -= acc[u][v];
         }
+    if (t == 0 && next_nb > 0) {
+        __syncthreads();
+        chol_diag_block(M, K, base, next_nb, fail, Ad);
+    }
 }
 
 // Lane c's value of v for the whole wave (c uniform): two v_readlane.
@@ -1132,14 +1145,16 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
             UVC_HIP(hipMemsetAsync(failf, 0, 4, st));
             for (int64_t j0 = 0; j0 < K; j0 += CH_B) {
                 const int nb = (int)std::min<int64_t>(CH_B, K - j0);
-                hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, M, K, j0, nb, failf);
+                // later diagonal blocks are factored by the previous panel's update
+                if (j0 == 0) hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, M, K, j0, nb, failf);
                 const int64_t rest = K - j0 - nb;
                 if (rest > 0) {
                     hipLaunchKernelGGL(k_chol_trsm, dim3((unsigned)((rest + 255) / 256)), dim3(256), 0, st, M, K, j0,
                                        nb);
                     const int64_t T2 = (rest + SY_T - 1) / SY_T;
+                    const int next_nb = (int)std::min<int64_t>(CH_B, rest);
                     hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(T2 * (T2 + 1) / 2)), dim3(256), 0, st, M, K,
-                                       j0, nb);
+                                       j0, nb, next_nb, failf);
                 }
             }
             UVC_HIP(hipGetLastError());

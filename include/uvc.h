@@ -232,7 +232,7 @@ void uvc_csr_job_destroy(uvc_csr_job* job);
 
 /* Pick the fastest launch options for this scene's size class: the first
  * probe_poses poses (<= 0: 256) are computed with every hierarchy variant
- * (packet_poses 1/4/16/64 x waves 5/6/8) and, for meshes of up to 200k
+ * (packet_poses 4/8/16/32/64 x waves 5/6/8) and, for meshes of up to 200k
  * triangles, every brute-force LDS tile (256..2048); each is timed with HIP
  * events and scored in occlusion rays per second.  The winner is stored in
  * the JSON table at table_path (NULL: no table) under the key

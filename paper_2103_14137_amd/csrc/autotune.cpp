@@ -135,7 +135,7 @@ extern "C" uvc_status uvc_autotune(const uvc_scene* scene, const float* poses_de
         return uvc::fail(UVC_ENOMEM, "autotune probe buffers");
     }
     std::vector<Entry> cands;
-    for (int tp : {1, 4, 16, 64})
+    for (int tp : {4, 8, 16, 32, 64})
         for (int w : {5, 6, 8}) {
             Entry e;
             e.path = UVC_PATH_LBVH;

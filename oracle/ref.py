@@ -46,6 +46,9 @@ def lib():
         L.oracle_irradiance_pairs.argtypes = [_P, _P, _I64, _P, _I64, _I32, _I32, _P, _P,
                                               _P, _P, _I64, _P, _P, _I32]
         L.oracle_irradiance_pairs.restype = ctypes.c_int
+        L.oracle_irradiance_pairs_lamp.argtypes = [_P, _P, _I64, _P, _I64, _I32, _I32, _P, _P, _I32, _P,
+                                                   ctypes.c_uint32, ctypes.c_uint32, _P, _P, _I64, _P, _P, _I32]
+        L.oracle_irradiance_pairs_lamp.restype = ctypes.c_int
         L.oracle_max_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -86,9 +89,14 @@ def segment_blocked(verts, tris, O, T, skip: int = -1) -> int:
     return int(lib().oracle_segment_blocked(_ptr(v), _ptr(t), t.shape[0], _ptr(o), _ptr(tt), int(skip)))
 
 
-def irradiance_pairs(verts, tris, poses, dz, power, pk, pi, threads: int = 0):
+def irradiance_pairs(verts, tris, poses, dz, power, pk, pi, threads: int = 0, profile=None, up_mask: int = 0,
+                     down_mask: int = 0):
     """E (FP64) and visibility bits (uint32, bit j = source j) for the pairs
-    (pose pk[q], element pi[q])."""
+    (pose pk[q], element pi[q]).  profile: None (uniform emission) or the
+    emission-pattern table over cos(theta) in [-1, 1]; up_mask / down_mask:
+    sources that emit only above / below their own height."""
+    if profile is not None or up_mask or down_mask:
+        return _irradiance_pairs_lamp(verts, tris, poses, dz, power, pk, pi, threads, profile, up_mask, down_mask)
     v = _c(verts, np.float32)
     t = _c(tris, np.int32)
     p = _c(poses, np.float32)
@@ -108,12 +116,36 @@ def irradiance_pairs(verts, tris, poses, dz, power, pk, pi, threads: int = 0):
     return E, vis
 
 
-def irradiance_dense(verts, tris, poses, dz, power, threads: int = 0):
+def _irradiance_pairs_lamp(verts, tris, poses, dz, power, pk, pi, threads, profile, up_mask, down_mask):
+    v = _c(verts, np.float32)
+    t = _c(tris, np.int32)
+    p = _c(poses, np.float32)
+    K, pdim = p.shape
+    dzf = _c(dz, np.float32)
+    pw = _c(power, np.float32)
+    prof = _c(profile if profile is not None else np.zeros(0), np.float32)
+    pk = _c(pk, np.int64)
+    pi = _c(pi, np.int64)
+    npairs = pk.shape[0]
+    E = np.empty(npairs, np.float64)
+    vis = np.empty(npairs, np.uint32)
+    rc = lib().oracle_irradiance_pairs_lamp(_ptr(v), _ptr(t), t.shape[0], _ptr(p), K, pdim, dzf.shape[0],
+                                            _ptr(dzf), _ptr(pw), prof.shape[0], _ptr(prof) if prof.size else None,
+                                            int(up_mask), int(down_mask), _ptr(pk), _ptr(pi), npairs,
+                                            _ptr(E), _ptr(vis), int(threads))
+    if rc != 0:
+        raise ValueError("oracle_irradiance_pairs_lamp: invalid arguments")
+    return E, vis
+
+
+def irradiance_dense(verts, tris, poses, dz, power, threads: int = 0, profile=None, up_mask: int = 0,
+                     down_mask: int = 0):
     """Full K x N matrices (E FP64, vis uint32)."""
     K = np.asarray(poses).shape[0]
     N = np.asarray(tris).shape[0]
     kk, ii = np.meshgrid(np.arange(K), np.arange(N), indexing="ij")
-    E, vis = irradiance_pairs(verts, tris, poses, dz, power, kk.ravel(), ii.ravel(), threads)
+    E, vis = irradiance_pairs(verts, tris, poses, dz, power, kk.ravel(), ii.ravel(), threads, profile, up_mask,
+                              down_mask)
     return E.reshape(K, N), vis.reshape(K, N)
 
 
@@ -121,11 +153,18 @@ def max_threads() -> int:
     return int(lib().oracle_max_threads())
 
 
-def entry_tolerance(verts, tris, poses, dz, power, vis, pk=None, pi=None):
+def entry_tolerance(verts, tris, poses, dz, power, vis, pk=None, pi=None, profile=None):
     """Absolute tolerance per entry for comparing an FP32 irradiance with the
     FP64 oracle: 1e-5 * E64 is added by the caller; this returns the grazing
-    term 1e-5 * sum_j V_j P_j / (4 pi r_j^2), which bounds the FP32 error of
-    the cosine factor when the cosine itself is small."""
+    term 1e-5 * sum_j V_j P_j W / (4 pi r_j^2), which bounds the FP32 error of
+    the cosine factor when the cosine itself is small.  W = 1 for uniform
+    emission; with an emission table W = max(largest table value, largest
+    table step x (n - 1) / 2), which also bounds the interpolated weight's
+    FP32 error (a few ulps of cos(theta) times the table's slope)."""
+    W = 1.0
+    if profile is not None:
+        pr = np.asarray(profile, np.float64)
+        W = max(float(pr.max()), float(np.abs(np.diff(pr)).max()) * (pr.size - 1) / 2.0)
     c32, _, _, _ = elements(verts, tris)
     p = np.asarray(poses, np.float32)
     pdim = p.shape[1]
@@ -143,5 +182,5 @@ def entry_tolerance(verts, tris, poses, dz, power, vis, pk=None, pi=None):
         d = np.stack([p[pk, 0], p[pk, 1], pz], -1).astype(np.float64) - c32[pi].astype(np.float64)
         r2 = (d * d).sum(-1)
         on = ((vis >> j) & 1).astype(bool)
-        tol += np.where(on, float(pw) / (4.0 * np.pi * r2), 0.0)
+        tol += np.where(on, float(pw) * W / (4.0 * np.pi * r2), 0.0)
     return 1e-5 * tol

@@ -109,21 +109,47 @@ int oracle_segment_blocked(const float* verts, const int32_t* tris, int64_t n,
     return 0;
 }
 
+/* Angular emission weight of a source (Sec. IV-C allows point sources with
+ * their own emission pattern; the default is uniform, weight 1).  The
+ * pattern is a table of n_prof >= 2 values at cos(theta) = -1 + 2 q /
+ * (n_prof - 1), q = 0 .. n_prof - 1, interpolated linearly; theta is the
+ * angle between the upward vertical through the source and the direction
+ * from the source to the element. */
+static double emission_weight(double cos_theta, int32_t n_prof, const float* prof)
+{
+    if (n_prof <= 0) return 1.0;
+    double u = (cos_theta + 1.0) * 0.5 * (double)(n_prof - 1);
+    if (u < 0.0) u = 0.0;
+    if (u > (double)(n_prof - 1)) u = (double)(n_prof - 1);
+    int q = (int)floor(u);
+    if (q > n_prof - 2) q = n_prof - 2;
+    double f = u - (double)q;
+    return (double)prof[q] + f * ((double)prof[q + 1] - (double)prof[q]);
+}
+
 /* Irradiance entries for a list of (pose, element) pairs.
  *   poses: K x pose_dim floats (x, y) or (x, y, z); source j sits at
  *          (x, y, z + dz[j]) with the height sum taken in FP32 (z = 0 for
  *          pose_dim 2).
  *   E_out[p]   = sum over sources j (ascending) of
- *                P_j * max(0, <p_j - c, n>) / (4 pi |p_j - c|^3) * V_j
- *   vis_out[p] = bit j set iff V_j = 1 (front-facing and unoccluded).
+ *                P_j * w_j * max(0, <p_j - c, n>) / (4 pi |p_j - c|^3) * V_j
+ *   vis_out[p] = bit j set iff V_j = 1: the source emits towards the
+ *                element (hemisphere masks below), the element faces it, and
+ *                nothing blocks the segment.
+ * Emission pattern: w_j = emission_weight(cos theta) with the lamp's table
+ * (n_prof = 0: w_j = 1).  A source whose bit is set in up_mask emits only
+ * into the open half-space above its own height (element centroid z >
+ * source z), one whose bit is set in down_mask only below it.
  * The element's own triangle is excluded from its occlusion test by index. */
-int oracle_irradiance_pairs(const float* verts, const int32_t* tris, int64_t n,
-                            const float* poses, int64_t K, int32_t pose_dim,
-                            int32_t S, const float* dz, const float* power,
-                            const int64_t* pk, const int64_t* pi, int64_t npairs,
-                            double* E_out, uint32_t* vis_out, int32_t nthreads)
+int oracle_irradiance_pairs_lamp(const float* verts, const int32_t* tris, int64_t n,
+                                 const float* poses, int64_t K, int32_t pose_dim,
+                                 int32_t S, const float* dz, const float* power,
+                                 int32_t n_prof, const float* prof, uint32_t up_mask, uint32_t down_mask,
+                                 const int64_t* pk, const int64_t* pi, int64_t npairs,
+                                 double* E_out, uint32_t* vis_out, int32_t nthreads)
 {
     if (S < 1 || S > 32 || (pose_dim != 2 && pose_dim != 3)) return -1;
+    if (n_prof == 1 || n_prof > 33 || (n_prof > 1 && !prof) || (up_mask & down_mask)) return -1;
     (void)K;
     if (nthreads > 0) omp_set_num_threads(nthreads);
     const double four_pi = 4.0 * M_PI;
@@ -148,6 +174,8 @@ int oracle_irradiance_pairs(const float* verts, const int32_t* tris, int64_t n,
             float pz = zb + dz[j]; /* FP32 sum */
             float pf[3] = {pp[0], pp[1], pz};
             d3 p = ld(pf);
+            if (((up_mask >> j) & 1u) && !(c.z > p.z)) continue;
+            if (((down_mask >> j) & 1u) && !(c.z < p.z)) continue;
             if (!front64(p, c, m)) continue;
             int blocked = 0;
             for (int64_t mm = 0; mm < n && !blocked; ++mm) {
@@ -163,13 +191,25 @@ int oracle_irradiance_pairs(const float* verts, const int32_t* tris, int64_t n,
             double r = sqrt(r2);
             double s = dot(d, nrm);
             if (s < 0.0) s = 0.0;
-            acc += (double)power[j] * s / (four_pi * r2 * r);
+            double w = emission_weight((c.z - p.z) / r, n_prof, prof);
+            acc += (double)power[j] * w * s / (four_pi * r2 * r);
             bits |= 1u << j;
         }
         E_out[q] = acc;
         vis_out[q] = bits;
     }
     return 0;
+}
+
+/* The uniform lamp (weight 1, no hemisphere masks). */
+int oracle_irradiance_pairs(const float* verts, const int32_t* tris, int64_t n,
+                            const float* poses, int64_t K, int32_t pose_dim,
+                            int32_t S, const float* dz, const float* power,
+                            const int64_t* pk, const int64_t* pi, int64_t npairs,
+                            double* E_out, uint32_t* vis_out, int32_t nthreads)
+{
+    return oracle_irradiance_pairs_lamp(verts, tris, n, poses, K, pose_dim, S, dz, power, 0, 0, 0u, 0u, pk, pi,
+                                        npairs, E_out, vis_out, nthreads);
 }
 
 int oracle_max_threads(void) { return omp_get_max_threads(); }

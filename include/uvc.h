@@ -107,13 +107,30 @@ void uvc_destroy_scene(uvc_scene* scene);
  * ------------------------------------------------------------------------ */
 
 /* A lamp is n_src point sources mounted dz[j] metres above the pose base
- * point, each emitting power_w[j] watts isotropically (Sec. IV-C: an extended
- * lamp as evenly distributed point sources of equal power).  Host arrays,
- * copied by the call.  1 <= n_src <= 32, power_w[j] > 0, dz[j] finite. */
+ * point, each emitting power_w[j] watts (Sec. IV-C: an extended lamp as
+ * point sources of equal power; each source may have its own emission
+ * pattern).  Host arrays, copied by the call.  1 <= n_src <= 32,
+ * power_w[j] > 0, dz[j] finite.
+ * Emission pattern (optional; zero-initialised fields = uniform emission):
+ *   n_prof, profile: 0 (uniform, weight 1) or 2..33 finite weights >= 0, not
+ *     all 0, at cos(theta) = -1 + 2 q / (n_prof - 1), q = 0 .. n_prof - 1,
+ *     interpolated linearly; theta is the angle between the upward vertical
+ *     through the source and the direction from the source to the element.
+ *     The source's term P_j / (4 pi) <d, n> / |d|^3 is multiplied by the
+ *     weight.
+ *   up_mask / down_mask: bit j set = source j emits only into the open
+ *     half-space above (element centroid z > source z) / below its own
+ *     height (a shield); a source may not be in both.  Where a source does
+ *     not emit, no segment is cast and its visibility bit is 0.
+ * The many-room batch (uvc_batch_*) takes uniform lamps only. */
 typedef struct {
     int32_t n_src;
     const float* dz;
     const float* power_w;
+    int32_t n_prof;
+    const float* profile;
+    uint32_t up_mask;
+    uint32_t down_mask;
 } uvc_lamp;
 
 enum { UVC_PATH_AUTO = 0, UVC_PATH_LBVH = 1, UVC_PATH_BRUTE = 2 };
@@ -291,7 +308,14 @@ typedef struct {
 /* Solve  min sum_k t_k + sum_i p_i sigma_i
  *        s.t. sum_k E[k,i] t_k + sigma_i >= mu_min (every visible element),
  *             sum_k t_k <= t_max, t >= 0, sigma >= 0
- * for the dense pose-major E_dev (K x N FP32, device).  Elements with
+ * (Sec. IV-D, relaxed LP) for the pose-major K x N matrix E on the device,
+ * given either dense (row_ptr_dev = NULL: E_dev holds K x N FP32, row k =
+ * pose k) or as CSR (row_ptr_dev: K + 1 int64 offsets starting at 0;
+ * col_dev: nnz = row_ptr[K] int32 element indices, strictly ascending within
+ * each row, in [0, N); E_dev: the nnz FP32 values), e.g. the output of
+ * uvc_compute_irradiance_csr_*.  A CSR input is validated on the device (a
+ * bad row is named in the error) and expanded once into a library-owned
+ * dense copy of K N 4 bytes for the normal-matrix products.  Elements with
  * E[k,i] = 0 for every k are dropped (sigma_i = mu_min, excluded from the
  * objective).  penalty_dev: N FP64 device values or NULL for
  * p_i = 1.001 * ||E||_F (the paper asks for p_i > ||I||_F).  Mehrotra
@@ -303,9 +327,12 @@ typedef struct {
  * (for a dropped element, its penalty p_i: its sigma_i = mu_min lies inside
  * its bound) followed by the dual of the time-budget row.  With them the
  * reduced cost of any further pose k is 1 + y_N - sum_i E[k,i] y_i.
- * Returns UVC_ENOTCONV with the last point when max_iter is reached.
- * Synchronises hip_stream. */
-uvc_status uvc_solve_dosage_lp(const float* E_dev, int64_t K, int64_t N,
+ * K = 0 or N = 0: UVC_OK with t = 0, sigma = mu_min, coverage duals equal
+ * to the penalties (0 for the default penalty of an empty matrix), budget
+ * dual 0 and objective 0.  Returns UVC_ENOTCONV with the last point when
+ * max_iter is reached.  Synchronises hip_stream. */
+uvc_status uvc_solve_dosage_lp(const float* E_dev, const int64_t* row_ptr_dev,
+                               const int32_t* col_dev, int64_t K, int64_t N,
                                const double* penalty_dev, double mu_min,
                                double t_max, double tol, int32_t max_iter,
                                double* t_out_dev, double* sigma_out_dev,
@@ -391,8 +418,12 @@ typedef struct {
  * (ties: lower index) form the restricted set.  Each round assembles E on
  * the restricted set (opts as for the dense call) and solves the relaxed LP
  * (tol, max_iter as for uvc_solve_dosage_lp) with the penalty p for every
- * element (penalty <= 0: 1.001 ||E_R||_F sqrt(K / |R|), an estimate of the
- * default 1.001 ||E||_F from the first restricted matrix E_R).  With its
+ * element (penalty <= 0: the LP's default 1.001 ||E||_F over all K poses,
+ * from one pass of the dense kernel over pose blocks that keeps only the
+ * norm, so that the restricted LPs and the pricing solve the LP over all
+ * K poses; the fallback passes the caller's penalty on, so that it is
+ * exactly the full plan, whose default is the same p up to the order of
+ * the norm's sum).  With its
  * duals y, every pruned pose k gets the reduced cost
  * 1 + y_b - sum_i E[k,i] y_i, summed over the elements with y_i > 1e-9
  * max y (their E columns over all K poses come from the targets kernel;
@@ -400,7 +431,7 @@ typedef struct {
  * -1e-6 the restricted plan is optimal for the LP over all K poses and is
  * returned; otherwise up to max(16, |R_0|) poses with the most negative
  * reduced costs join and the next round starts.  Rounds that go on to add
- * poses solve their LP to max(tol, 1e-6); when pricing finds nothing the
+ * poses solve their LP to max(tol, 1e-4); when pricing finds nothing the
  * same set is solved to tol and priced once more before the plan is
  * accepted.  After max_rounds rounds that added poses with pricing still
  * negative, or if an LP does not converge, the

@@ -26,6 +26,7 @@
 #include <cfloat>
 #include <cmath>
 #include <cstring>
+#include <string>
 
 namespace uvc {
 
@@ -35,6 +36,11 @@ struct LampArgs {
     int32_t S;
     float dz[32];
     float pw[32];  // P_j / (4 pi)
+    // emission pattern (read by the lamp-variant kernels only)
+    int32_t nprof;     // 0: uniform; else the table's node count (2..33)
+    float ph;          // (nprof - 1) / 2
+    float prof[33];
+    uint32_t up, down; // hemisphere masks
 };
 
 struct IrrParams {
@@ -199,6 +205,42 @@ __device__ __forceinline__ float entry_term(float dx, float dy, float dz, float 
     const float ri = __builtin_amdgcn_rsqf(r2);
     const float w = (pw * fmaxf(s, 0.0f)) * ((ri * ri) * ri);
     return fmaxf(w, FLT_MIN);
+}
+
+// The same term times the source's emission weight: the lamp's table
+// interpolated at cos(theta) = -dz / |d| (d = source - element, so -dz is
+// the element's height above the source).  Table entries are uniform; the
+// two bracketing entries are picked with a select chain, not an indexed
+// load.
+__device__ __forceinline__ float entry_term_weighted(float dx, float dy, float dz, float s, float pw,
+                                                     const LampArgs& L) {
+#pragma clang fp contract(off)
+    const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+    const float ri = __builtin_amdgcn_rsqf(r2);
+    float wgt = 1.0f;
+    if (L.nprof > 0) {
+        const int last = L.nprof - 1;
+        const float ct = -dz * ri;
+        const float u = fminf(fmaxf((ct + 1.0f) * L.ph, 0.0f), (float)last);
+        const int q = min((int)u, last - 1);
+        const float f = u - (float)q;
+        float a = L.prof[0], b = L.prof[1];
+        for (int qq = 1; qq < last; ++qq) {
+            const bool here = q == qq;
+            a = here ? L.prof[qq] : a;
+            b = here ? L.prof[qq + 1] : b;
+        }
+        wgt = a + f * (b - a);
+    }
+    const float w = ((pw * fmaxf(s, 0.0f)) * ((ri * ri) * ri)) * wgt;
+    return fmaxf(w, FLT_MIN);
+}
+
+// Does source j emit towards a point at height cz (source height oz)?
+__device__ __forceinline__ bool lamp_emits(const LampArgs& L, int j, float cz, float oz) {
+    if ((L.up >> j) & 1u) return cz > oz;
+    if ((L.down >> j) & 1u) return cz < oz;
+    return true;
 }
 
 __device__ __forceinline__ float cos_numerator(float dx, float dy, float dz, float nx, float ny, float nz) {
@@ -422,7 +464,7 @@ __device__ __forceinline__ unsigned long long traverse(PT& P, const Ray& r, unsi
 // the 64 segments of a source share their target and diverge only towards
 // their nearby origins.  Each lane sums its element's terms over the sources
 // in ascending order, exactly like the brute-force path.
-template <bool STATS, class PT>
+template <bool STATS, bool LV, class PT>
 __device__ __forceinline__ void irr_lbvh_packet(PT& P, const LampArgs& L, int64_t kg, int64_t quad) {
     const int lane = lane_id(), w = (int)(threadIdx.x >> 6);
     const int tkl = P.tk_log2, tel = 6 - tkl;
@@ -472,7 +514,7 @@ __device__ __forceinline__ void irr_lbvh_packet(PT& P, const LampArgs& L, int64_
         const float dx = px - e.cx, dy = py - e.cy, dz = oz - e.cz;
         const float s = cos_numerator(dx, dy, dz, e.nx, e.ny, e.nz);
         bool f = false;
-        if (ok) f = front_face(P, e, sl, px, py, oz, dx, dy, dz, s, f64_p);
+        if (ok && (!LV || lamp_emits(L, j, e.cz, oz))) f = front_face(P, e, sl, px, py, oz, dx, dy, dz, s, f64_p);
         const unsigned long long live = __ballot(f);
         if (!live) continue;
         Ray r;
@@ -517,7 +559,7 @@ __device__ __forceinline__ void irr_lbvh_packet(PT& P, const LampArgs& L, int64_
             n_vis += (unsigned long long)__popcll(__ballot(vis));
         }
         if (vis) {
-            acc = acc + entry_term(dx, dy, dz, s, L.pw[j]);
+            acc = acc + (LV ? entry_term_weighted(dx, dy, dz, s, L.pw[j], L) : entry_term(dx, dy, dz, s, L.pw[j]));
             bits |= 1u << j;
         }
     }
@@ -576,29 +618,31 @@ __device__ __forceinline__ int64_t next_item(const PersistArgs& Q, int& range, l
     return -1;
 }
 
-template <bool STATS>
+template <bool STATS, bool LV>
 __device__ __forceinline__ void irr_lbvh_body(const IrrParams& P, const PersistArgs& Q) {
     __shared__ long long item_s;
     int range = 0;
     for (int64_t item; (item = next_item(Q, range, &item_s)) >= 0;)
-        irr_lbvh_packet<STATS, const IrrParams>(P, P.lamp, item % P.kgroups, item / P.kgroups);
+        irr_lbvh_packet<STATS, LV, const IrrParams>(P, P.lamp, item % P.kgroups, item / P.kgroups);
 }
 
 // Kernel variants differ only in the occupancy the register allocator aims
-// for (waves per SIMD); which one is fastest depends on the scene.
-template <bool STATS>
+// for (waves per SIMD); which one is fastest depends on the scene.  LV: the
+// lamp has an emission pattern or hemisphere masks (a separate
+// instantiation, so that uniform lamps run the plain code).
+template <bool STATS, bool LV>
 __global__ __launch_bounds__(256) void k_irr_lbvh(IrrParams P, PersistArgs Q) {
-    irr_lbvh_body<STATS>(P, Q);
+    irr_lbvh_body<STATS, LV>(P, Q);
 }
-template <bool STATS>
+template <bool STATS, bool LV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_irr_lbvh_w6(IrrParams P,
                                                                                              PersistArgs Q) {
-    irr_lbvh_body<STATS>(P, Q);
+    irr_lbvh_body<STATS, LV>(P, Q);
 }
-template <bool STATS>
+template <bool STATS, bool LV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_irr_lbvh_w8(IrrParams P,
                                                                                              PersistArgs Q) {
-    irr_lbvh_body<STATS>(P, Q);
+    irr_lbvh_body<STATS, LV>(P, Q);
 }
 
 __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int n) {
@@ -684,12 +728,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
         // them through the constant address space (scalar loads)
         const CIrrParams& P = ((const CIrrParams*)(B.rooms))[room];
         const int64_t local = ufl64(item - B.item_off[lo]);
-        irr_lbvh_packet<false, const CIrrParams>(P, B.lamp, local % P.kgroups, local / P.kgroups);
+        irr_lbvh_packet<false, false, const CIrrParams>(P, B.lamp, local % P.kgroups, local / P.kgroups);
     }
 }
 
 // ---------------------------------------------------------- brute force
-template <bool STATS>
+template <bool STATS, bool LV>
 __global__ __launch_bounds__(256) void k_irr_brute(IrrParams P) {
     extern __shared__ float4 lds[];  // tile_tris x 3 float4
     int64_t kk, quad;
@@ -710,7 +754,7 @@ __global__ __launch_bounds__(256) void k_irr_brute(IrrParams P) {
         const float dx = px - e.cx, dy = py - e.cy, dz = oz - e.cz;
         const float s = cos_numerator(dx, dy, dz, e.nx, e.ny, e.nz);
         bool f = false;
-        if (e.valid) f = front_face(P, e, slot, px, py, oz, dx, dy, dz, s, &f64);
+        if (e.valid && (!LV || lamp_emits(P.lamp, j, e.cz, oz))) f = front_face(P, e, slot, px, py, oz, dx, dy, dz, s, &f64);
         const unsigned long long live = __ballot(f);
         Ray r;
         make_ray(r, px, py, oz, e.cx, e.cy, e.cz, e.self);
@@ -773,7 +817,8 @@ __global__ __launch_bounds__(256) void k_irr_brute(IrrParams P) {
             n_vis += (unsigned long long)__popcll(__ballot(vis));
         }
         if (vis) {
-            acc = acc + entry_term(dx, dy, dz, s, P.lamp.pw[j]);
+            acc = acc + (LV ? entry_term_weighted(dx, dy, dz, s, P.lamp.pw[j], P.lamp)
+                            : entry_term(dx, dy, dz, s, P.lamp.pw[j]));
             bits |= 1u << j;
         }
     }
@@ -861,6 +906,8 @@ __global__ void k_row_gather(const float* __restrict__ E, int64_t rows, int64_t 
 }
 
 // ------------------------------------------------------------------ host
+static bool lamp_variant(const LampArgs& L) { return L.nprof > 0 || L.up != 0u || L.down != 0u; }
+
 static uvc_status make_params(const uvc_scene* s, const float* poses, int64_t K, int32_t pd, const uvc_lamp* lamp,
                               const uvc_opts* opts, IrrParams& P) {
     if (!s) return fail(UVC_EINVAL, "scene is NULL");
@@ -878,6 +925,28 @@ static uvc_status make_params(const uvc_scene* s, const float* poses, int64_t K,
         P.lamp.dz[j] = lamp->dz[j];
         P.lamp.pw[j] = (float)((double)lamp->power_w[j] / (4.0 * M_PI));
     }
+    if (lamp->n_prof != 0) {
+        if (lamp->n_prof < 2 || lamp->n_prof > 33 || !lamp->profile)
+            return fail(UVC_EINVAL, "lamp emission table must have 2..33 entries");
+        bool any = false;
+        for (int q = 0; q < lamp->n_prof; ++q) {
+            const float v = lamp->profile[q];
+            if (!std::isfinite(v) || v < 0.f)
+                return fail(UVC_EINVAL, "lamp emission table entry " + std::to_string(q) + " must be finite and >= 0");
+            any = any || v > 0.f;
+            P.lamp.prof[q] = v;
+        }
+        if (!any) return fail(UVC_EINVAL, "lamp emission table is all zero");
+        P.lamp.nprof = lamp->n_prof;
+        P.lamp.ph = 0.5f * (float)(lamp->n_prof - 1);
+    }
+    const uint32_t srcmask = lamp->n_src == 32 ? 0xffffffffu : ((1u << lamp->n_src) - 1u);
+    if ((lamp->up_mask | lamp->down_mask) & ~srcmask)
+        return fail(UVC_EINVAL, "lamp hemisphere masks name sources beyond n_src");
+    if (lamp->up_mask & lamp->down_mask)
+        return fail(UVC_EINVAL, "a source cannot emit only upwards and only downwards");
+    P.lamp.up = lamp->up_mask;
+    P.lamp.down = lamp->down_mask;
     const float bs = opts ? opts->band_scale : 1.0f;
     if (!(bs >= 0.f)) return fail(UVC_EINVAL, "band_scale must be >= 0");
     P.tau_f = TAU_F * bs;
@@ -994,10 +1063,15 @@ static uvc_status launch_irr_impl(const IrrParams& P0, int path, hipStream_t st)
     const bool stats = P.stats != nullptr;
     if (path == UVC_PATH_BRUTE) {
         const size_t shm = (size_t)P.tile_tris * 48;  // 3 float4 per staged triangle
-        if (stats)
-            hipLaunchKernelGGL(k_irr_brute<true>, dim3((unsigned)blocks), dim3(256), shm, st, P);
+        const bool lv = lamp_variant(P.lamp);
+        if (stats && lv)
+            hipLaunchKernelGGL((k_irr_brute<true, true>), dim3((unsigned)blocks), dim3(256), shm, st, P);
+        else if (stats)
+            hipLaunchKernelGGL((k_irr_brute<true, false>), dim3((unsigned)blocks), dim3(256), shm, st, P);
+        else if (lv)
+            hipLaunchKernelGGL((k_irr_brute<false, true>), dim3((unsigned)blocks), dim3(256), shm, st, P);
         else
-            hipLaunchKernelGGL(k_irr_brute<false>, dim3((unsigned)blocks), dim3(256), shm, st, P);
+            hipLaunchKernelGGL((k_irr_brute<false, false>), dim3((unsigned)blocks), dim3(256), shm, st, P);
     } else {
         // persistent launch: as many workgroups as the variant keeps resident
         // (4 waves each, `waves` per SIMD), draining the items per XCD range
@@ -1010,14 +1084,26 @@ static uvc_status launch_irr_impl(const IrrParams& P0, int path, hipStream_t st)
         for (int x = 0; x <= 8; ++x) Q.range_off[x] = (int64_t)(blocks * (uint64_t)x / 8u);
         UVC_HIP(hipMallocAsync(reinterpret_cast<void**>(&Q.counter), 8 * sizeof(unsigned long long), st));
         hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, Q.counter, 0ull, 8);
-        if (stats)
-            hipLaunchKernelGGL(k_irr_lbvh<true>, dim3((unsigned)grid), dim3(256), 0, st, P, Q);
-        else if (waves == 8)
-            hipLaunchKernelGGL(k_irr_lbvh_w8<false>, dim3((unsigned)grid), dim3(256), 0, st, P, Q);
-        else if (waves == 6)
-            hipLaunchKernelGGL(k_irr_lbvh_w6<false>, dim3((unsigned)grid), dim3(256), 0, st, P, Q);
-        else
-            hipLaunchKernelGGL(k_irr_lbvh<false>, dim3((unsigned)grid), dim3(256), 0, st, P, Q);
+        const dim3 g((unsigned)grid), b(256);
+        if (!lamp_variant(P.lamp)) {
+            if (stats)
+                hipLaunchKernelGGL((k_irr_lbvh<true, false>), g, b, 0, st, P, Q);
+            else if (waves == 8)
+                hipLaunchKernelGGL((k_irr_lbvh_w8<false, false>), g, b, 0, st, P, Q);
+            else if (waves == 6)
+                hipLaunchKernelGGL((k_irr_lbvh_w6<false, false>), g, b, 0, st, P, Q);
+            else
+                hipLaunchKernelGGL((k_irr_lbvh<false, false>), g, b, 0, st, P, Q);
+        } else {
+            if (stats)
+                hipLaunchKernelGGL((k_irr_lbvh<true, true>), g, b, 0, st, P, Q);
+            else if (waves == 8)
+                hipLaunchKernelGGL((k_irr_lbvh_w8<false, true>), g, b, 0, st, P, Q);
+            else if (waves == 6)
+                hipLaunchKernelGGL((k_irr_lbvh_w6<false, true>), g, b, 0, st, P, Q);
+            else
+                hipLaunchKernelGGL((k_irr_lbvh<false, true>), g, b, 0, st, P, Q);
+        }
         const hipError_t le = hipGetLastError();
         const hipError_t fe = hipFreeAsync(Q.counter, st);
         if (le != hipSuccess) return fail(UVC_EDEVICE, std::string("irradiance launch: ") + hipGetErrorString(le));
@@ -1295,6 +1381,8 @@ extern "C" uvc_status uvc_batch_create(const uvc_scene* const* scenes, int32_t n
     for (int32_t r = 0; r < n_rooms; ++r) {
         IrrParams P;
         uvc_status st_ = make_params(scenes[r], poses_dev[r], K[r], pose_dim, lamp, opts, P);
+        if (st_ == UVC_OK && lamp_variant(P.lamp))
+            st_ = fail(UVC_EUNSUPPORTED, "the many-room batch takes uniform lamps only");
         if (st_ == UVC_OK && K[r] > 0 && scenes[r]->n > 0 && !E_dev[r]) st_ = fail(UVC_EINVAL, "E is NULL");
         std::vector<float> hp;
         if (st_ == UVC_OK) st_ = fetch_poses(scenes[r], poses_dev[r], K[r], pose_dim, P.lamp, st, hp);

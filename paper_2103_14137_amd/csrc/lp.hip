@@ -1348,23 +1348,144 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
     return UVC_OK;
 }
 
+__global__ void k_lp_fill(double* __restrict__ p, double v, int64_t n) {
+    const int64_t q = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
+    if (q < n) p[q] = v;
+}
+
+__global__ void k_lp_copy(double* __restrict__ dst, const double* __restrict__ src, int64_t n) {
+    const int64_t q = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
+    if (q < n) dst[q] = src[q];
+}
+
+// An LP without poses or without elements: no element is visible, so every
+// element is dropped (sigma_i = mu_min, its dual is its penalty), t = 0 and
+// the objective (which leaves dropped elements out) is 0.  The default
+// penalty 1.001 ||E||_F of an empty matrix is 0.
+static uvc_status solve_empty(int64_t K, int64_t N, const double* pen_dev, double mu, double* t_out, double* s_out,
+                              double* y_out, uvc_lp_info* info, hipStream_t st) {
+    double p0 = 0.0;
+    if (pen_dev && N > 0) {
+        UVC_HIP(hipMemcpyAsync(&p0, pen_dev, 8, hipMemcpyDeviceToHost, st));
+        UVC_HIP(hipStreamSynchronize(st));
+    }
+    if (t_out && K > 0) hipLaunchKernelGGL(k_lp_fill, dim3(nblk(K)), dim3(LP_TB), 0, st, t_out, 0.0, K);
+    if (s_out && N > 0) hipLaunchKernelGGL(k_lp_fill, dim3(nblk(N)), dim3(LP_TB), 0, st, s_out, mu, N);
+    if (y_out) {
+        if (N > 0 && pen_dev)
+            hipLaunchKernelGGL(k_lp_copy, dim3(nblk(N)), dim3(LP_TB), 0, st, y_out, pen_dev, N);
+        else if (N > 0)
+            hipLaunchKernelGGL(k_lp_fill, dim3(nblk(N)), dim3(LP_TB), 0, st, y_out, 0.0, N);
+        hipLaunchKernelGGL(k_lp_fill, dim3(1), dim3(LP_TB), 0, st, y_out + N, 0.0, (int64_t)1);
+    }
+    UVC_HIP(hipGetLastError());
+    UVC_HIP(hipStreamSynchronize(st));
+    if (info) info->penalty = p0;
+    return UVC_OK;
+}
+
+// ------------------------------------------------------------ CSR input
+// Row k of a CSR matrix with nnz entries: 0 <= row_ptr[k] <= row_ptr[k + 1]
+// <= nnz, columns strictly ascending within [0, N) (columns are read only
+// for rows whose range lies inside [0, nnz)).  *bad receives the smallest
+// offending row (left at ~0 when every row passes).
+__global__ __launch_bounds__(LP_TB) void k_csr_check(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                     int64_t K, int64_t N, int64_t nnz,
+                                                     unsigned long long* __restrict__ bad) {
+    const int64_t k = blockIdx.x;
+    const int64_t q0 = rp[k], q1 = rp[k + 1];
+    bool ok = 0 <= q0 && q0 <= q1 && q1 <= nnz;
+    if (ok) {
+        for (int64_t q = q0 + threadIdx.x; q < q1; q += LP_TB) {
+            const int32_t c = col[q];
+            if (c < 0 || (int64_t)c >= N || (q > q0 && col[q - 1] >= c)) ok = false;
+        }
+    }
+    if (!ok) atomicMin(bad, (unsigned long long)k);
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, float v, int64_t n) {
+    for (int64_t q = blockIdx.x * (int64_t)LP_TB + threadIdx.x; q < n; q += (int64_t)gridDim.x * LP_TB) p[q] = v;
+}
+
+__global__ void k_fill_u64x1(unsigned long long* p, unsigned long long v) { *p = v; }
+
+// D[k * N + col[q]] = val[q] for the entries of row k (one workgroup per row).
+__global__ __launch_bounds__(LP_TB) void k_csr_scatter(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                       const float* __restrict__ val, int64_t N,
+                                                       float* __restrict__ D) {
+    const int64_t k = blockIdx.x;
+    for (int64_t q = rp[k] + threadIdx.x; q < rp[k + 1]; q += LP_TB) D[k * N + col[q]] = val[q];
+}
+
+// The interior point method works on the K x K normal matrix, which is
+// dense whatever the sparsity of E; its product reads E as a dense pose-major
+// matrix.  A CSR input is validated and expanded once into a library-owned
+// dense copy (K N 4 bytes; released after the solve).
+static uvc_status csr_to_dense(const int64_t* rp, const int32_t* col, const float* val, int64_t K, int64_t N,
+                               hipStream_t st, float** out) {
+    *out = nullptr;
+    if (K > (int64_t)0x7fffffff) return fail(UVC_EINVAL, "K too large for a CSR input");
+    int64_t ends[2] = {0, 0};
+    UVC_HIP(hipMemcpyAsync(&ends[0], rp, 8, hipMemcpyDeviceToHost, st));
+    UVC_HIP(hipMemcpyAsync(&ends[1], rp + K, 8, hipMemcpyDeviceToHost, st));
+    UVC_HIP(hipStreamSynchronize(st));
+    if (ends[0] != 0 || ends[1] < 0) return fail(UVC_EINVAL, "CSR row_ptr must start at 0 and end at nnz >= 0");
+    if (ends[1] > 0 && !val) return fail(UVC_EINVAL, "CSR values are NULL");
+    unsigned long long* bad = nullptr;
+    UVC_TRY(dalloc_n(&bad, 1, "csr check flag"));
+    hipLaunchKernelGGL(k_fill_u64x1, dim3(1), dim3(1), 0, st, bad, ~0ull);
+    hipLaunchKernelGGL(k_csr_check, dim3((unsigned)K), dim3(LP_TB), 0, st, rp, col, K, N, ends[1], bad);
+    unsigned long long hb = 0;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&hb, bad, 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(bad);
+    if (e != hipSuccess) return fail(UVC_EDEVICE, std::string("csr check: ") + hipGetErrorString(e));
+    if (hb != ~0ull)
+        return fail(UVC_EINVAL, "CSR row " + std::to_string(hb) +
+                                    ": row_ptr decreasing, or columns outside [0, N) or not strictly ascending");
+    float* D = nullptr;
+    UVC_TRY(dalloc_n(&D, (size_t)K * (size_t)N, "dense copy of the CSR matrix"));
+    hipLaunchKernelGGL(k_fill_f32, dim3(4096), dim3(LP_TB), 0, st, D, 0.0f, K * N);
+    hipLaunchKernelGGL(k_csr_scatter, dim3((unsigned)K), dim3(LP_TB), 0, st, rp, col, val, N, D);
+    e = hipGetLastError();
+    if (e != hipSuccess) {
+        (void)hipFree(D);
+        return fail(UVC_EDEVICE, std::string("csr expand: ") + hipGetErrorString(e));
+    }
+    *out = D;
+    return UVC_OK;
+}
+
 }  // namespace uvc
 
 using namespace uvc;
 
-extern "C" uvc_status uvc_solve_dosage_lp(const float* E_dev, int64_t K, int64_t N, const double* penalty_dev,
-                                          double mu_min, double t_max, double tol, int32_t max_iter,
-                                          double* t_out_dev, double* sigma_out_dev, double* y_out_dev,
-                                          uvc_lp_info* info, void* hip_stream) {
+extern "C" uvc_status uvc_solve_dosage_lp(const float* E_dev, const int64_t* row_ptr_dev, const int32_t* col_dev,
+                                          int64_t K, int64_t N, const double* penalty_dev, double mu_min,
+                                          double t_max, double tol, int32_t max_iter, double* t_out_dev,
+                                          double* sigma_out_dev, double* y_out_dev, uvc_lp_info* info,
+                                          void* hip_stream) {
     if (info) *info = uvc_lp_info{};
     if (K < 0 || N < 0) return fail(UVC_EINVAL, "negative LP size");
     if (!(mu_min > 0) || !(t_max > 0) || !(tol > 0) || max_iter <= 0)
         return fail(UVC_EINVAL, "mu_min, t_max, tol and max_iter must be positive");
-    if (K == 0 || N == 0) return fail(UVC_EINVAL, "empty LP");
-    if (!E_dev) return fail(UVC_EINVAL, "E is NULL");
+    if (K == 0 || N == 0) return solve_empty(K, N, penalty_dev, mu_min, t_out_dev, sigma_out_dev, y_out_dev, info,
+                                             (hipStream_t)hip_stream);
+    if (!row_ptr_dev && !E_dev) return fail(UVC_EINVAL, "E is NULL");
+    if (row_ptr_dev && col_dev == nullptr) return fail(UVC_EINVAL, "CSR input needs col");
+    hipStream_t st = (hipStream_t)hip_stream;
     try {
-        return solve_ipm(E_dev, K, N, penalty_dev, mu_min, t_max, tol, max_iter, t_out_dev, sigma_out_dev, y_out_dev,
-                         info, (hipStream_t)hip_stream);
+        if (!row_ptr_dev)
+            return solve_ipm(E_dev, K, N, penalty_dev, mu_min, t_max, tol, max_iter, t_out_dev, sigma_out_dev,
+                             y_out_dev, info, st);
+        float* dense = nullptr;
+        UVC_TRY(csr_to_dense(row_ptr_dev, col_dev, E_dev, K, N, st, &dense));
+        const uvc_status r = solve_ipm(dense, K, N, penalty_dev, mu_min, t_max, tol, max_iter, t_out_dev,
+                                       sigma_out_dev, y_out_dev, info, st);
+        (void)hipFree(dense);
+        return r;
     } catch (const std::exception& e) {
         return fail(UVC_ENOMEM, std::string("host exception: ") + e.what());
     }

@@ -213,30 +213,16 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
         UVC_HIP(hipGetLastError());
         return UVC_OK;
     };
-    auto frob = [&](const float* E, int64_t n, double& out) -> uvc_status {
-        Dev part;
-        const int nb = 1024;
-        UVC_TRY(alloc<double>(part, nb, "norm partials"));
-        hipLaunchKernelGGL(k_sumsq, dim3(nb), dim3(256), 0, st, E, n, (double*)part.p);
-        UVC_HIP(hipGetLastError());
-        std::vector<double> h(nb);
-        UVC_HIP(hipMemcpyAsync(h.data(), part.p, nb * 8, hipMemcpyDeviceToHost, st));
-        UVC_HIP(hipStreamSynchronize(st));
-        double a = 0.0;
-        for (double v : h) a += v;
-        out = std::sqrt(a);
-        return UVC_OK;
-    };
 
-    auto full_plan = [&](hipEvent_t before, hipEvent_t after) -> uvc_status {
+    // p <= 0: the LP's own default over the full matrix
+    auto full_plan = [&](hipEvent_t before, hipEvent_t after, double p) -> uvc_status {
         Dev E;
         UVC_TRY(alloc<float>(E, K * N, "E (full candidate set)"));
         UVC_TRY(uvc_compute_irradiance_dense(scene, poses_dev, K, pose_dim, lamp, &o, (float*)E.p, nullptr, st));
-        // penalty <= 0: the LP's own default over the full matrix
-        if (penalty > 0.0) UVC_TRY(set_penalty(penalty));
+        if (p > 0.0) UVC_TRY(set_penalty(p));
         UVC_HIP(hipEventRecord(before, st));
         const uvc_status s =
-            uvc_solve_dosage_lp((const float*)E.p, K, N, penalty > 0.0 ? (const double*)pen.p : nullptr, mu_min,
+            uvc_solve_dosage_lp((const float*)E.p, nullptr, nullptr, K, N, p > 0.0 ? (const double*)pen.p : nullptr, mu_min,
                                 t_max, tol, max_iter, t_out_dev, sigma_out_dev, nullptr, &li, st);
         UVC_HIP(hipEventRecord(after, st));
         if (s != UVC_OK && s != UVC_ENOTCONV) return s;
@@ -251,7 +237,7 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
     };
 
     if (score_mode == UVC_RANK_NONE) {
-        UVC_TRY(full_plan(ev.e[1], ev.e[2]));
+        UVC_TRY(full_plan(ev.e[1], ev.e[2], penalty));
         UVC_HIP(hipEventSynchronize(ev.e[2]));
         info->ms_E = ms_between(ev.e[0], ev.e[1]);
         info->ms_lp = ms_between(ev.e[1], ev.e[2]);
@@ -288,7 +274,35 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
     std::sort(kept.begin(), kept.end());
     UVC_HIP(hipEventRecord(ev.e[2], st));
 
-    // 3. restricted LP, then pricing rounds
+    // 3. the LP penalty.  The default, 1.001 ||E||_F, is taken over the whole
+    // candidate set, so that the restricted LPs, the pricing and the
+    // fallback all solve the LP over all K poses with the same p.  The norm
+    // streams E through a bounded buffer, pose rows in blocks (E itself is
+    // not kept).
+    double p_lp = penalty;
+    if (!(p_lp > 0.0)) {
+        const int64_t kc = std::max<int64_t>(1, std::min<int64_t>(K, ((int64_t)1 << 26) / N));
+        Dev Eb, part;
+        const int nb = 1024;
+        UVC_TRY(alloc<float>(Eb, kc * N, "E block (penalty)"));
+        UVC_TRY(alloc<double>(part, nb, "norm partials"));
+        std::vector<double> h(nb);
+        double e2 = 0.0;
+        for (int64_t k0 = 0; k0 < K; k0 += kc) {
+            const int64_t kb = std::min(kc, K - k0);
+            UVC_TRY(uvc_compute_irradiance_dense(scene, poses_dev + k0 * pose_dim, kb, pose_dim, lamp, &o,
+                                                 (float*)Eb.p, nullptr, st));
+            hipLaunchKernelGGL(k_sumsq, dim3(nb), dim3(256), 0, st, (const float*)Eb.p, kb * N, (double*)part.p);
+            UVC_HIP(hipGetLastError());
+            UVC_HIP(hipMemcpyAsync(h.data(), part.p, nb * 8, hipMemcpyDeviceToHost, st));
+            UVC_HIP(hipStreamSynchronize(st));
+            for (double v : h) e2 += v;
+        }
+        p_lp = 1.001 * std::sqrt(e2);
+    }
+    UVC_HIP(hipEventRecord(ev.e[3], st));
+
+    // 4. restricted LP, then pricing rounds
     const int64_t add_cap = std::max<int64_t>(16, keep0);
     const double rc_tol = 1e-6;
     // rounds that add poses solve to a looser tolerance; once pricing finds
@@ -300,7 +314,6 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
     Dev tred, dkept;
     std::vector<hipEvent_t> marks;  // per round: E start, LP start, pricing start, pricing end
     bool fallback = false, optimal = false;
-    double p_lp = penalty;
     for (int round = 0; !fallback && !optimal; ++round) {
         const int64_t keep = (int64_t)kept.size();
         hipEvent_t mk[4];
@@ -323,15 +336,9 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
         UVC_HIP(hipGetLastError());
         UVC_TRY(uvc_compute_irradiance_dense(scene, (const float*)red_poses.p, keep, pose_dim, lamp, &o,
                                              (float*)Ered.p, nullptr, st));
-        if (round == 0 && !(p_lp > 0.0)) {
-            // estimate of 1.001 ||E||_F over all candidates from the kept rows
-            double f = 0.0;
-            UVC_TRY(frob((const float*)Ered.p, keep * N, f));
-            p_lp = 1.001 * f * std::sqrt((double)K / (double)keep);
-        }
         if (round == 0) UVC_TRY(set_penalty(p_lp));
         UVC_HIP(hipEventRecord(mk[1], st));
-        const uvc_status lps = uvc_solve_dosage_lp((const float*)Ered.p, keep, N, (const double*)pen.p, mu_min, t_max,
+        const uvc_status lps = uvc_solve_dosage_lp((const float*)Ered.p, nullptr, nullptr, keep, N, (const double*)pen.p, mu_min, t_max,
                                                    (final_pass || keep == K) ? tol : tol_loose, max_iter, (double*)tred.p,
                                                    sigma_out_dev, (double*)yd.p, &li, st);
         if (lps != UVC_OK && lps != UVC_ENOTCONV) return lps;
@@ -431,7 +438,10 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
     UVC_HIP(hipEventRecord(ev.e[5], st));
     if (fallback) {
         info->fell_back = 1;
-        UVC_TRY(full_plan(ev.e[6], ev.e[7]));
+        // the full candidate set with the caller's penalty (<= 0: the LP's own
+        // default over the full matrix, the same p as p_lp up to the order of
+        // the norm's sum), so that the fallback is exactly the full plan
+        UVC_TRY(full_plan(ev.e[6], ev.e[7], penalty));
     } else {
         const int64_t keep = (int64_t)kept.size();
         hipLaunchKernelGGL(k_fill_f64, dim3(grid_of(K, 256)), dim3(256), 0, st, t_out_dev, 0.0, K);
@@ -446,6 +456,7 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
     UVC_HIP(hipEventSynchronize(ev.e[7]));
     info->ms_features = ms_between(ev.e[0], ev.e[1]);
     info->ms_score = ms_between(ev.e[1], ev.e[2]);
+    info->ms_E = ms_between(ev.e[2], ev.e[3]);  // the default penalty's norm pass
     for (size_t r = 0; r + 3 < marks.size(); r += 4) {
         info->ms_E += ms_between(marks[r], marks[r + 1]);
         info->ms_lp += ms_between(marks[r + 1], marks[r + 2]);

@@ -1,7 +1,8 @@
-// Learned pose ranker: cheap per-pose visibility features, a small MLP that
-// scores poses, and the ranked plan (keep the top-scoring poses, assemble E
-// on them only, solve the dosage LP, check coverability, fall back to the
-// full candidate set when an element that some pose can see stays uncovered).
+// Learned pose ranker: cheap per-pose visibility features and a small MLP
+// that scores poses (forward, backward and Adam on the GPU).  The ranked
+// plan that uses the scores (keep the top-scoring poses, assemble E on them
+// only, solve the dosage LP, price the pruned poses with its duals) lives
+// with the column generation in the ranked-plan source.
 //
 // Features of pose k: 16 x 16 closest-hit rays from the point (x, y, z + h)
 // over an equal-area direction set (16 azimuths x 16 bands uniform in the

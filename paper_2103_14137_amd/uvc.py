@@ -35,7 +35,8 @@ class UvcError(RuntimeError):
 
 
 class LampC(ctypes.Structure):
-    _fields_ = [("n_src", _I32), ("dz", _P), ("power_w", _P)]
+    _fields_ = [("n_src", _I32), ("dz", _P), ("power_w", _P), ("n_prof", _I32), ("profile", _P),
+                ("up_mask", ctypes.c_uint32), ("down_mask", ctypes.c_uint32)]
 
 
 class LpInfoC(ctypes.Structure):
@@ -95,7 +96,7 @@ def lib():
         "uvc_batch_destroy": ([_P], None),
         "uvc_autotune": ([_P, _P, _I64, _I32, ctypes.POINTER(LampC), _I32, ctypes.c_char_p, _I32,
                           ctypes.POINTER(OptsC), _P], _I32),
-        "uvc_solve_dosage_lp": ([_P, _I64, _I64, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _I32, _P, _P,
+        "uvc_solve_dosage_lp": ([_P, _P, _P, _I64, _I64, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _I32, _P, _P,
                                  _P, ctypes.POINTER(LpInfoC), _P], _I32),
         "uvc_ranker_param_count": ([], _I64),
         "uvc_ranker_features": ([_P, _P, _I64, _I32, ctypes.c_float, _P, _P], _I32),
@@ -137,14 +138,21 @@ def _require_cuda(t: torch.Tensor, name: str, dtype) -> torch.Tensor:
 
 
 class Lamp:
-    """Point sources dz[j] metres above the pose base, power[j] watts each."""
+    """Point sources dz[j] metres above the pose base, power[j] watts each;
+    optionally an emission table over cos(theta) (profile) and hemisphere
+    masks (sources that emit only above / below their own height)."""
 
-    def __init__(self, dz, power):
+    def __init__(self, dz, power, profile=None, up_mask: int = 0, down_mask: int = 0):
         self.dz = np.ascontiguousarray(dz, np.float32).reshape(-1)
         self.power = np.ascontiguousarray(power, np.float32).reshape(-1)
         if self.dz.shape != self.power.shape:
             raise ValueError("dz and power must have the same length")
-        self._c = LampC(int(self.dz.shape[0]), self.dz.ctypes.data_as(_P), self.power.ctypes.data_as(_P))
+        self.profile = None if profile is None else np.ascontiguousarray(profile, np.float32).reshape(-1)
+        self.up_mask, self.down_mask = int(up_mask), int(down_mask)
+        np_ = 0 if self.profile is None else int(self.profile.shape[0])
+        pp = None if self.profile is None else self.profile.ctypes.data_as(_P)
+        self._c = LampC(int(self.dz.shape[0]), self.dz.ctypes.data_as(_P), self.power.ctypes.data_as(_P), np_, pp,
+                        self.up_mask, self.down_mask)
 
     @property
     def n_src(self) -> int:
@@ -307,18 +315,33 @@ def stats_dict(stats: torch.Tensor) -> dict:
 
 
 def solve_lp(E: torch.Tensor, mu_min: float = 280.0, t_max: float = 3.6e5, penalty: torch.Tensor | None = None,
-             tol: float = 1e-9, max_iter: int = 200, stream=None, allow_notconv: bool = False):
-    """Relaxed dosage LP on the dense pose-major E (K x N float32, device).
-    Returns dict(t [K] float64, sigma [N] float64, objective, residuals...)."""
+             tol: float = 1e-9, max_iter: int = 200, stream=None, allow_notconv: bool = False,
+             csr: tuple | None = None):
+    """Relaxed dosage LP on the pose-major E: dense (E is K x N float32,
+    device), or CSR when csr = (row_ptr int64 [K+1], col int32 [nnz], N) is
+    given (E then holds the nnz float32 values).  Returns dict(t [K] float64,
+    sigma [N] float64, y [N+1] float64, objective, residuals, ...)."""
     E = _require_cuda(E, "E", torch.float32)
-    K, N = E.shape
-    t = torch.empty(K, dtype=torch.float64, device=E.device)
-    sg = torch.empty(N, dtype=torch.float64, device=E.device)
-    y = torch.empty(N + 1, dtype=torch.float64, device=E.device)
+    if csr is None:
+        K, N = E.shape
+        rp_ptr = col_ptr = None
+    else:
+        rp, col, N = csr
+        rp = _require_cuda(rp, "row_ptr", torch.int64)
+        col = _require_cuda(col, "col", torch.int32)
+        K = rp.numel() - 1
+        if K < 0 or col.numel() != E.numel():
+            raise ValueError("CSR: row_ptr needs K+1 entries and col one per value")
+        rp_ptr, col_ptr = rp.data_ptr(), col.data_ptr()
+    dev = E.device
+    t = torch.empty(K, dtype=torch.float64, device=dev)
+    sg = torch.empty(N, dtype=torch.float64, device=dev)
+    y = torch.empty(N + 1, dtype=torch.float64, device=dev)
     if penalty is not None:
         penalty = _require_cuda(penalty, "penalty", torch.float64)
     info = LpInfoC()
-    st = lib().uvc_solve_dosage_lp(E.data_ptr(), K, N, penalty.data_ptr() if penalty is not None else None,
+    st = lib().uvc_solve_dosage_lp(E.data_ptr(), rp_ptr, col_ptr, K, N,
+                                   penalty.data_ptr() if penalty is not None else None,
                                    float(mu_min), float(t_max), float(tol), int(max_iter), t.data_ptr(),
                                    sg.data_ptr(), y.data_ptr(), ctypes.byref(info), _stream(stream))
     if st != 0 and not (allow_notconv and st == -4):

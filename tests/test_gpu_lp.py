@@ -93,3 +93,98 @@ def test_duals_certify_optimality(uvc, seed, K, N, t_max):
     prim, dual, gap = lp.kkt_residuals(E.astype(np.float64), cert, mu_min=280.0, t_max=t_max)
     assert prim <= 1e-6 * 280.0 and dual <= 1e-6 * (1.0 + sol["penalty"]) and gap <= 1e-7, (prim, dual, gap)
     assert np.all(y[:N][~vis] == sol["penalty"]) and y[N] >= 0
+
+
+def test_large_lp_certified_single_split(uvc):
+    """K = 4,451 poses (a batched-workload room, N = 6,604 triangles): at this
+    size the normal matrix is formed without splitting the element range
+    (one partial product per tile, written directly), which no smaller LP
+    reaches.  The GPU's t, sigma and duals pass the reference module's KKT
+    check on the FP64 copy of the same matrix, first with the 100 h budget
+    (not binding), then with half the dwell time that solution uses, where
+    the budget binds and its dual is positive."""
+    w = wl.batch_room(8)
+    print(f"batch room 8: N={w.N} K={w.K}", flush=True)
+    assert w.K >= 3000
+    sc = uvc.Scene(w.mesh.verts, w.mesh.tris)
+    E, _ = uvc.irradiance_dense(sc, torch.from_numpy(w.poses).cuda(), w.lamp)
+    E64 = E.cpu().numpy().astype(np.float64)
+    N = w.N
+    vis = E64.max(0) > 0
+    t_max = 3.6e5
+    for case in ("free", "binding"):
+        sol = uvc.solve_lp(E, mu_min=280.0, t_max=t_max, tol=1e-9, max_iter=300)
+        assert sol["converged"]
+        y = sol["y"].cpu().numpy()
+        cert = {"t": sol["t"].cpu().numpy(), "sigma": sol["sigma"].cpu().numpy(), "visible": vis,
+                "penalty": np.full(N, sol["penalty"]), "duals": np.concatenate([y[:N][vis], y[N:]])}
+        prim, dual, gap = lp.kkt_residuals(E64, cert, mu_min=280.0, t_max=t_max)
+        print(case, t_max, sol["iterations"], prim, dual, gap, flush=True)
+        assert prim <= 1e-6 * 280.0 and dual <= 1e-6 * (1.0 + sol["penalty"]) and gap <= 1e-7, (prim, dual, gap)
+        assert sol["penalty"] == pytest.approx(lp.default_penalty(E64), rel=1e-12)
+        if case == "binding":
+            assert cert["t"].sum() == pytest.approx(t_max, rel=1e-6) and y[N] > 0
+        t_max = 0.5 * float(cert["t"].sum())
+    sc.close()
+
+
+def test_empty_lp_succeeds(uvc):
+    """K = 0 or N = 0: success with empty output (t = 0, sigma = mu_min,
+    duals = penalties, budget dual 0, objective 0)."""
+    E = torch.zeros((0, 5), dtype=torch.float32, device="cuda")
+    sol = uvc.solve_lp(E)
+    assert sol["converged"] and sol["n_visible"] == 0 and sol["objective"] == 0.0
+    assert torch.all(sol["sigma"] == 280.0) and torch.all(sol["y"] == 0.0)
+    pen = torch.full((5,), 7.0, dtype=torch.float64, device="cuda")
+    sol = uvc.solve_lp(E, penalty=pen)
+    assert torch.all(sol["y"][:5] == 7.0) and float(sol["y"][5]) == 0.0
+    sol = uvc.solve_lp(torch.zeros((4, 0), dtype=torch.float32, device="cuda"))
+    assert sol["converged"] and torch.all(sol["t"] == 0.0) and sol["y"].numel() == 1 and float(sol["y"][0]) == 0.0
+
+
+def _to_csr(E):
+    K, N = E.shape
+    nz = E != 0
+    rp = np.concatenate([[0], np.cumsum(nz.sum(1))]).astype(np.int64)
+    kk, ii = np.nonzero(nz)
+    return rp, ii.astype(np.int32), E[kk, ii].astype(np.float32)
+
+
+@pytest.mark.parametrize("seed,K,N,t_max", [(0, 40, 300, 3.6e5), (2, 60, 400, 500.0), (3, 150, 900, 3.6e5)])
+def test_csr_input_matches_highs_and_dense(uvc, seed, K, N, t_max):
+    """The same LP given as CSR (rows = poses, ascending columns): the
+    objective matches HiGHS within 1e-6 at tol 1e-8, and the solution is the
+    dense input's bit for bit (the CSR is expanded to the same dense matrix)."""
+    E = _random_instance(seed, K, N)
+    E[3] = 0.0  # an empty row
+    rp, col, val = _to_csr(E)
+    ref_sol = lp.solve(E.astype(np.float64), mu_min=280.0, t_max=t_max)
+    sc = uvc.solve_lp(torch.from_numpy(val).cuda(), t_max=t_max, tol=1e-8,
+                      csr=(torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda(), N))
+    sd = uvc.solve_lp(torch.from_numpy(E).cuda(), t_max=t_max, tol=1e-8)
+    assert sc["converged"]
+    assert lp.relative_objective_gap(sc["objective"], ref_sol["objective"]) <= 1e-6
+    assert torch.equal(sc["t"], sd["t"]) and torch.equal(sc["y"], sd["y"]) and sc["objective"] == sd["objective"]
+
+
+def test_csr_input_validation(uvc):
+    E = _random_instance(4, 20, 50)
+    rp, col, val = _to_csr(E)
+    dev = lambda a: torch.from_numpy(a).cuda()  # noqa: E731
+    bad = col.copy()
+    r = 5
+    bad[rp[r]], bad[rp[r] + 1] = bad[rp[r] + 1], bad[rp[r]]  # not ascending in row 5
+    with pytest.raises(uvc.UvcError, match="CSR row 5"):
+        uvc.solve_lp(dev(val), csr=(dev(rp), dev(bad), 50))
+    bad = col.copy()
+    bad[rp[7]] = 50  # outside [0, N)
+    with pytest.raises(uvc.UvcError, match="CSR row 7"):
+        uvc.solve_lp(dev(val), csr=(dev(rp), dev(bad), 50))
+    brp = rp.copy()
+    brp[9] = brp[10] + 1  # decreasing offsets
+    with pytest.raises(uvc.UvcError, match="CSR row"):
+        uvc.solve_lp(dev(val), csr=(dev(brp), dev(col), 50))
+    brp = rp.copy()
+    brp[0] = 1
+    with pytest.raises(uvc.UvcError, match="start at 0"):
+        uvc.solve_lp(dev(val), csr=(dev(brp), dev(col), 50))

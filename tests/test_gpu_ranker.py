@@ -213,9 +213,42 @@ def test_plan_pruned_reaches_full_optimum(plan_room):
             assert torch.all(t[torch.from_numpy(pruned).cuda()] == 0)
         ev = uvc.plan_evaluate(E, t, penalty=p)
         assert abs(ev["objective"] - ref["objective"]) <= 1e-6 * ref["objective"]
-    # the default penalty estimate still gives a valid plan
+    # the default penalty is the full LP's: 1.001 ||E||_F over all candidates
     r = uvc.plan_ranked(sc, poses, w.lamp, mode="area", keep_frac=0.1)
-    assert r["penalty"] > 0 and torch.all(r["t"] >= 0)
+    assert r["fell_back"] == 0 and torch.all(r["t"] >= 0)
+    assert abs(r["penalty"] - p) <= 1e-12 * p
+    full_def = uvc.plan_ranked(sc, poses, w.lamp, mode="none")
+    assert abs(r["objective"] - full_def["objective"]) <= 1e-6 * full_def["objective"]
+
+
+def test_ranked_plan_matches_highs():
+    """An MLP-ranked plan with the committed weights and the default penalty
+    on a held-out room (N = 2,553 triangles, K = 408 poses) against SciPy's
+    HiGHS on the full-candidate LP over the same matrix (the GPU's E in
+    FP64): the objectives agree within 1e-6 relative, and the plan is
+    feasible for HiGHS's LP (time budget, nonnegative dwell times)."""
+    import os
+    from oracle import lp as LP
+    path = os.path.join(os.path.dirname(RK.__file__), "weights", "ranker_tower8.bin")
+    params = RK.load_checkpoint(path)["params"]
+    w = RK.room(900005)
+    print(f"room 900005: N={w.N} K={w.K}", flush=True)
+    sc = uvc.Scene(w.mesh.verts, w.mesh.tris)
+    poses = torch.from_numpy(w.poses).cuda()
+    E, _ = uvc.irradiance_dense(sc, poses, w.lamp)
+    torch.cuda.synchronize()
+    E64 = E.cpu().numpy().astype(np.float64)
+    ref = LP.solve(E64, mu_min=280.0, t_max=3.6e5)
+    r = uvc.plan_ranked(sc, poses, w.lamp, mode="mlp", params=_cuda(params), keep_frac=0.1, tol=1e-9)
+    print({k: r[k] for k in ("n_kept", "n_added", "rounds", "fell_back", "penalty", "objective")},
+          "highs", ref["objective"], flush=True)
+    assert abs(r["penalty"] - LP.default_penalty(E64)) <= 1e-12 * r["penalty"]
+    assert LP.relative_objective_gap(r["objective"], ref["objective"]) <= 1e-6
+    t = r["t"].cpu().numpy()
+    assert t.min() >= 0 and t.sum() <= 3.6e5 * (1 + 1e-9)
+    ev = uvc.plan_evaluate(E, r["t"], penalty=r["penalty"])
+    assert LP.relative_objective_gap(ev["objective"], ref["objective"]) <= 1e-6
+    sc.close()
 
 
 def test_plan_evaluate_matches_numpy():

@@ -208,6 +208,27 @@ uvc_status uvc_compute_irradiance_dense(const uvc_scene* scene,
                                         const uvc_opts* opts, float* E_dev,
                                         uint32_t* vis_dev, void* hip_stream);
 
+/* The dense call for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, same validation and the same bits in E_dev and vis_dev as
+ * uvc_compute_irradiance_dense, but no hipMalloc, hipFree or other
+ * allocation.  Its scratch (8 work counters, the pose check word and the
+ * pose visiting order) lives in a file-scope device array of 4 MiB + 256 B
+ * that each GPU holds until the process ends; poses are checked on the
+ * device and visited in the caller's order.  Limits: K <= 1,048,576 poses
+ * (UVC_EINVAL beyond), and opts->kernel_ms must be NULL (timing needs HIP
+ * events; UVC_EINVAL otherwise).  Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams or host threads) race
+ * and must be serialised by the caller.  Synchronises hip_stream once
+ * (pose check) before the launch. */
+uvc_status uvc_compute_irradiance_dense_noalloc(const uvc_scene* scene,
+                                                const float* poses_dev,
+                                                int64_t K, int32_t pose_dim,
+                                                const uvc_lamp* lamp,
+                                                const uvc_opts* opts,
+                                                float* E_dev, uint32_t* vis_dev,
+                                                void* hip_stream);
+
 /* Irradiance of a subset of the elements: targets_dev holds n_targets input
  * element indices (device int32); E_dev (K x n_targets FP32, device) gets
  * column j = element targets_dev[j], bit-identical to that column of the

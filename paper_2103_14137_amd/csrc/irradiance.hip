@@ -26,6 +26,7 @@
 #include <cfloat>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 namespace uvc {
@@ -1050,7 +1051,10 @@ static int choose_path(const uvc_scene* s, const uvc_opts* opts) {
 }
 
 // Launch the irradiance kernel for P.K poses into P.E / P.vis.
-static uvc_status launch_irr_impl(const IrrParams& P0, int path, hipStream_t st) {
+// counter_ext: NULL (a stream-ordered allocation holds the persistent
+// loop's 8 work counters for this launch) or 8 caller-provided counters.
+static uvc_status launch_irr_impl(const IrrParams& P0, int path, hipStream_t st,
+                                  unsigned long long* counter_ext = nullptr) {
     if (P0.K == 0 || P0.N == 0) return UVC_OK;
     IrrParams P = P0;
     const int64_t per = (path == UVC_PATH_BRUTE) ? 64 : ((int64_t)1 << (6 - P.tk_log2));
@@ -1082,7 +1086,10 @@ static uvc_status launch_irr_impl(const IrrParams& P0, int path, hipStream_t st)
         const uint64_t grid = std::min<uint64_t>(blocks, (uint64_t)std::max(1, cus) * (uint64_t)waves);
         PersistArgs Q{nullptr, {}};
         for (int x = 0; x <= 8; ++x) Q.range_off[x] = (int64_t)(blocks * (uint64_t)x / 8u);
-        UVC_HIP(hipMallocAsync(reinterpret_cast<void**>(&Q.counter), 8 * sizeof(unsigned long long), st));
+        if (counter_ext)
+            Q.counter = counter_ext;
+        else
+            UVC_HIP(hipMallocAsync(reinterpret_cast<void**>(&Q.counter), 8 * sizeof(unsigned long long), st));
         hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, Q.counter, 0ull, 8);
         const dim3 g((unsigned)grid), b(256);
         if (!lamp_variant(P.lamp)) {
@@ -1105,7 +1112,7 @@ static uvc_status launch_irr_impl(const IrrParams& P0, int path, hipStream_t st)
                 hipLaunchKernelGGL((k_irr_lbvh<false, true>), g, b, 0, st, P, Q);
         }
         const hipError_t le = hipGetLastError();
-        const hipError_t fe = hipFreeAsync(Q.counter, st);
+        const hipError_t fe = counter_ext ? hipSuccess : hipFreeAsync(Q.counter, st);
         if (le != hipSuccess) return fail(UVC_EDEVICE, std::string("irradiance launch: ") + hipGetErrorString(le));
         if (fe != hipSuccess) return fail(UVC_EDEVICE, std::string("counter release: ") + hipGetErrorString(fe));
         return UVC_OK;
@@ -1115,14 +1122,15 @@ static uvc_status launch_irr_impl(const IrrParams& P0, int path, hipStream_t st)
 }
 
 // Launch with optional HIP-event timing of the kernel on the caller's stream.
-static uvc_status launch_irr(const IrrParams& P, int path, hipStream_t st, float* kernel_ms) {
-    if (!kernel_ms) return launch_irr_impl(P, path, st);
+static uvc_status launch_irr(const IrrParams& P, int path, hipStream_t st, float* kernel_ms,
+                             unsigned long long* counter_ext = nullptr) {
+    if (!kernel_ms) return launch_irr_impl(P, path, st, counter_ext);
     hipEvent_t e0, e1;
     UVC_HIP(hipEventCreate(&e0));
     UVC_HIP(hipEventCreate(&e1));
     uvc_status r = UVC_OK;
     hipError_t he = hipEventRecord(e0, st);
-    if (he == hipSuccess) r = launch_irr_impl(P, path, st);
+    if (he == hipSuccess) r = launch_irr_impl(P, path, st, counter_ext);
     if (he == hipSuccess && r == UVC_OK) he = hipEventRecord(e1, st);
     if (he == hipSuccess && r == UVC_OK) he = hipEventSynchronize(e1);
     float ms = 0.f;
@@ -1187,6 +1195,119 @@ extern "C" uvc_status uvc_compute_irradiance_dense(const uvc_scene* scene, const
     const uvc_status r = launch_irr(P, path, st, opts ? opts->kernel_ms : nullptr);
     if (dorder) (void)hipFreeAsync(dorder, st);
     return r;
+}
+
+// ------------------------------------------------ dense, without allocation
+// The dense call allocates two small stream-ordered buffers per call (the
+// persistent loop's work counters and the pose visiting order).  For callers
+// that cannot allocate, the variant below takes both from one file-scope
+// device array instead.  Each device holds its own copy of the array at its
+// own address, looked up once per device with hipGetSymbolAddress; host code
+// uses only that address.  Layout: 8 work counters at byte 0, the pose
+// check word at byte 64, the pose order (int32) from byte 256.
+namespace uvc {
+constexpr int64_t NOALLOC_MAX_POSES = (int64_t)1 << 20;
+constexpr size_t SCR_CHECK = 64, SCR_ORDER = 256;
+constexpr size_t SCRATCH_BYTES = SCR_ORDER + (size_t)NOALLOC_MAX_POSES * 4;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+// Device address of the current device's scratch array (looked up on the
+// first call on each device, with that device current).
+static uvc_status scratch_address(void** out) {
+    int dev = 0;
+    UVC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return fail(UVC_EUNSUPPORTED, "device ordinal out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(UVC_EDEVICE, std::string("scratch address: ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return UVC_OK;
+}
+
+// The host-side pose check of the dense call, on the device: *bad receives
+// the smallest (k << 1) | c over the offending poses, c = 0 for a
+// non-finite coordinate, 1 for a source point farther than lim from the
+// origin (left at ~0 when every pose passes).
+__global__ void k_check_poses(const float* __restrict__ poses, int64_t K, int pd, float dzmin, float dzmax, float lim,
+                              unsigned long long* __restrict__ bad) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    const float x = poses[k * pd], y = poses[k * pd + 1], z = (pd == 3) ? poses[k * pd + 2] : 0.0f;
+    unsigned long long code = ~0ull;
+    if (!isfinite(x) || !isfinite(y) || !isfinite(z)) {
+        code = (unsigned long long)k << 1;
+    } else {
+        const float z0 = z + dzmin, z1 = z + dzmax;
+        if (fabsf(x) > lim || fabsf(y) > lim || fabsf(z0) > lim || fabsf(z1) > lim)
+            code = ((unsigned long long)k << 1) | 1ull;
+    }
+    if (code != ~0ull) atomicMin(bad, code);
+}
+
+__global__ void k_iota_i32(int32_t* __restrict__ p, int64_t n) {
+    const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (q < n) p[q] = (int32_t)q;
+}
+}  // namespace uvc
+
+extern "C" uvc_status uvc_compute_irradiance_dense_noalloc(const uvc_scene* scene, const float* poses_dev, int64_t K,
+                                                           int32_t pose_dim, const uvc_lamp* lamp,
+                                                           const uvc_opts* opts, float* E_dev, uint32_t* vis_dev,
+                                                           void* hip_stream) {
+    IrrParams P;
+    UVC_TRY(make_params(scene, poses_dev, K, pose_dim, lamp, opts, P));
+    if (opts && opts->kernel_ms)
+        return fail(UVC_EINVAL, "kernel_ms is not available without allocation (timing creates HIP events)");
+    if (K > NOALLOC_MAX_POSES)
+        return fail(UVC_EINVAL, "K = " + std::to_string(K) + " exceeds the no-allocation limit of " +
+                                    std::to_string(NOALLOC_MAX_POSES) + " poses");
+    if (K == 0 || scene->n == 0) return UVC_OK;
+    if (!E_dev) return fail(UVC_EINVAL, "E is NULL");
+    hipStream_t st = (hipStream_t)hip_stream;
+    void* base = nullptr;
+    UVC_TRY(scratch_address(&base));
+    unsigned long long* counters = reinterpret_cast<unsigned long long*>(base);
+    unsigned long long* checkw = reinterpret_cast<unsigned long long*>((char*)base + SCR_CHECK);
+    int32_t* order = reinterpret_cast<int32_t*>((char*)base + SCR_ORDER);
+    float dzmin = P.lamp.dz[0], dzmax = P.lamp.dz[0];
+    for (int j = 1; j < P.lamp.S; ++j) {
+        dzmin = std::min(dzmin, P.lamp.dz[j]);
+        dzmax = std::max(dzmax, P.lamp.dz[j]);
+    }
+    const float lim = 2.0f * std::max(scene->max_abs, 1e-30f);
+    const unsigned gk = (unsigned)((K + 255) / 256);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, checkw, ~0ull, 1);
+    hipLaunchKernelGGL(k_check_poses, dim3(gk), dim3(256), 0, st, poses_dev, K, pose_dim, dzmin, dzmax, lim, checkw);
+    UVC_HIP(hipGetLastError());
+    unsigned long long bad = 0;
+    UVC_HIP(hipMemcpyAsync(&bad, checkw, 8, hipMemcpyDeviceToHost, st));
+    UVC_HIP(hipStreamSynchronize(st));
+    if (bad != ~0ull) {
+        const std::string k = std::to_string(bad >> 1);
+        if ((bad & 1ull) == 0) return fail(UVC_EINVAL, "pose " + k + ": a pose coordinate is not finite");
+        return fail(UVC_EINVAL, "pose " + k + ": a source point lies farther than 2 * max_abs_coord from the origin");
+    }
+    const int path = choose_path(scene, opts);
+    if (path == UVC_PATH_LBVH) {
+        // poses are visited in the caller's order (the dense call sorts them
+        // into a compact 2D order first); every entry is computed on its own,
+        // so the order changes no bit of the result
+        hipLaunchKernelGGL(k_iota_i32, dim3(gk), dim3(256), 0, st, order, K);
+        UVC_HIP(hipGetLastError());
+        P.pose_order = order;
+    }
+    P.E = E_dev;
+    P.vis = vis_dev;
+    return launch_irr(P, path, st, nullptr, counters);
 }
 
 static void free_job(uvc_csr_job* j) {

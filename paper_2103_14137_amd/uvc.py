@@ -83,6 +83,8 @@ def lib():
         "uvc_destroy_scene": ([_P], None),
         "uvc_compute_irradiance_dense": ([_P, _P, _I64, _I32, ctypes.POINTER(LampC), ctypes.POINTER(OptsC), _P, _P,
                                           _P], _I32),
+        "uvc_compute_irradiance_dense_noalloc": ([_P, _P, _I64, _I32, ctypes.POINTER(LampC), ctypes.POINTER(OptsC),
+                                                  _P, _P, _P], _I32),
         "uvc_compute_irradiance_targets": ([_P, _P, _I64, _I32, ctypes.POINTER(LampC), ctypes.POINTER(OptsC), _P,
                                             _I64, _P, _P, _P], _I32),
         "uvc_compute_irradiance_csr_begin": ([_P, _P, _I64, _I32, ctypes.POINTER(LampC), ctypes.POINTER(OptsC), _P,
@@ -263,6 +265,30 @@ def irradiance_dense(scene: Scene, poses: torch.Tensor, lamp, path="auto", band_
     check(lib().uvc_compute_irradiance_dense(scene.handle, poses.data_ptr(), K, pd, ctypes.byref(lamp._c),
                                              ctypes.byref(opts), out.data_ptr(),
                                              vis.data_ptr() if vis is not None else None, _stream(stream)))
+    return out, vis
+
+
+def irradiance_dense_noalloc(scene: Scene, poses: torch.Tensor, lamp, out: torch.Tensor,
+                             vis: torch.Tensor | None = None, path="auto", band_scale: float = 1.0,
+                             stats: torch.Tensor | None = None, stream=None, packet_poses: int = 0, flags: int = 0,
+                             waves: int = 0, tile_tris: int = 0):
+    """The dense matrix into caller-provided out (K x N float32) and
+    optional vis (K x N int32) through the entry point that allocates no
+    device memory (its scratch is a fixed device array; K <= 2^20)."""
+    poses = _require_cuda(poses, "poses", torch.float32)
+    K, pd = poses.shape
+    lamp = as_lamp(lamp)
+    out = _require_cuda(out, "out", torch.float32)
+    if out.numel() != K * scene.n:
+        raise ValueError("out must hold K*N floats")
+    if vis is not None:
+        vis = _require_cuda(vis, "vis", torch.int32)
+        if vis.numel() != K * scene.n:
+            raise ValueError("vis must hold K*N ints")
+    opts = make_opts(path, band_scale, tile_tris, stats, None, packet_poses, flags, waves)
+    check(lib().uvc_compute_irradiance_dense_noalloc(scene.handle, poses.data_ptr(), K, pd, ctypes.byref(lamp._c),
+                                                     ctypes.byref(opts), out.data_ptr(),
+                                                     vis.data_ptr() if vis is not None else None, _stream(stream)))
     return out, vis
 
 

@@ -49,6 +49,9 @@ def lib():
         L.oracle_irradiance_pairs_lamp.argtypes = [_P, _P, _I64, _P, _I64, _I32, _I32, _P, _P, _I32, _P,
                                                    ctypes.c_uint32, ctypes.c_uint32, _P, _P, _I64, _P, _P, _I32]
         L.oracle_irradiance_pairs_lamp.restype = ctypes.c_int
+        L.oracle_area_irradiance.argtypes = [_P, _P, _I64, _P, _I64, _I32, _I32, _P, _P, _I32, _P,
+                                             ctypes.c_uint32, ctypes.c_uint32, _I32, _P, _P, _P, _I32]
+        L.oracle_area_irradiance.restype = ctypes.c_int
         L.oracle_max_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -184,3 +187,39 @@ def entry_tolerance(verts, tris, poses, dz, power, vis, pk=None, pi=None, profil
         on = ((vis >> j) & 1).astype(bool)
         tol += np.where(on, float(pw) * W / (4.0 * np.pi * r2), 0.0)
     return 1e-5 * tol
+
+
+def area_irradiance(verts, tris, poses, dz, power, face_res: int, profile=None, up_mask: int = 0,
+                    down_mask: int = 0, threads: int = 0):
+    """Area-integrated irradiance by the visibility-cube procedure (closest
+    hit per cube-map pixel, pixel power to the hit triangle, collected power
+    over triangle area): E (K x N FP64), the near-tie pixel counts (K x N
+    int32) and the power collected per pose (K)."""
+    v = _c(verts, np.float32)
+    t = _c(tris, np.int32)
+    p = _c(poses, np.float32)
+    K, pdim = p.shape
+    N = t.shape[0]
+    dzf = _c(dz, np.float32)
+    pw = _c(power, np.float32)
+    prof = _c(profile if profile is not None else np.zeros(0), np.float32)
+    E = np.empty((K, N), np.float64)
+    amb = np.empty((K, N), np.int32)
+    landed = np.empty(K, np.float64)
+    rc = lib().oracle_area_irradiance(_ptr(v), _ptr(t), N, _ptr(p), K, pdim, dzf.shape[0], _ptr(dzf), _ptr(pw),
+                                      prof.shape[0], _ptr(prof) if prof.size else None, int(up_mask),
+                                      int(down_mask), int(face_res), _ptr(E), _ptr(amb), _ptr(landed), int(threads))
+    if rc != 0:
+        raise ValueError("oracle_area_irradiance: invalid arguments")
+    return E, amb, landed
+
+
+def cube_pixel_power_max(power, face_res: int, profile=None) -> float:
+    """An upper bound on the power one cube-map pixel carries for these
+    sources: pixels shrink away from a face's centre, and none subtends more
+    than the square [-1/R, 1/R]^2 at unit distance, 4 atan(h^2 / sqrt(1 +
+    2 h^2)) with h = 1/R."""
+    h = 1.0 / face_res
+    dom = 4.0 * np.arctan(h * h / np.sqrt(1.0 + 2.0 * h * h))
+    wmax = 1.0 if profile is None else float(np.max(np.asarray(profile, np.float64)))
+    return float(np.max(np.asarray(power, np.float64))) * wmax * dom / (4.0 * np.pi)

@@ -212,4 +212,149 @@ int oracle_irradiance_pairs(const float* verts, const int32_t* tris, int64_t n,
                                         npairs, E_out, vis_out, nthreads);
 }
 
+/* ---------------------------------------------------------------------------
+ * Area-integrated irradiance (Sec. IV-C, the visibility-cube procedure).
+ * Each source emits through the pixels of a cube around it: face f (axis
+ * ax = f / 2, sign +1 for even f, -1 for odd f) holds R x R pixels over
+ * (u, v) in [-1, 1]^2; pixel (a, b) spans u in [-1 + 2a/R, -1 + 2(a+1)/R]
+ * (likewise v with b) and its centre direction has component ax = sign,
+ * component (ax+1) mod 3 = u_c and component (ax+2) mod 3 = v_c.  Its
+ * solid angle is the exact solid angle of that square on the plane at unit
+ * distance, dOmega = F(u1,v1) - F(u0,v1) - F(u1,v0) + F(u0,v0) with
+ * F(x, y) = atan2(x y, sqrt(1 + x^2 + y^2)).  The pixel carries the power
+ * e = P_j w_j(cos theta) dOmega / (4 pi) (w_j: the emission table at the
+ * centre direction, 1 for uniform emission; a hemisphere mask drops pixels
+ * whose centre direction points into the masked half: d_z <= 0 for an
+ * upward-only source, d_z >= 0 for a downward-only one).  The ray through
+ * the pixel centre meets its closest triangle (smallest plane parameter
+ * t > 0 among the closed triangles it passes through; equal t: the lower
+ * index); that triangle collects e if the ray reaches its front side
+ * (D . m < 0, m its normal; a back side keeps nothing).  The entry is the
+ * collected power over the triangle's area, F_i / |s_i|.
+ * amb_out counts, per (pose, triangle), pixels whose decision is close to
+ * a tie: the ray passes within a relative 1e-6 of the edge of a triangle
+ * at least as close as the winner (or of the winner), two hits lie within a
+ * relative 1e-6 in t, or the winner is met within 1e-6 of edge-on; such a
+ * pixel counts for the winner and for every such near triangle.
+ * power_out[k] = the power collected over all triangles for pose k. */
+static double omega_corner(double x, double y) { return atan2(x * y, sqrt(1.0 + x * x + y * y)); }
+
+int oracle_area_irradiance(const float* verts, const int32_t* tris, int64_t n,
+                           const float* poses, int64_t K, int32_t pose_dim,
+                           int32_t S, const float* dz, const float* power,
+                           int32_t n_prof, const float* prof, uint32_t up_mask, uint32_t down_mask,
+                           int32_t R, double* E_out, int32_t* amb_out, double* power_out, int32_t nthreads)
+{
+    if (S < 1 || S > 32 || (pose_dim != 2 && pose_dim != 3) || R < 1) return -1;
+    if (n_prof == 1 || n_prof > 33 || (n_prof > 1 && !prof) || (up_mask & down_mask)) return -1;
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    const double four_pi = 4.0 * M_PI;
+    const double rel = 1e-6;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < K; ++k) {
+        double* F = E_out + k * n;
+        int32_t* amb = amb_out + k * n;
+        for (int64_t m = 0; m < n; ++m) { F[m] = 0.0; amb[m] = 0; }
+        const float* pp = poses + pose_dim * k;
+        float zb = (pose_dim == 3) ? pp[2] : 0.0f;
+        double landed = 0.0;
+        for (int j = 0; j < S; ++j) {
+            float pz = zb + dz[j]; /* FP32 sum */
+            float pf[3] = {pp[0], pp[1], pz};
+            d3 O = ld(pf);
+            for (int f = 0; f < 6; ++f) {
+                int ax = f / 2;
+                double sgn = (f % 2 == 0) ? 1.0 : -1.0;
+                for (int a = 0; a < R; ++a) {
+                    double u0 = -1.0 + 2.0 * a / R, u1 = -1.0 + 2.0 * (a + 1) / R, uc = 0.5 * (u0 + u1);
+                    for (int b = 0; b < R; ++b) {
+                        double v0 = -1.0 + 2.0 * b / R, v1 = -1.0 + 2.0 * (b + 1) / R, vc = 0.5 * (v0 + v1);
+                        double dir[3];
+                        dir[ax] = sgn;
+                        dir[(ax + 1) % 3] = uc;
+                        dir[(ax + 2) % 3] = vc;
+                        d3 D = {dir[0], dir[1], dir[2]};
+                        if (((up_mask >> j) & 1u) && !(D.z > 0.0)) continue;
+                        if (((down_mask >> j) & 1u) && !(D.z < 0.0)) continue;
+                        double dom = omega_corner(u1, v1) - omega_corner(u0, v1) - omega_corner(u1, v0)
+                                     + omega_corner(u0, v0);
+                        double dl = sqrt(dot(D, D));
+                        double w = emission_weight(D.z / dl, n_prof, prof);
+                        double e = (double)power[j] * w * dom / four_pi;
+                        /* closest hit by brute force */
+                        int64_t best = -1;
+                        double tbest = INFINITY, dmbest = 0.0, grbest = 1.0;
+                        for (int64_t m = 0; m < n; ++m) {
+                            d3 A = ld(verts + 3 * (int64_t)tris[3 * m + 0]);
+                            d3 B = ld(verts + 3 * (int64_t)tris[3 * m + 1]);
+                            d3 C = ld(verts + 3 * (int64_t)tris[3 * m + 2]);
+                            d3 mm = cross(sub(B, A), sub(C, A));
+                            double dm = dot(D, mm);
+                            if (dm == 0.0) continue;
+                            double t = dot(sub(A, O), mm) / dm;
+                            if (!(t > 0.0)) continue;
+                            d3 a3 = sub(A, O), b3 = sub(B, O), c3 = sub(C, O);
+                            double U = dot(D, cross(b3, c3)), V = dot(D, cross(c3, a3)), W = dot(D, cross(a3, b3));
+                            int neg = (U < 0.0) || (V < 0.0) || (W < 0.0);
+                            int pos = (U > 0.0) || (V > 0.0) || (W > 0.0);
+                            if (neg && pos) continue;
+                            if (t < tbest || (t == tbest && m < best)) {
+                                tbest = t;
+                                best = m;
+                                dmbest = dm / (dl * sqrt(dot(mm, mm)));
+                                double sa = sqrt(dot(a3, a3)), sb = sqrt(dot(b3, b3)), sc = sqrt(dot(c3, c3));
+                                double g = fmin(fmin(fabs(U) / (dl * sb * sc), fabs(V) / (dl * sc * sa)),
+                                                fabs(W) / (dl * sa * sb));
+                                grbest = g;
+                            }
+                        }
+                        if (best < 0) continue;
+                        int ambiguous = grbest <= rel || fabs(dmbest) <= rel;
+                        /* near triangles: close in t, or grazed at a distance not beyond the winner */
+                        for (int64_t m = 0; m < n; ++m) {
+                            if (m == best) continue;
+                            d3 A = ld(verts + 3 * (int64_t)tris[3 * m + 0]);
+                            d3 B = ld(verts + 3 * (int64_t)tris[3 * m + 1]);
+                            d3 C = ld(verts + 3 * (int64_t)tris[3 * m + 2]);
+                            d3 mm = cross(sub(B, A), sub(C, A));
+                            double dm = dot(D, mm);
+                            if (dm == 0.0) continue;
+                            double t = dot(sub(A, O), mm) / dm;
+                            if (!(t > 0.0) || t > tbest * (1.0 + rel)) continue;
+                            d3 a3 = sub(A, O), b3 = sub(B, O), c3 = sub(C, O);
+                            double U = dot(D, cross(b3, c3)), V = dot(D, cross(c3, a3)), W = dot(D, cross(a3, b3));
+                            double sa = sqrt(dot(a3, a3)), sb = sqrt(dot(b3, b3)), sc = sqrt(dot(c3, c3));
+                            double u = U / (dl * sb * sc), v = V / (dl * sc * sa), ww = W / (dl * sa * sb);
+                            int inside = !(((u < 0) || (v < 0) || (ww < 0)) && ((u > 0) || (v > 0) || (ww > 0)));
+                            /* outside: how far is the ray from entering (the most negative orientation with
+                               the others of the majority sign); inside: a tie in t with the winner */
+                            double mn = fmin(fmin(u, v), ww), mx = fmax(fmax(u, v), ww);
+                            double miss = (mx > 0.0) ? -mn : mx;   /* distance-like to the boundary */
+                            int near = inside ? (t >= tbest * (1.0 - rel)) : (fabs(miss) <= rel);
+                            if (near) {
+                                amb[m] += 1;
+                                ambiguous = 1;
+                            }
+                        }
+                        if (ambiguous) amb[best] += 1;
+                        if (dmbest < 0.0) {
+                            F[best] += e;
+                            landed += e;
+                        }
+                    }
+                }
+            }
+        }
+        for (int64_t m = 0; m < n; ++m) {
+            d3 A = ld(verts + 3 * (int64_t)tris[3 * m + 0]);
+            d3 B = ld(verts + 3 * (int64_t)tris[3 * m + 1]);
+            d3 C = ld(verts + 3 * (int64_t)tris[3 * m + 2]);
+            d3 mm = cross(sub(B, A), sub(C, A));
+            F[m] = F[m] / (0.5 * sqrt(dot(mm, mm)));
+        }
+        if (power_out) power_out[k] = landed;
+    }
+    return 0;
+}
+
 int oracle_max_threads(void) { return omp_get_max_threads(); }

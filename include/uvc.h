@@ -229,6 +229,34 @@ uvc_status uvc_compute_irradiance_dense_noalloc(const uvc_scene* scene,
                                                 float* E_dev, uint32_t* vis_dev,
                                                 void* hip_stream);
 
+/* Area-integrated irradiance (Sec. IV-C, the visibility-cube procedure): the
+ * paper's own entry, the power a triangle receives over its area, with
+ * partial occlusion.  Each source emits through a cube of face_res x
+ * face_res pixels per face (0: 512, the paper's resolution; at most 1024):
+ * face f has axis f / 2 and outward sign + for even f, pixel (a, b) spans
+ * u in [-1 + 2a/R, -1 + 2(a+1)/R] along axis (f/2 + 1) mod 3 and v likewise
+ * along (f/2 + 2) mod 3, carries the power P_j w_j dOmega / (4 pi) (dOmega
+ * the pixel's exact solid angle, w_j the lamp's emission weight at the
+ * pixel centre direction; hemisphere masks drop pixels whose centre
+ * direction points into the masked half) and sends it along the ray
+ * through its centre to the closest triangle, which collects it if the ray
+ * reaches its front side.  E_dev[k * N + i] (K x N FP32, caller-owned,
+ * input element order) = collected power / triangle area (W/m^2);
+ * power_dev: NULL or K FP64 values, the power collected per pose.
+ * Closest hits are decided in FP32, with a ray within ~1e-6 (relative) of
+ * a triangle edge counted as inside so that no ray slips between triangles
+ * that share an edge (such pixels, and rays meeting two triangles at nearly
+ * the same distance, may go to a neighbour of the FP64 choice); collection
+ * is in 2^-40 W fixed point
+ * with integer atomics, so results do not depend on scheduling.  Requires
+ * total lamp power <= 2^22 W.  Non-finite poses return UVC_EINVAL (poses
+ * are copied to the host for the check).  Synchronises hip_stream. */
+uvc_status uvc_compute_irradiance_area(const uvc_scene* scene,
+                                       const float* poses_dev, int64_t K,
+                                       int32_t pose_dim, const uvc_lamp* lamp,
+                                       int32_t face_res, float* E_dev,
+                                       double* power_dev, void* hip_stream);
+
 /* Irradiance of a subset of the elements: targets_dev holds n_targets input
  * element indices (device int32); E_dev (K x n_targets FP32, device) gets
  * column j = element targets_dev[j], bit-identical to that column of the

@@ -232,10 +232,12 @@ int oracle_irradiance_pairs(const float* verts, const int32_t* tris, int64_t n,
  * (D . m < 0, m its normal; a back side keeps nothing).  The entry is the
  * collected power over the triangle's area, F_i / |s_i|.
  * amb_out counts, per (pose, triangle), pixels whose decision is close to
- * a tie: the ray passes within a relative 1e-6 of the edge of a triangle
+ * a tie: the ray passes within a relative 1e-5 of the edge of a triangle
  * at least as close as the winner (or of the winner), two hits lie within a
- * relative 1e-6 in t, or the winner is met within 1e-6 of edge-on; such a
- * pixel counts for the winner and for every such near triangle.
+ * relative 1e-5 in t, or the winner is met within 1e-5 of edge-on; such a
+ * pixel counts for the winner and for every such near triangle.  (Edge
+ * closeness of a ray: the smallest |orientation| D . (p x q) over
+ * |D| |p| |q| for the triangle's vertices p, q relative to the origin.)
  * power_out[k] = the power collected over all triangles for pose k. */
 static double omega_corner(double x, double y) { return atan2(x * y, sqrt(1.0 + x * x + y * y)); }
 
@@ -249,7 +251,7 @@ int oracle_area_irradiance(const float* verts, const int32_t* tris, int64_t n,
     if (n_prof == 1 || n_prof > 33 || (n_prof > 1 && !prof) || (up_mask & down_mask)) return -1;
     if (nthreads > 0) omp_set_num_threads(nthreads);
     const double four_pi = 4.0 * M_PI;
-    const double rel = 1e-6;
+    const double rel = 1e-5;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t k = 0; k < K; ++k) {
         double* F = E_out + k * n;
@@ -326,10 +328,10 @@ int oracle_area_irradiance(const float* verts, const int32_t* tris, int64_t n,
                             double sa = sqrt(dot(a3, a3)), sb = sqrt(dot(b3, b3)), sc = sqrt(dot(c3, c3));
                             double u = U / (dl * sb * sc), v = V / (dl * sc * sa), ww = W / (dl * sa * sb);
                             int inside = !(((u < 0) || (v < 0) || (ww < 0)) && ((u > 0) || (v > 0) || (ww > 0)));
-                            /* outside: how far is the ray from entering (the most negative orientation with
-                               the others of the majority sign); inside: a tie in t with the winner */
+                            /* outside (mixed signs): how far the ray is from making all three orientations
+                               one sign, either way; inside: a tie in t with the winner */
                             double mn = fmin(fmin(u, v), ww), mx = fmax(fmax(u, v), ww);
-                            double miss = (mx > 0.0) ? -mn : mx;   /* distance-like to the boundary */
+                            double miss = fmin(-mn, mx);
                             int near = inside ? (t >= tbest * (1.0 - rel)) : (fabs(miss) <= rel);
                             if (near) {
                                 amb[m] += 1;

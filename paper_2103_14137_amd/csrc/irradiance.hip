@@ -33,16 +33,6 @@ namespace uvc {
 
 constexpr float INV_4PI = 0.0795774715459476678844f;  // 1 / (4 pi)
 
-struct LampArgs {
-    int32_t S;
-    float dz[32];
-    float pw[32];  // P_j / (4 pi)
-    // emission pattern (read by the lamp-variant kernels only)
-    int32_t nprof;     // 0: uniform; else the table's node count (2..33)
-    float ph;          // (nprof - 1) / 2
-    float prof[33];
-    uint32_t up, down; // hemisphere masks
-};
 
 struct IrrParams {
     const float* tri;
@@ -210,29 +200,13 @@ __device__ __forceinline__ float entry_term(float dx, float dy, float dz, float 
 
 // The same term times the source's emission weight: the lamp's table
 // interpolated at cos(theta) = -dz / |d| (d = source - element, so -dz is
-// the element's height above the source).  Table entries are uniform; the
-// two bracketing entries are picked with a select chain, not an indexed
-// load.
+// the element's height above the source).
 __device__ __forceinline__ float entry_term_weighted(float dx, float dy, float dz, float s, float pw,
                                                      const LampArgs& L) {
 #pragma clang fp contract(off)
     const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
     const float ri = __builtin_amdgcn_rsqf(r2);
-    float wgt = 1.0f;
-    if (L.nprof > 0) {
-        const int last = L.nprof - 1;
-        const float ct = -dz * ri;
-        const float u = fminf(fmaxf((ct + 1.0f) * L.ph, 0.0f), (float)last);
-        const int q = min((int)u, last - 1);
-        const float f = u - (float)q;
-        float a = L.prof[0], b = L.prof[1];
-        for (int qq = 1; qq < last; ++qq) {
-            const bool here = q == qq;
-            a = here ? L.prof[qq] : a;
-            b = here ? L.prof[qq + 1] : b;
-        }
-        wgt = a + f * (b - a);
-    }
+    const float wgt = (L.nprof > 0) ? table_weight(L, -dz * ri) : 1.0f;
     const float w = ((pw * fmaxf(s, 0.0f)) * ((ri * ri) * ri)) * wgt;
     return fmaxf(w, FLT_MIN);
 }
@@ -907,6 +881,45 @@ __global__ void k_row_gather(const float* __restrict__ E, int64_t rows, int64_t 
 }
 
 // ------------------------------------------------------------------ host
+// Validated device copy of a lamp (shared by every kernel that emits from
+// lamp sources).
+uvc_status lamp_args(const uvc_lamp* lamp, LampArgs& L) {
+    if (!lamp || lamp->n_src < 1 || lamp->n_src > 32 || !lamp->dz || !lamp->power_w)
+        return fail(UVC_EINVAL, "lamp must have 1..32 sources with dz and power arrays");
+    std::memset(&L, 0, sizeof(L));
+    L.S = lamp->n_src;
+    for (int j = 0; j < lamp->n_src; ++j) {
+        if (!std::isfinite(lamp->dz[j])) return fail(UVC_EINVAL, "lamp dz[" + std::to_string(j) + "] is not finite");
+        if (!(lamp->power_w[j] > 0.f) || !std::isfinite(lamp->power_w[j]))
+            return fail(UVC_EINVAL, "lamp power[" + std::to_string(j) + "] must be positive and finite");
+        L.dz[j] = lamp->dz[j];
+        L.pw[j] = (float)((double)lamp->power_w[j] / (4.0 * M_PI));
+    }
+    if (lamp->n_prof != 0) {
+        if (lamp->n_prof < 2 || lamp->n_prof > 33 || !lamp->profile)
+            return fail(UVC_EINVAL, "lamp emission table must have 2..33 entries");
+        bool any = false;
+        for (int q = 0; q < lamp->n_prof; ++q) {
+            const float v = lamp->profile[q];
+            if (!std::isfinite(v) || v < 0.f)
+                return fail(UVC_EINVAL, "lamp emission table entry " + std::to_string(q) + " must be finite and >= 0");
+            any = any || v > 0.f;
+            L.prof[q] = v;
+        }
+        if (!any) return fail(UVC_EINVAL, "lamp emission table is all zero");
+        L.nprof = lamp->n_prof;
+        L.ph = 0.5f * (float)(lamp->n_prof - 1);
+    }
+    const uint32_t srcmask = lamp->n_src == 32 ? 0xffffffffu : ((1u << lamp->n_src) - 1u);
+    if ((lamp->up_mask | lamp->down_mask) & ~srcmask)
+        return fail(UVC_EINVAL, "lamp hemisphere masks name sources beyond n_src");
+    if (lamp->up_mask & lamp->down_mask)
+        return fail(UVC_EINVAL, "a source cannot emit only upwards and only downwards");
+    L.up = lamp->up_mask;
+    L.down = lamp->down_mask;
+    return UVC_OK;
+}
+
 static bool lamp_variant(const LampArgs& L) { return L.nprof > 0 || L.up != 0u || L.down != 0u; }
 
 static uvc_status make_params(const uvc_scene* s, const float* poses, int64_t K, int32_t pd, const uvc_lamp* lamp,
@@ -918,36 +931,7 @@ static uvc_status make_params(const uvc_scene* s, const float* poses, int64_t K,
         return fail(UVC_EINVAL, "lamp must have 1..32 sources with dz and power arrays");
     if (K > 0 && s->n > 0 && !poses) return fail(UVC_EINVAL, "poses is NULL");
     std::memset(&P, 0, sizeof(P));
-    P.lamp.S = lamp->n_src;
-    for (int j = 0; j < lamp->n_src; ++j) {
-        if (!std::isfinite(lamp->dz[j])) return fail(UVC_EINVAL, "lamp dz[" + std::to_string(j) + "] is not finite");
-        if (!(lamp->power_w[j] > 0.f) || !std::isfinite(lamp->power_w[j]))
-            return fail(UVC_EINVAL, "lamp power[" + std::to_string(j) + "] must be positive and finite");
-        P.lamp.dz[j] = lamp->dz[j];
-        P.lamp.pw[j] = (float)((double)lamp->power_w[j] / (4.0 * M_PI));
-    }
-    if (lamp->n_prof != 0) {
-        if (lamp->n_prof < 2 || lamp->n_prof > 33 || !lamp->profile)
-            return fail(UVC_EINVAL, "lamp emission table must have 2..33 entries");
-        bool any = false;
-        for (int q = 0; q < lamp->n_prof; ++q) {
-            const float v = lamp->profile[q];
-            if (!std::isfinite(v) || v < 0.f)
-                return fail(UVC_EINVAL, "lamp emission table entry " + std::to_string(q) + " must be finite and >= 0");
-            any = any || v > 0.f;
-            P.lamp.prof[q] = v;
-        }
-        if (!any) return fail(UVC_EINVAL, "lamp emission table is all zero");
-        P.lamp.nprof = lamp->n_prof;
-        P.lamp.ph = 0.5f * (float)(lamp->n_prof - 1);
-    }
-    const uint32_t srcmask = lamp->n_src == 32 ? 0xffffffffu : ((1u << lamp->n_src) - 1u);
-    if ((lamp->up_mask | lamp->down_mask) & ~srcmask)
-        return fail(UVC_EINVAL, "lamp hemisphere masks name sources beyond n_src");
-    if (lamp->up_mask & lamp->down_mask)
-        return fail(UVC_EINVAL, "a source cannot emit only upwards and only downwards");
-    P.lamp.up = lamp->up_mask;
-    P.lamp.down = lamp->down_mask;
+    UVC_TRY(lamp_args(lamp, P.lamp));
     const float bs = opts ? opts->band_scale : 1.0f;
     if (!(bs >= 0.f)) return fail(UVC_EINVAL, "band_scale must be >= 0");
     P.tau_f = TAU_F * bs;

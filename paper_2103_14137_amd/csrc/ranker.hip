@@ -15,6 +15,7 @@
 // W1[128][64], b1[128], W2[128][128], b2[128], W3[128], b3 (24,961 floats);
 // binary cross-entropy on the logit; Adam.
 #include "uvc_common.hpp"
+#include "closest_hit.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -29,53 +30,7 @@ constexpr int H1 = 128, H2 = 128;
 constexpr int64_t OFF_W1 = 0, OFF_B1 = OFF_W1 + H1 * FEAT, OFF_W2 = OFF_B1 + H1, OFF_B2 = OFF_W2 + H2 * H1,
                   OFF_W3 = OFF_B2 + H2, OFF_B3 = OFF_W3 + H2, N_PARAMS = OFF_B3 + 1;
 
-__device__ __forceinline__ float max3r(float a, float b, float c) { return fmaxf(fmaxf(a, b), c); }
-__device__ __forceinline__ float min3r(float a, float b, float c) { return fminf(fminf(a, b), c); }
-
 // ------------------------------------------------------------- features
-struct CRay {
-    float ox, oy, oz, dx, dy, dz, ix, iy, iz, nx, ny, nz;
-    float tbest;
-    int best;
-};
-
-__device__ __forceinline__ bool cslab(const CRay& r, float lx, float ly, float lz, float hx, float hy, float hz) {
-    const float t0x = fmaf(lx, r.ix, r.nx), t1x = fmaf(hx, r.ix, r.nx);
-    const float t0y = fmaf(ly, r.iy, r.ny), t1y = fmaf(hy, r.iy, r.ny);
-    const float t0z = fmaf(lz, r.iz, r.nz), t1z = fmaf(hz, r.iz, r.nz);
-    const float tn = fmaxf(max3r(fminf(t0x, t1x), fminf(t0y, t1y), fminf(t0z, t1z)), 0.0f);
-    const float tf = fminf(min3r(fmaxf(t0x, t1x), fmaxf(t0y, t1y), fmaxf(t0z, t1z)), r.tbest);
-    return tn <= tf;
-}
-
-// Closest hit of the ray with one triangle record (FP32; features need no
-// exact decisions).  Updates tbest / best.
-__device__ __forceinline__ void ctri(CRay& r, const float* __restrict__ t, int slot) {
-    const float v0x = t[0], v0y = t[1], v0z = t[2];
-    const float e01x = t[TRI_E01], e01y = t[TRI_E01 + 1], e01z = t[TRI_E01 + 2];
-    const float e12x = t[TRI_E12], e12y = t[TRI_E12 + 1], e12z = t[TRI_E12 + 2];
-    const float e20x = t[TRI_E20], e20y = t[TRI_E20 + 1], e20z = t[TRI_E20 + 2];
-    const float ax = v0x - r.ox, ay = v0y - r.oy, az = v0z - r.oz;
-    const float bx = t[3] - r.ox, by = t[4] - r.oy, bz = t[5] - r.oz;
-    const float cx = t[6] - r.ox, cy = t[7] - r.oy, cz = t[8] - r.oz;
-    const float U = r.dx * fmaf(by, e12z, -bz * e12y) + r.dy * fmaf(bz, e12x, -bx * e12z) + r.dz * fmaf(bx, e12y, -by * e12x);
-    const float V = r.dx * fmaf(cy, e20z, -cz * e20y) + r.dy * fmaf(cz, e20x, -cx * e20z) + r.dz * fmaf(cx, e20y, -cy * e20x);
-    const float W = r.dx * fmaf(ay, e01z, -az * e01y) + r.dy * fmaf(az, e01x, -ax * e01z) + r.dz * fmaf(ax, e01y, -ay * e01x);
-    const bool in = (U >= 0.f && V >= 0.f && W >= 0.f) || (U <= 0.f && V <= 0.f && W <= 0.f);
-    const float det = U + V + W;
-    if (!in || det == 0.f) return;
-    // plane crossing: t = ((v0 - O) . m) / (D . m), m = e01 x (v2 - v0) = e20 x e01
-    const float mx = fmaf(e20y, e01z, -e20z * e01y), my = fmaf(e20z, e01x, -e20x * e01z),
-                mz = fmaf(e20x, e01y, -e20y * e01x);
-    const float den = r.dx * mx + r.dy * my + r.dz * mz;
-    if (den == 0.f) return;
-    const float tt = (ax * mx + ay * my + az * mz) / den;
-    if (tt > 0.f && tt < r.tbest) {
-        r.tbest = tt;
-        r.best = slot;
-    }
-}
-
 __global__ __launch_bounds__(256) void k_rank_features(const float* __restrict__ tri, const float* __restrict__ elem,
                                                        const float* __restrict__ nodes, int64_t N,
                                                        const float* __restrict__ poses, int64_t K, int pd, float h,
@@ -99,50 +54,7 @@ __global__ __launch_bounds__(256) void k_rank_features(const float* __restrict__
     r.nx = -ox * r.ix; r.ny = -oy * r.iy; r.nz = -oz * r.iz;
     r.tbest = 1.0f;
     r.best = -1;
-    if (N == 1) {
-        ctri(r, tri, 0);
-    } else if (N > 1) {
-        // packet walk: every lane keeps its own closest hit; no early exit
-        unsigned long long m = ~0ull;
-        int node = 0, sp = 0, sn = 0, slo = 0, shi = 0;
-        while (true) {
-            const float4* q = reinterpret_cast<const float4*>(nodes + (int64_t)node * NODE_WORDS);
-            const float4 q0 = q[0], q1 = q[1], q2 = q[2], q3 = q[3];
-            unsigned long long mL = __ballot(cslab(r, q0.x, q0.y, q0.z, q0.w, q1.x, q1.y)) & m;
-            unsigned long long mR = __ballot(cslab(r, q1.z, q1.w, q2.x, q2.y, q2.z, q2.w)) & m;
-            const int cl = __float_as_int(q3.x), cr = __float_as_int(q3.y);
-            if (cl < 0 && mL) {
-                if ((mL >> lane) & 1ull) ctri(r, tri + (int64_t)(~cl) * TRI_WORDS, ~cl);
-                mL = 0;
-            }
-            if (cr < 0 && mR) {
-                if ((mR >> lane) & 1ull) ctri(r, tri + (int64_t)(~cr) * TRI_WORDS, ~cr);
-                mR = 0;
-            }
-            if (mL && mR) {
-                const bool here = lane == sp;
-                sn = here ? cr : sn;
-                slo = here ? (int)(unsigned)mR : slo;
-                shi = here ? (int)(unsigned)(mR >> 32) : shi;
-                ++sp;
-                node = cl;
-                m = mL;
-            } else if (mL) {
-                node = cl;
-                m = mL;
-            } else if (mR) {
-                node = cr;
-                m = mR;
-            } else {
-                if (sp == 0) break;
-                --sp;
-                node = __builtin_amdgcn_readlane(sn, sp);
-                const unsigned lo = (unsigned)__builtin_amdgcn_readlane(slo, sp);
-                const unsigned hi = (unsigned)__builtin_amdgcn_readlane(shi, sp);
-                m = ((unsigned long long)hi << 32) | lo;
-            }
-        }
-    }
+    closest_hit_walk<false>(r, tri, nodes, N, lane);
     int bin = -1;
     float wgt = 0.f;
     if (r.best >= 0) {

@@ -83,6 +83,40 @@ constexpr float TAU_P = 1.0f / 8192.0f;     // 2^-13
 // Box padding relative to the scene's largest |coordinate|.
 constexpr float PAD_REL = 1.0f / 262144.0f; // 2^-18
 
+// A lamp as the kernels read it (a kernel argument).
+struct LampArgs {
+    int32_t S;
+    float dz[32];
+    float pw[32];      // P_j / (4 pi)
+    // emission pattern (read by the lamp-variant kernels only)
+    int32_t nprof;     // 0: uniform; else the table's node count (2..33)
+    float ph;          // (nprof - 1) / 2
+    float prof[33];
+    uint32_t up, down; // hemisphere masks
+};
+
+// Validates a lamp of the C ABI and fills its kernel form.
+uvc_status lamp_args(const uvc_lamp* lamp, LampArgs& L);
+
+// Emission weight of the lamp's table (L.nprof >= 2) at cos(theta): linear
+// interpolation between equally spaced nodes over [-1, 1].  The table is
+// uniform across the wave; the two bracketing entries are picked with a
+// select chain, not an indexed load.
+__device__ __forceinline__ float table_weight(const LampArgs& L, float ct) {
+#pragma clang fp contract(off)
+    const int last = L.nprof - 1;
+    const float u = fminf(fmaxf((ct + 1.0f) * L.ph, 0.0f), (float)last);
+    const int q = min((int)u, last - 1);
+    const float f = u - (float)q;
+    float a = L.prof[0], b = L.prof[1];
+    for (int qq = 1; qq < last; ++qq) {
+        const bool here = q == qq;
+        a = here ? L.prof[qq] : a;
+        b = here ? L.prof[qq + 1] : b;
+    }
+    return a + f * (b - a);
+}
+
 }  // namespace uvc
 
 struct uvc_scene {

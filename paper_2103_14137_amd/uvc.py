@@ -85,6 +85,7 @@ def lib():
                                           _P], _I32),
         "uvc_compute_irradiance_dense_noalloc": ([_P, _P, _I64, _I32, ctypes.POINTER(LampC), ctypes.POINTER(OptsC),
                                                   _P, _P, _P], _I32),
+        "uvc_compute_irradiance_area": ([_P, _P, _I64, _I32, ctypes.POINTER(LampC), _I32, _P, _P, _P], _I32),
         "uvc_compute_irradiance_targets": ([_P, _P, _I64, _I32, ctypes.POINTER(LampC), ctypes.POINTER(OptsC), _P,
                                             _I64, _P, _P, _P], _I32),
         "uvc_compute_irradiance_csr_begin": ([_P, _P, _I64, _I32, ctypes.POINTER(LampC), ctypes.POINTER(OptsC), _P,
@@ -290,6 +291,20 @@ def irradiance_dense_noalloc(scene: Scene, poses: torch.Tensor, lamp, out: torch
                                                      ctypes.byref(opts), out.data_ptr(),
                                                      vis.data_ptr() if vis is not None else None, _stream(stream)))
     return out, vis
+
+
+def irradiance_area(scene: Scene, poses: torch.Tensor, lamp, face_res: int = 0, stream=None):
+    """Area-integrated irradiance by the visibility-cube procedure (see
+    uvc_compute_irradiance_area): E (K x N float32) and the power collected
+    per pose (K float64)."""
+    poses = _require_cuda(poses, "poses", torch.float32)
+    K, pd = poses.shape
+    lamp = as_lamp(lamp)
+    E = torch.empty((K, scene.n), dtype=torch.float32, device=poses.device)
+    pw = torch.empty(K, dtype=torch.float64, device=poses.device)
+    check(lib().uvc_compute_irradiance_area(scene.handle, poses.data_ptr(), K, pd, ctypes.byref(lamp._c),
+                                            int(face_res), E.data_ptr(), pw.data_ptr(), _stream(stream)))
+    return E, pw
 
 
 def irradiance_targets(scene: Scene, poses: torch.Tensor, lamp, targets: torch.Tensor, path="auto",

@@ -67,6 +67,8 @@ class Workload:
     poses: np.ndarray  # float32 [K, 2] lamp base positions
     lamp: Lamp
     meta: dict = field(default_factory=dict)
+    free_fn: object = None   # (X, Y) -> bool array: where the lamp base may stand
+    bounds: tuple = None     # ((x0, x1), (y0, y1)) of the pose region
 
     @property
     def K(self) -> int:
@@ -300,6 +302,26 @@ def free_grid(free_fn, bounds, h):
     return np.stack([X[comp], Y[comp]], -1)
 
 
+def occupancy(w: "Workload", cell: float = 0.05):
+    """Free-space grid for the route stage: cells of side `cell` over the
+    pose region grown by one cell; a cell is free when its centre lies
+    within one half-diagonal of free space (free_fn with the clearance
+    reduced by cell / sqrt(2)), so that every pose's cell is free.  Returns
+    (free uint8 [H, W] with row = y index, column = x index, x0, y0): cell
+    (r, c) covers [x0 + c cell, x0 + (c + 1) cell) x [y0 + r cell, ...)."""
+    if w.free_fn is None:
+        raise ValueError(f"{w.name}: no free-space description")
+    (bx0, bx1), (by0, by1) = w.bounds
+    x0, y0 = bx0 - cell, by0 - cell
+    W = int(math.ceil((bx1 + cell - x0) / cell))
+    H = int(math.ceil((by1 + cell - y0) / cell))
+    cx = x0 + cell * (np.arange(W) + 0.5)
+    cy = y0 + cell * (np.arange(H) + 0.5)
+    X, Y = np.meshgrid(cx, cy, indexing="xy")
+    free = w.free_fn(X, Y, slack=cell / math.sqrt(2.0))
+    return free.astype(np.uint8), np.float32(x0), np.float32(y0)
+
+
 def pose_grid(free_fn, bounds, K, rng, h0=0.25, shrink=0.8):
     """K poses: the free grid at spacing h0, refined geometrically until its
     largest component holds at least K points, then a seeded subsample of K
@@ -351,12 +373,13 @@ def box_room(seed: int = 0, cell: float = 0.4, K: int = 200) -> Workload:
     mb.add(*box_surface((x0, y0, 0.0), (x0 + s, y0 + s, s), (1, 1, 1), inward=False))
     fp = [Footprint(x0 + 0.5 * s, y0 + 0.5 * s, s, s, 0.0)]
 
-    def free_fn(X, Y):
-        return _dist_to_footprints(X, Y, fp) > 0.10
+    def free_fn(X, Y, slack=0.0):
+        return _dist_to_footprints(X, Y, fp) > 0.10 - slack
 
-    poses, h = pose_grid(free_fn, ((0.25, 3.75), (0.25, 3.75)), K, rng, h0=0.25)
+    bounds = ((0.25, 3.75), (0.25, 3.75))
+    poses, h = pose_grid(free_fn, bounds, K, rng, h0=0.25)
     return Workload("box_room", mb.mesh(), poses, point_lamp(),
-                    dict(seed=seed, cube_lo=(x0, y0, 0.0), cube_size=s, room=L, pose_spacing=h))
+                    dict(seed=seed, cube_lo=(x0, y0, 0.0), cube_size=s, room=L, pose_spacing=h), free_fn, bounds)
 
 
 def _room_with_cuboids(rng, L, beds, n_cuboids, cell, clearance, K, h0=0.25):
@@ -379,12 +402,16 @@ def _room_with_cuboids(rng, L, beds, n_cuboids, cell, clearance, K, h0=0.25):
     for fp, ht in zip(fps, heights):
         mb.add(*_cuboid_mesh(fp, ht, cell))
 
-    def free_fn(X, Y):
-        return _dist_to_footprints(X, Y, fps) > clearance
+    def free_fn(X, Y, slack=0.0):
+        free = _dist_to_footprints(X, Y, fps) > clearance - slack
+        if slack > 0.0:  # the route grid also covers the margin along the walls
+            free &= ((X > clearance - slack) & (X < L[0] - clearance + slack) & (Y > clearance - slack)
+                     & (Y < L[1] - clearance + slack))
+        return free
 
     bounds = ((clearance, L[0] - clearance), (clearance, L[1] - clearance))
     poses, h = pose_grid(free_fn, bounds, K, rng, h0=h0)
-    return mb.mesh(), poses, fps, heights, h
+    return mb.mesh(), poses, fps, heights, h, free_fn, bounds
 
 
 # Tower base 55 cm across plus a 5 cm dilation: clearance from walls and
@@ -398,9 +425,9 @@ def ward(seed: int = 1, cell: float = 0.1, K: int = 5000) -> Workload:
     of 8 x 20 W sources at 0.2 ... 1.6 m."""
     rng = np.random.default_rng(seed)
     L = (8.0, 6.0, 3.0)
-    mesh, poses, fps, heights, h = _room_with_cuboids(rng, L, 6, 10, cell, TOWER_CLEARANCE, K)
+    mesh, poses, fps, heights, h, free_fn, bounds = _room_with_cuboids(rng, L, 6, 10, cell, TOWER_CLEARANCE, K)
     return Workload("ward", mesh, poses, tower_lamp(),
-                    dict(seed=seed, room=L, cell=cell, pose_spacing=h, n_obstacles=len(fps)))
+                    dict(seed=seed, room=L, cell=cell, pose_spacing=h, n_obstacles=len(fps)), free_fn, bounds)
 
 
 def _room_tri_count(L, dims_list, h):
@@ -438,13 +465,19 @@ def batch_room(seed: int, n_range=(2000, 80000), k_range=(500, 8000)) -> Workloa
         fps.append(fp)
         mb.add(*_cuboid_mesh(fp, dd[2], cell))
 
-    def free_fn(X, Y):
-        return _dist_to_footprints(X, Y, fps) > TOWER_CLEARANCE
+    c = TOWER_CLEARANCE
 
-    bounds = ((TOWER_CLEARANCE, L[0] - TOWER_CLEARANCE), (TOWER_CLEARANCE, L[1] - TOWER_CLEARANCE))
+    def free_fn(X, Y, slack=0.0):
+        free = _dist_to_footprints(X, Y, fps) > c - slack
+        if slack > 0.0:  # the route grid also covers the margin along the walls
+            free &= (X > c - slack) & (X < L[0] - c + slack) & (Y > c - slack) & (Y < L[1] - c + slack)
+        return free
+
+    bounds = ((c, L[0] - c), (c, L[1] - c))
     poses, h = pose_grid(free_fn, bounds, K, rng, h0=0.25)
     return Workload(f"batch_room_{seed}", mb.mesh(), poses, tower_lamp(),
-                    dict(seed=seed, room=L, cell=cell, pose_spacing=h, n_target=n_target, n_obstacles=n_cub))
+                    dict(seed=seed, room=L, cell=cell, pose_spacing=h, n_target=n_target, n_obstacles=n_cub),
+                    free_fn, bounds)
 
 
 def batch(seed: int = 3, n_rooms: int = 64, **kw) -> list:
@@ -578,24 +611,25 @@ def floorplan(seed: int = 2, target_tris: int = 500_000, K: int = 20000) -> Work
     c = TOWER_CLEARANCE
     all_fp = [fp for lst in furn.values() for fp, _ in lst]
 
-    def free_fn(X, Y):
+    def free_fn(X, Y, slack=0.0):
+        cc = c - slack
         inside = np.zeros(X.shape, bool)
         for (x0, x1, y0, y1) in rooms.values():
-            inside |= (X > x0 + c) & (X < x1 - c) & (Y > y0 + c) & (Y < y1 - c)
+            inside |= (X > x0 + cc) & (X < x1 - cc) & (Y > y0 + cc) & (Y < y1 - cc)
         for (a, b, dax, cen) in doors:
             if dax == 0:
                 xa, xb = rooms[a][1], rooms[b][0]
-                inside |= (X > xa - c - 1e-9) & (X < xb + c + 1e-9) & (Y > cen - DW / 2 + c) & (Y < cen + DW / 2 - c)
+                inside |= (X > xa - c - 1e-9) & (X < xb + c + 1e-9) & (Y > cen - DW / 2 + cc) & (Y < cen + DW / 2 - cc)
             else:
                 ya, yb = rooms[a][3], rooms[b][2]
-                inside |= (Y > ya - c - 1e-9) & (Y < yb + c + 1e-9) & (X > cen - DW / 2 + c) & (X < cen + DW / 2 - c)
-        return inside & (_dist_to_footprints(X, Y, all_fp) > c)
+                inside |= (Y > ya - c - 1e-9) & (Y < yb + c + 1e-9) & (X > cen - DW / 2 + cc) & (X < cen + DW / 2 - cc)
+        return inside & (_dist_to_footprints(X, Y, all_fp) > cc)
 
     ext = ((0.0, float(X0[-1] + widths[-1])), (0.0, float(Y0[-1] + depths[-1])))
     poses, h = pose_grid(free_fn, ext, K, rng, h0=0.25)
     return Workload("floorplan", mesh, poses, tower_lamp(),
                     dict(seed=seed, cell=cell, pose_spacing=h, n_doors=len(doors), n_obstacles=len(all_fp),
-                         extent=ext))
+                         extent=ext), free_fn, ext)
 
 
 CONFIGS = {

@@ -514,6 +514,61 @@ uvc_status uvc_plan_evaluate(const float* E_dev, int64_t K, int64_t N,
                              double* shortfall, int64_t* n_short,
                              int64_t* n_visible, void* hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Route stage (Sec. IV-D second stage; roadmap distances Sec. IV-B): a
+ * closed tour over the poses the LP gives a dwell time.
+ * ------------------------------------------------------------------------ */
+
+/* Free space is an H x W grid of cells of side `cell` (free_dev: H * W
+ * uint8, row-major, row = y index, nonzero = free; cell (r, c) covers
+ * [x0 + c cell, x0 + (c + 1) cell) x [y0 + r cell, y0 + (r + 1) cell)).  A
+ * stop lies in cell (floor((y - y0) / cell), floor((x - x0) / cell)),
+ * evaluated in FP64.  Paths step between 8-connected free cells at cost
+ * cell (orthogonal) or cell * sqrt(2) (diagonal, allowed only when both
+ * orthogonal neighbours are free); the distance between two stops is the
+ * smallest FP64 sum of a path's steps between their cells, symmetrised as
+ * min(d(a, b), d(b, a)) (the paper uses roadmap distances; a grid stands in
+ * for the roadmap).
+ * uvc_route_geodesics: the m x m matrix dist_dev (FP64, device) for the m
+ * stops stops_dev (m x 2 FP32, device; m <= 4096, H W m <= 2^31).
+ * UVC_EINVAL if a stop lies outside the grid or in a blocked cell, or if
+ * two stops are not connected.  Synchronises hip_stream. */
+uvc_status uvc_route_geodesics(const uint8_t* free_dev, int32_t H, int32_t W,
+                               float x0, float y0, float cell,
+                               const float* stops_dev, int32_t m,
+                               double* dist_dev, void* hip_stream);
+
+/* Closed tour over m stops (m <= 4096) with the distance matrix dist_dev
+ * (m x m FP64, device, symmetric): nearest neighbour from stop 0 (ties: the
+ * lowest index), then best-improvement 2-opt (move (i, j), 0 <= i <= m-3,
+ * i+2 <= j <= m-1, not (0, m-1): reverse stops i+1 .. j; index i m + j) and,
+ * when no 2-opt move improves, best-improvement Or-opt (move (s, i, p):
+ * stops i .. i+s-1, 1 <= s <= 3, 1 <= i <= m-s, reinserted in the same
+ * orientation after the stop at position p outside [i-1, i+s-1]; index
+ * ((s-1) m + i) m + p); the best move has the smallest FP64 delta, ties
+ * the lowest index; stop when no move improves by more than 1e-12 of the
+ * tour length or after max_moves moves (<= 0: 100 m).  The paper uses LKH;
+ * this is a local search.  Outputs: tour_host (m int32, stop 0 first), the
+ * tour length (FP64 sum in tour order) and the number of moves.
+ * Synchronises hip_stream. */
+uvc_status uvc_route_tour(const double* dist_dev, int32_t m, int32_t max_moves,
+                          int32_t* tour_host, double* length, int32_t* moves,
+                          void* hip_stream);
+
+/* The plan after the LP: the stops are the poses with
+ * t_k > rel_threshold * sum t (t_dev: K FP64, device; poses_dev K x
+ * pose_dim FP32, device), ascending; their geodesics and tour as above.
+ * Outputs: stops_host (K int32 capacity; the first *m_out entries are the
+ * pose indices in tour order), the tour length (m) and the plan time
+ * sum_k t_k + length / v_max (s).  Synchronises hip_stream. */
+uvc_status uvc_plan_route(const float* poses_dev, int64_t K, int32_t pose_dim,
+                          const double* t_dev, double rel_threshold,
+                          const uint8_t* free_dev, int32_t H, int32_t W,
+                          float x0, float y0, float cell, double v_max,
+                          int32_t* stops_host, int32_t* m_out,
+                          double* length, double* plan_time,
+                          void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -101,6 +101,12 @@ def lib():
                           ctypes.POINTER(OptsC), _P], _I32),
         "uvc_solve_dosage_lp": ([_P, _P, _P, _I64, _I64, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _I32, _P, _P,
                                  _P, ctypes.POINTER(LpInfoC), _P], _I32),
+        "uvc_route_geodesics": ([_P, _I32, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P, _I32, _P, _P],
+                                _I32),
+        "uvc_route_tour": ([_P, _I32, _I32, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I32), _P], _I32),
+        "uvc_plan_route": ([_P, _I64, _I32, _P, ctypes.c_double, _P, _I32, _I32, ctypes.c_float, ctypes.c_float,
+                            ctypes.c_float, ctypes.c_double, _P, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_double),
+                            ctypes.POINTER(ctypes.c_double), _P], _I32),
         "uvc_ranker_param_count": ([], _I64),
         "uvc_ranker_features": ([_P, _P, _I64, _I32, ctypes.c_float, _P, _P], _I32),
         "uvc_ranker_forward": ([_P, _P, _I64, _I32, _P, _P], _I32),
@@ -561,3 +567,44 @@ def plan_evaluate(E: torch.Tensor, t: torch.Tensor, mu_min: float = 280.0, penal
     check(lib().uvc_plan_evaluate(E.data_ptr(), K, N, t.data_ptr(), float(mu_min), float(penalty), ctypes.byref(obj),
                                   ctypes.byref(sh), ctypes.byref(ns), ctypes.byref(nv), _stream(stream)))
     return {"objective": obj.value, "shortfall": sh.value, "n_short": ns.value, "n_visible": nv.value}
+
+
+def route_geodesics(free: torch.Tensor, x0: float, y0: float, cell: float, stops: torch.Tensor, stream=None):
+    """m x m grid-geodesic distances between the stops (see
+    uvc_route_geodesics); free is an H x W uint8 device grid."""
+    free = _require_cuda(free, "free", torch.uint8)
+    stops = _require_cuda(stops, "stops", torch.float32)
+    H, W = free.shape
+    m = stops.shape[0]
+    D = torch.empty((m, m), dtype=torch.float64, device=stops.device)
+    check(lib().uvc_route_geodesics(free.data_ptr(), H, W, float(x0), float(y0), float(cell), stops.data_ptr(), m,
+                                    D.data_ptr(), _stream(stream)))
+    return D
+
+
+def route_tour(D: torch.Tensor, max_moves: int = 0, stream=None):
+    """Closed tour over the stops of distance matrix D (see uvc_route_tour):
+    (tour int32 numpy array, length, moves)."""
+    D = _require_cuda(D, "D", torch.float64)
+    m = D.shape[0]
+    tour = np.zeros(max(m, 1), np.int32)
+    L, mv = ctypes.c_double(), _I32()
+    check(lib().uvc_route_tour(D.data_ptr(), m, int(max_moves), tour.ctypes.data_as(_P), ctypes.byref(L),
+                               ctypes.byref(mv), _stream(stream)))
+    return tour[:m].copy(), L.value, mv.value
+
+
+def plan_route(poses: torch.Tensor, t: torch.Tensor, free: torch.Tensor, x0: float, y0: float, cell: float,
+               rel_threshold: float = 1e-5, v_max: float = 0.5, stream=None) -> dict:
+    """Tour over the poses with a dwell time (see uvc_plan_route)."""
+    poses = _require_cuda(poses, "poses", torch.float32)
+    t = _require_cuda(t, "t", torch.float64)
+    free = _require_cuda(free, "free", torch.uint8)
+    K, pd = poses.shape
+    H, W = free.shape
+    stops = np.zeros(max(K, 1), np.int32)
+    m, L, T = _I32(), ctypes.c_double(), ctypes.c_double()
+    check(lib().uvc_plan_route(poses.data_ptr(), K, pd, t.data_ptr(), float(rel_threshold), free.data_ptr(), H, W,
+                               float(x0), float(y0), float(cell), float(v_max), stops.ctypes.data_as(_P),
+                               ctypes.byref(m), ctypes.byref(L), ctypes.byref(T), _stream(stream)))
+    return {"stops": stops[:m.value].copy(), "length": L.value, "plan_time": T.value}

@@ -119,8 +119,32 @@ def extras(uvc, workloads, dev, log):
         b.run(mode, timing=True)
         ms = b.run(mode, timing=True)
         modes[mode] = {"ms": ms, "entries_per_s": entries / (ms * 1e-3)}
+    # the autotuner on the largest room of every size class, then the batch
+    # driven by that table (per-room packet shapes; one launch per room also
+    # per-room occupancy)
+    import tempfile
+    t0 = time.perf_counter()
+    rep = {}
+    for q, r in enumerate(rooms):
+        key = int(np.floor(np.log2(r.N)))
+        if key not in rep or r.N > rooms[rep[key]].N:
+            rep[key] = q
+    with tempfile.TemporaryDirectory() as td:
+        tpath = os.path.join(td, "tune.json")
+        tuned = {}
+        for key, q in sorted(rep.items()):
+            tuned[f"n{key}"] = uvc.autotune(scenes[q], poses[q], lamp, probe_poses=256, table_path=tpath)
+        table = open(tpath).read()
+    tune_s = time.perf_counter() - t0
+    b.close()
+    b = uvc.Batch(scenes, poses, lamp, tune_table=table)
+    for mode in ("persistent", "per_room"):
+        b.run(mode, timing=True)
+        ms = b.run(mode, timing=True)
+        modes["tuned_" + mode] = {"ms": ms, "entries_per_s": entries / (ms * 1e-3)}
     out["batched"] = {"rooms": len(rooms), "N_total": sum(r.N for r in rooms), "K_total": sum(r.K for r in rooms),
-                      "entries": entries, "E_GB": entries * 4 / 1e9, "generate_s": gen_s, "modes": modes}
+                      "entries": entries, "E_GB": entries * 4 / 1e9, "generate_s": gen_s, "modes": modes,
+                      "autotune_s": tune_s, "tuned_options": tuned}
     log(f"batched {out['batched']}")
     b.close()
     for sc in scenes:
@@ -142,6 +166,37 @@ def extras(uvc, workloads, dev, log):
                             "entries_per_s": fp.K * fp.N / csr_s}
     log(f"floorplan csr {out['floorplan_csr']}")
     del rp, col, val
+    sc.close()
+    torch.cuda.empty_cache()
+    # area-integrated irradiance (visibility cube at the paper's 512 x 512
+    # per face) on 64 ward poses
+    w = workloads.ward()
+    sc = uvc.Scene(torch.from_numpy(w.mesh.verts).to(dev), torch.from_numpy(w.mesh.tris).to(dev))
+    P = torch.from_numpy(np.ascontiguousarray(w.poses[:: max(1, w.K // 64)][:64])).to(dev)
+    uvc.irradiance_area(sc, P[:2].contiguous(), lamp, face_res=512)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Ea, Pw = uvc.irradiance_area(sc, P, lamp, face_res=512)
+    torch.cuda.synchronize()
+    area_s = time.perf_counter() - t0
+    nray = P.shape[0] * lamp.n_src * 6 * 512 * 512
+    out["area_irradiance"] = {"poses": int(P.shape[0]), "N": w.N, "face_res": 512, "rays": nray,
+                              "seconds": area_s, "rays_per_s": nray / area_s,
+                              "power_collected_W": float(Pw.mean())}
+    log(f"area {out['area_irradiance']}")
+    del Ea
+    # the ward's full plan: dense E, LP, then the route over the dwell poses
+    E, _ = uvc.irradiance_dense(sc, torch.from_numpy(w.poses).to(dev), lamp, path="lbvh")
+    sol = uvc.solve_lp(E, allow_notconv=True, max_iter=300)
+    free, x0, y0 = workloads.occupancy(w, 0.05)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rt = uvc.plan_route(torch.from_numpy(w.poses).to(dev), sol["t"], torch.from_numpy(free).to(dev), x0, y0, 0.05)
+    route_s = time.perf_counter() - t0
+    out["route"] = {"workload": "ward LP solution, 0.05 m grid", "stops": int(len(rt["stops"])),
+                    "tour_m": rt["length"], "plan_time_s": rt["plan_time"], "seconds": route_s}
+    log(f"route {out['route']}")
+    del E
     sc.close()
     torch.cuda.empty_cache()
     # dosage LP on one room (2k-20k triangles, 200-1000 poses family)

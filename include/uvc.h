@@ -297,10 +297,11 @@ void uvc_csr_job_destroy(uvc_csr_job* job);
  * ------------------------------------------------------------------------ */
 
 /* Pick the fastest launch options for this scene's size class: the first
- * probe_poses poses (<= 0: 256) are computed with every hierarchy variant
- * (packet_poses 4/8/16/32/64 x waves 5/6/8) and, for meshes of up to 200k
- * triangles, every brute-force LDS tile (256..2048); each is timed with HIP
- * events and scored in occlusion rays per second.  The winner is stored in
+ * max(probe_poses (<= 0: 256), 2^23 / N) poses, at most K (a probe large
+ * enough for the persistent loop's steady state), are computed with every
+ * hierarchy variant (packet_poses 4/8/16/32/64 x waves 5/6/8) and, for
+ * meshes of up to 16,384 triangles, every brute-force LDS tile (256..2048);
+ * each is timed with HIP events and scored in occlusion rays per second.  The winner is stored in
  * the JSON table at table_path (NULL: no table) under the key
  * "n<floor(log2 N)>_s<n_src>" and returned in *best.  When the table already
  * holds the key and force == 0, no probe runs.  Synchronises hip_stream. */
@@ -309,6 +310,15 @@ uvc_status uvc_autotune(const uvc_scene* scene, const float* poses_dev,
                         int32_t probe_poses, const char* table_path,
                         int32_t force, uvc_opts* best, void* hip_stream);
 
+/* Register a tuning table for the whole library (json: the text of a table
+ * written by uvc_autotune; NULL clears it).  While one is registered, calls
+ * with opts->path = UVC_PATH_AUTO (dense, CSR, targets and the batch) take
+ * the path, packet shape, occupancy and LDS tile of the scene's size class
+ * from it (options the caller set to nonzero values stay the caller's);
+ * size classes the table lacks keep the built-in rule (brute force up to
+ * 2,048 triangles).  UVC_EINVAL for an entry with invalid options. */
+uvc_status uvc_set_tune_table(const char* json);
+
 /* ------------------------------------------------------------------------
  * Many rooms in one launch.
  * ------------------------------------------------------------------------ */
@@ -316,17 +326,25 @@ typedef struct uvc_batch uvc_batch;
 
 enum { UVC_BATCH_PERSISTENT = 0, UVC_BATCH_GRAPH = 1, UVC_BATCH_PER_ROOM = 2 };
 
-/* Prepare the dense irradiance matrices of n_rooms rooms (same lamp and
- * options for all; hierarchy path) for repeated runs.  scenes[r], the device
- * poses poses_dev[r] (K[r] x pose_dim) and the caller-owned device outputs
- * E_dev[r] (K[r] x N_r FP32) must stay valid while the batch exists.  Poses
- * are validated here (synchronises hip_stream).  The work queue lists the
- * rooms by estimated cost per work item, longest first. */
+/* Prepare the dense irradiance matrices of n_rooms rooms (same lamp; hierarchy
+ * path) for repeated runs.  scenes[r], the device poses poses_dev[r]
+ * (K[r] x pose_dim) and the caller-owned device outputs E_dev[r] (K[r] x N_r
+ * FP32) must stay valid while the batch exists.  Launch options per room:
+ * with tune_table_json (the text of a table written by uvc_autotune), or
+ * with opts->path = UVC_PATH_AUTO and a table registered by
+ * uvc_set_tune_table, each room takes the packet shape and occupancy of its
+ * size class's hierarchy entry (the persistent launch honours the packet
+ * shape per room and runs at 6 waves per SIMD; one launch per room honours
+ * both); rooms without an entry, and every room otherwise, take opts.  The
+ * results are the same bits whatever the options.  Poses are validated here
+ * (synchronises hip_stream).  The work queue lists the rooms by estimated
+ * cost per work item, longest first. */
 uvc_status uvc_batch_create(const uvc_scene* const* scenes, int32_t n_rooms,
                             const float* const* poses_dev, const int64_t* K,
                             int32_t pose_dim, const uvc_lamp* lamp,
-                            const uvc_opts* opts, float* const* E_dev,
-                            void* hip_stream, uvc_batch** out);
+                            const uvc_opts* opts, const char* tune_table_json,
+                            float* const* E_dev, void* hip_stream,
+                            uvc_batch** out);
 
 /* Compute every room's E.  mode UVC_BATCH_PERSISTENT: one persistent launch
  * whose workgroups drain the queue through an atomic counter;

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -44,14 +45,8 @@ double read_num(const std::string& body, const char* name) {
     return std::atof(body.c_str() + at + k.size());
 }
 
-std::map<std::string, Entry> read_table(const char* path) {
+std::map<std::string, Entry> parse_table(const std::string& s) {
     std::map<std::string, Entry> t;
-    if (!path) return t;
-    std::ifstream f(path);
-    if (!f) return t;
-    std::stringstream ss;
-    ss << f.rdbuf();
-    const std::string s = ss.str();
     size_t pos = 0;
     while (true) {
         const size_t q0 = s.find('"', pos);
@@ -73,6 +68,27 @@ std::map<std::string, Entry> read_table(const char* path) {
         pos = b1 + 1;
     }
     return t;
+}
+
+std::map<std::string, Entry> read_table(const char* path) {
+    if (!path) return {};
+    std::ifstream f(path);
+    if (!f) return {};
+    std::stringstream ss;
+    ss << f.rdbuf();
+    return parse_table(ss.str());
+}
+
+// The table registered with uvc_set_tune_table (consulted by UVC_PATH_AUTO
+// and by batches created without a table of their own).
+std::mutex g_tune_mu;
+std::map<std::string, Entry> g_tune;
+
+void fill_opts(const Entry& e, uvc_opts& o) {
+    o.path = e.path;
+    o.packet_poses = e.packet_poses;
+    o.waves = e.waves;
+    o.tile_tris = e.tile_tris;
 }
 
 bool write_table(const char* path, const std::map<std::string, Entry>& t) {
@@ -126,7 +142,11 @@ extern "C" uvc_status uvc_autotune(const uvc_scene* scene, const float* poses_de
         return UVC_OK;
     }
     hipStream_t s = (hipStream_t)hip_stream;
-    const int64_t P = std::max<int64_t>(1, std::min<int64_t>(K, probe_poses > 0 ? probe_poses : 256));
+    // the probe must be large enough for the persistent loop to run in its
+    // steady state (a few hundred poses leave most workgroups idle at the
+    // end and favour small packets): at least 2^23 entries, at most K poses
+    const int64_t want = std::max<int64_t>(probe_poses > 0 ? probe_poses : 256, ((int64_t)1 << 23) / std::max<int64_t>(n, 1));
+    const int64_t P = std::max<int64_t>(1, std::min<int64_t>(K, want));
     float* E = nullptr;
     unsigned long long* stats = nullptr;
     if (hipMalloc(&E, (size_t)P * n * 4) != hipSuccess || hipMalloc(&stats, 8 * UVC_STAT_N) != hipSuccess) {
@@ -143,7 +163,9 @@ extern "C" uvc_status uvc_autotune(const uvc_scene* scene, const float* poses_de
             e.waves = w;
             cands.push_back(e);
         }
-    if (n <= 200000)
+    // brute force costs N segment/triangle tests per segment: only small
+    // meshes can win with it
+    if (n <= 16384)
         for (int tt : {256, 512, 1024, 2048}) {
             Entry e;
             e.path = UVC_PATH_BRUTE;
@@ -192,5 +214,43 @@ extern "C" uvc_status uvc_autotune(const uvc_scene* scene, const float* poses_de
     fill(win);
     if (!write_table(table_path, table))
         return uvc::fail(UVC_EINVAL, std::string("cannot write the tuning table ") + table_path);
+    return UVC_OK;
+}
+
+namespace uvc {
+// Launch options of the table entry for this scene size and source count
+// (json: a table text, or NULL for the registered table).  Returns false
+// (o unchanged) when the table has no entry for the bucket.
+bool tune_lookup(const char* json, int64_t n, int n_src, uvc_opts& o) {
+    const std::string key = bucket_key(n, n_src);
+    if (json) {
+        const auto t = parse_table(json);
+        const auto it = t.find(key);
+        if (it == t.end()) return false;
+        fill_opts(it->second, o);
+        return true;
+    }
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    fill_opts(it->second, o);
+    return true;
+}
+}  // namespace uvc
+
+extern "C" uvc_status uvc_set_tune_table(const char* json) {
+    std::map<std::string, Entry> t;
+    if (json) {
+        t = parse_table(json);
+        for (const auto& kv : t) {
+            const Entry& e = kv.second;
+            const bool ok_tp = e.packet_poses >= 1 && e.packet_poses <= 64 && (e.packet_poses & (e.packet_poses - 1)) == 0;
+            if ((e.path != UVC_PATH_LBVH && e.path != UVC_PATH_BRUTE) || !ok_tp ||
+                (e.waves != 5 && e.waves != 6 && e.waves != 8) || e.tile_tris < 1 || e.tile_tris > 2048)
+                return uvc::fail(UVC_EINVAL, "tuning table entry " + kv.first + " has invalid options");
+        }
+    }
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune = std::move(t);
     return UVC_OK;
 }

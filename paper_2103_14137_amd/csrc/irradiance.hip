@@ -1034,6 +1034,23 @@ static int choose_path(const uvc_scene* s, const uvc_opts* opts) {
     return s->n <= 2048 ? UVC_PATH_BRUTE : UVC_PATH_LBVH;
 }
 
+// UVC_PATH_AUTO with a registered tuning table: the table's path, and its
+// packet shape, occupancy and LDS tile wherever the caller left them at 0.
+// Other options (flags, bands, counters, timing) stay the caller's.
+static uvc_opts resolve_auto(const uvc_scene* s, const uvc_lamp* lamp, const uvc_opts* opts) {
+    uvc_opts o{};
+    o.band_scale = 1.0f;
+    if (opts) o = *opts;
+    if (o.path != UVC_PATH_AUTO || !s || !lamp) return o;
+    uvc_opts t{};
+    if (!tune_lookup(nullptr, s->n, lamp->n_src, t)) return o;
+    o.path = t.path;
+    if (o.packet_poses <= 0) o.packet_poses = t.packet_poses;
+    if (o.waves <= 0) o.waves = t.waves;
+    if (o.tile_tris <= 0) o.tile_tris = t.tile_tris;
+    return o;
+}
+
 // Launch the irradiance kernel for P.K poses into P.E / P.vis.
 // counter_ext: NULL (a stream-ordered allocation holds the persistent
 // loop's 8 work counters for this launch) or 8 caller-provided counters.
@@ -1160,8 +1177,10 @@ static uvc_status upload_order(const std::vector<float>& hp, int pd, int64_t k0,
 }
 
 extern "C" uvc_status uvc_compute_irradiance_dense(const uvc_scene* scene, const float* poses_dev, int64_t K,
-                                                   int32_t pose_dim, const uvc_lamp* lamp, const uvc_opts* opts,
+                                                   int32_t pose_dim, const uvc_lamp* lamp, const uvc_opts* opts_in,
                                                    float* E_dev, uint32_t* vis_dev, void* hip_stream) {
+    const uvc_opts opts_r = resolve_auto(scene, lamp, opts_in);
+    const uvc_opts* opts = &opts_r;
     IrrParams P;
     UVC_TRY(make_params(scene, poses_dev, K, pose_dim, lamp, opts, P));
     if (K == 0 || scene->n == 0) return UVC_OK;
@@ -1305,8 +1324,10 @@ static void free_job(uvc_csr_job* j) {
 }
 
 extern "C" uvc_status uvc_compute_irradiance_csr_begin(const uvc_scene* scene, const float* poses_dev, int64_t K,
-                                                       int32_t pose_dim, const uvc_lamp* lamp, const uvc_opts* opts,
+                                                       int32_t pose_dim, const uvc_lamp* lamp, const uvc_opts* opts_in,
                                                        void* hip_stream, uvc_csr_job** job, int64_t* nnz) {
+    const uvc_opts opts_r = resolve_auto(scene, lamp, opts_in);
+    const uvc_opts* opts = &opts_r;
     if (!job || !nnz) return fail(UVC_EINVAL, "job / nnz output is NULL");
     *job = nullptr;
     *nnz = 0;
@@ -1472,7 +1493,8 @@ static void free_batch(uvc_batch* b) {
 
 extern "C" uvc_status uvc_batch_create(const uvc_scene* const* scenes, int32_t n_rooms, const float* const* poses_dev,
                                        const int64_t* K, int32_t pose_dim, const uvc_lamp* lamp, const uvc_opts* opts,
-                                       float* const* E_dev, void* hip_stream, uvc_batch** out) {
+                                       const char* tune_table_json, float* const* E_dev, void* hip_stream,
+                                       uvc_batch** out) {
     if (!out) return fail(UVC_EINVAL, "out is NULL");
     *out = nullptr;
     if (n_rooms < 0 || (n_rooms > 0 && (!scenes || !poses_dev || !K || !E_dev)))
@@ -1484,8 +1506,21 @@ extern "C" uvc_status uvc_batch_create(const uvc_scene* const* scenes, int32_t n
     std::vector<std::vector<int32_t>> orders((size_t)n_rooms);
     int64_t order_total = 0;
     for (int32_t r = 0; r < n_rooms; ++r) {
+        // per room: the tuning table's packet shape and occupancy for its
+        // size class (hierarchy path; the caller's options otherwise)
+        uvc_opts ro{};
+        ro.band_scale = 1.0f;
+        if (opts) ro = *opts;
+        uvc_opts t{};
+        if (scenes && scenes[r] && lamp &&
+            (tune_table_json || ro.path == UVC_PATH_AUTO) &&
+            tune_lookup(tune_table_json, scenes[r]->n, lamp->n_src, t) && t.path == UVC_PATH_LBVH) {
+            ro.packet_poses = t.packet_poses;
+            ro.waves = t.waves;
+        }
+        ro.path = UVC_PATH_LBVH;
         IrrParams P;
-        uvc_status st_ = make_params(scenes[r], poses_dev[r], K[r], pose_dim, lamp, opts, P);
+        uvc_status st_ = make_params(scenes[r], poses_dev[r], K[r], pose_dim, lamp, &ro, P);
         if (st_ == UVC_OK && lamp_variant(P.lamp))
             st_ = fail(UVC_EUNSUPPORTED, "the many-room batch takes uniform lamps only");
         if (st_ == UVC_OK && K[r] > 0 && scenes[r]->n > 0 && !E_dev[r]) st_ = fail(UVC_EINVAL, "E is NULL");
@@ -1626,9 +1661,11 @@ extern "C" void uvc_batch_destroy(uvc_batch* b) {
 }
 
 extern "C" uvc_status uvc_compute_irradiance_targets(const uvc_scene* scene, const float* poses_dev, int64_t K,
-                                                     int32_t pose_dim, const uvc_lamp* lamp, const uvc_opts* opts,
+                                                     int32_t pose_dim, const uvc_lamp* lamp, const uvc_opts* opts_in,
                                                      const int32_t* targets_dev, int64_t n_targets, float* E_dev,
                                                      uint32_t* vis_dev, void* hip_stream) {
+    const uvc_opts opts_r = resolve_auto(scene, lamp, opts_in);
+    const uvc_opts* opts = &opts_r;
     IrrParams P;
     UVC_TRY(make_params(scene, poses_dev, K, pose_dim, lamp, opts, P));
     if (n_targets < 0) return fail(UVC_EINVAL, "n_targets < 0");

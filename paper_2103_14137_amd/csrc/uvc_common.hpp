@@ -95,6 +95,11 @@ struct LampArgs {
     uint32_t up, down; // hemisphere masks
 };
 
+// Launch options from a tuning table (json text, or NULL: the table
+// registered with uvc_set_tune_table) for an n-triangle scene and n_src
+// sources; false when the table has no entry for that size class.
+bool tune_lookup(const char* json, int64_t n, int n_src, uvc_opts& o);
+
 // Validates a lamp of the C ABI and fills its kernel form.
 uvc_status lamp_args(const uvc_lamp* lamp, LampArgs& L);
 

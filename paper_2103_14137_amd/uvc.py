@@ -93,8 +93,9 @@ def lib():
         "uvc_compute_irradiance_csr_finish": ([_P, _P, _P, _P, _P], _I32),
         "uvc_csr_job_destroy": ([_P], None),
         "uvc_batch_create": ([ctypes.POINTER(_P), _I32, ctypes.POINTER(_P), ctypes.POINTER(_I64), _I32,
-                              ctypes.POINTER(LampC), ctypes.POINTER(OptsC), ctypes.POINTER(_P), _P, ctypes.POINTER(_P)],
-                             _I32),
+                              ctypes.POINTER(LampC), ctypes.POINTER(OptsC), ctypes.c_char_p, ctypes.POINTER(_P), _P,
+                              ctypes.POINTER(_P)], _I32),
+        "uvc_set_tune_table": ([ctypes.c_char_p], _I32),
         "uvc_batch_run": ([_P, _I32, ctypes.POINTER(ctypes.c_float), _P], _I32),
         "uvc_batch_destroy": ([_P], None),
         "uvc_autotune": ([_P, _P, _I64, _I32, ctypes.POINTER(LampC), _I32, ctypes.c_char_p, _I32,
@@ -406,7 +407,8 @@ class Batch:
     launch (optionally replayed from a hipGraph).  Keeps references to the
     scenes, poses and outputs it was created with."""
 
-    def __init__(self, scenes, poses_list, lamp, packet_poses: int = 0, waves: int = 0, stream=None):
+    def __init__(self, scenes, poses_list, lamp, packet_poses: int = 0, waves: int = 0, stream=None,
+                 tune_table: str | None = None, path: str = "lbvh"):
         self.scenes = list(scenes)
         self.poses = [_require_cuda(p, "poses", torch.float32) for p in poses_list]
         if len(self.poses) != len(self.scenes):
@@ -422,11 +424,12 @@ class Batch:
         self._ps = SA(*[p.data_ptr() for p in self.poses])
         self._ks = KA(*[p.shape[0] for p in self.poses])
         self._es = SA(*[e.data_ptr() for e in self.E])
-        self._opts = make_opts("lbvh", packet_poses=packet_poses, waves=waves)
+        self._opts = make_opts(path, packet_poses=packet_poses, waves=waves)
         h = _P()
         self._h = None
+        tt = tune_table.encode() if tune_table is not None else None
         check(lib().uvc_batch_create(self._sc, n, self._ps, self._ks, pd, ctypes.byref(self.lamp._c),
-                                     ctypes.byref(self._opts), self._es, _stream(stream), ctypes.byref(h)))
+                                     ctypes.byref(self._opts), tt, self._es, _stream(stream), ctypes.byref(h)))
         self._h = h
 
     def run(self, mode: str = "graph", timing: bool = False, stream=None):
@@ -445,6 +448,12 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def set_tune_table(json_text: str | None) -> None:
+    """Register a tuning table (its JSON text) for UVC_PATH_AUTO calls; None
+    clears it (see uvc_set_tune_table)."""
+    check(lib().uvc_set_tune_table(json_text.encode() if json_text is not None else None))
 
 
 def autotune(scene: Scene, poses: torch.Tensor, lamp, probe_poses: int = 256, table_path: str | None = None,

@@ -95,3 +95,69 @@ def test_full_size_batch_equals_per_room_and_oracle(uvc):
     del ref_E
     for sc in scenes:
         sc.close()
+
+
+def _table(entries):
+    """A tuning table in the layout uvc_autotune writes."""
+    import json
+    return json.dumps({k: {"path": p, "packet_poses": tp, "waves": wv, "tile_tris": 512, "rays_per_s": 1.0}
+                       for k, (p, tp, wv) in entries.items()})
+
+
+def test_tuned_batch_equals_per_room(uvc, rooms):
+    """A batch driven by a tuning table (a different packet shape and
+    occupancy per size class) writes the bits of the untuned batch in every
+    mode; the table is also honoured when registered and the batch asks for
+    UVC_PATH_AUTO."""
+    scenes = [uvc.Scene(w.mesh.verts, w.mesh.tris) for w in rooms]
+    poses = [torch.from_numpy(w.poses).cuda() for w in rooms]
+    lamp = rooms[0].lamp
+    b0 = uvc.Batch(scenes, poses, lamp)
+    b0.run("persistent")
+    torch.cuda.synchronize()
+    ref_E = [e.clone() for e in b0.E]
+    b0.close()
+    buckets = sorted({int(np.floor(np.log2(w.N))) for w in rooms})
+    shapes = [(1, 4, 5), (1, 64, 8), (1, 32, 6), (1, 8, 5), (1, 1, 6)]
+    table = _table({f"n{bk}_s8": shapes[q % len(shapes)] for q, bk in enumerate(buckets)})
+    for how in ("argument", "registered"):
+        if how == "argument":
+            b = uvc.Batch(scenes, poses, lamp, tune_table=table)
+        else:
+            uvc.set_tune_table(table)
+            b = uvc.Batch(scenes, poses, lamp, path="auto")
+        for mode in ("persistent", "graph", "per_room"):
+            for e in b.E:
+                e.fill_(-1.0)
+            b.run(mode)
+            torch.cuda.synchronize()
+            for r, (e, s1) in enumerate(zip(b.E, ref_E)):
+                assert torch.equal(e, s1), (how, mode, r)
+        b.close()
+    uvc.set_tune_table(None)
+    for sc in scenes:
+        sc.close()
+
+
+def test_registered_table_drives_auto_path(uvc):
+    """With a registered table, UVC_PATH_AUTO takes the table's path for the
+    scene's size class: the box room (1,052 triangles) goes to the hierarchy
+    instead of the built-in brute-force rule (the counters show node
+    visits), with the same bits; clearing the table restores the rule."""
+    w = wl.box_room()
+    sc = uvc.Scene(w.mesh.verts, w.mesh.tris)
+    poses = torch.from_numpy(w.poses[:20].copy()).cuda()
+    s0 = uvc.new_stats()
+    E0, _ = uvc.irradiance_dense(sc, poses, w.lamp, path="auto", stats=s0)
+    uvc.set_tune_table(_table({"n10_s1": (1, 16, 6)}))
+    s1 = uvc.new_stats()
+    E1, _ = uvc.irradiance_dense(sc, poses, w.lamp, path="auto", stats=s1)
+    uvc.set_tune_table(None)
+    s2 = uvc.new_stats()
+    E2, _ = uvc.irradiance_dense(sc, poses, w.lamp, path="auto", stats=s2)
+    torch.cuda.synchronize()
+    assert uvc.stats_dict(s0)["nodes"] == 0 and uvc.stats_dict(s1)["nodes"] > 0 and uvc.stats_dict(s2)["nodes"] == 0
+    assert torch.equal(E0, E1) and torch.equal(E0, E2)
+    with pytest.raises(uvc.UvcError, match="invalid options"):
+        uvc.set_tune_table(_table({"n10_s1": (1, 3, 6)}))
+    sc.close()

@@ -21,8 +21,10 @@ little-endian float32.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
+import os
 import sys
 import time
 
@@ -98,6 +100,58 @@ def room_samples(w: workloads.Workload, mu_min: float = 280.0, t_max: float = 3.
                 "K": w.K, "N": w.N}
     finally:
         sc.close()
+
+
+# ------------------------------------------------------------ label cache
+# One JSON line per labelled room: how to regenerate it (seed and size
+# ranges), a hash of the generated scene (mesh, poses, lamp) so that a
+# regenerated room is checked to be the one that was labelled, and the
+# label: the poses with a dwell time in the full-candidate LP.  Labels thus
+# survive across runs; features are recomputed (one cheap kernel per room).
+def scene_key(w: workloads.Workload) -> str:
+    h = hashlib.sha1()
+    for a in (w.mesh.verts, w.mesh.tris, w.poses, w.lamp.dz, w.lamp.power):
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()[:20]
+
+
+def read_cache(path: str) -> dict:
+    out = {}
+    if path and os.path.exists(path):
+        with open(path) as f:
+            for line in f:
+                line = line.strip()
+                if line:
+                    rec = json.loads(line)
+                    out[(rec["seed"], tuple(rec["n_range"]), tuple(rec["k_range"]))] = rec
+    return out
+
+
+def label_record(seed: int, n_range, k_range, mu_min: float = 280.0, t_max: float = 3.6e5,
+                 tol: float = 1e-9) -> dict:
+    w = room(seed, tuple(n_range), tuple(k_range))
+    t0 = time.time()
+    d = room_samples(w, mu_min, t_max, tol)
+    return {"seed": int(seed), "n_range": list(n_range), "k_range": list(k_range), "key": scene_key(w),
+            "K": w.K, "N": w.N, "positives": np.nonzero(d["y"])[0].astype(int).tolist(),
+            "objective": d["objective"], "converged": bool(d["converged"]), "seconds": time.time() - t0}
+
+
+def cached_samples(rec: dict) -> tuple:
+    """Features (recomputed) and labels of a cached room, after checking
+    that the regenerated scene is the labelled one."""
+    w = room(rec["seed"], tuple(rec["n_range"]), tuple(rec["k_range"]))
+    if scene_key(w) != rec["key"]:
+        raise ValueError(f"room {rec['seed']}: regenerated scene differs from the labelled one")
+    sc = uvc.Scene(w.mesh.verts, w.mesh.tris)
+    try:
+        poses = torch.from_numpy(np.ascontiguousarray(w.poses, np.float32)).cuda()
+        feat = uvc.ranker_features(sc, poses, FEATURE_HEIGHT).cpu()
+    finally:
+        sc.close()
+    y = np.zeros(w.K, np.float32)
+    y[np.asarray(rec["positives"], np.int64)] = 1.0
+    return feat, y
 
 
 def train(feat: torch.Tensor, y: np.ndarray, params=None, m=None, v=None, step0: int = 0, epochs: int = 30,
@@ -193,7 +247,24 @@ def _main(argv=None) -> int:
     t.add_argument("--seed", type=int, default=0)
     t.add_argument("--resume", default=None, help="checkpoint with Adam state to continue from")
     t.add_argument("--out", required=True)
+    g = sub.add_parser("labels", help="label rooms into a cache (resumable)")
+    g.add_argument("--cache", required=True)
+    g.add_argument("--seed0", type=int, default=TRAIN_SEED0)
+    g.add_argument("--rooms", type=int, default=256)
+    g.add_argument("--n-range", type=int, nargs=2, default=list(TRAIN_N_RANGE))
+    g.add_argument("--k-range", type=int, nargs=2, default=list(TRAIN_K_RANGE))
+    g.add_argument("--time-limit", type=float, default=0.0, help="stop starting rooms after this many seconds")
+    tc = sub.add_parser("train-cached", help="train on the rooms of label caches")
+    tc.add_argument("--cache", nargs="+", required=True)
+    tc.add_argument("--epochs", type=int, default=40)
+    tc.add_argument("--batch", type=int, default=1024)
+    tc.add_argument("--lr", type=float, default=1e-3)
+    tc.add_argument("--seed", type=int, default=0)
+    tc.add_argument("--out", required=True)
     e = sub.add_parser("eval", help="held-out evaluation of a checkpoint")
+    e.add_argument("--results", default=None, help="JSON lines of per-room results (resumable)")
+    e.add_argument("--modes", nargs="+", default=["mlp", "area"])
+    e.add_argument("--time-limit", type=float, default=0.0)
     e.add_argument("--weights", required=True)
     e.add_argument("--rooms", type=int, default=64)
     e.add_argument("--keep", type=float, default=0.1)
@@ -207,6 +278,44 @@ def _main(argv=None) -> int:
     def log(msg):
         print(msg, flush=True)
 
+    if a.cmd == "labels":
+        have = read_cache(a.cache)
+        t0 = time.time()
+        done = 0
+        with open(a.cache, "a") as f:
+            for r in range(a.rooms):
+                key = (a.seed0 + r, tuple(a.n_range), tuple(a.k_range))
+                if key in have:
+                    continue
+                if a.time_limit and time.time() - t0 > a.time_limit:
+                    log(f"time limit: stopping after {done} new rooms")
+                    break
+                rec = label_record(a.seed0 + r, a.n_range, a.k_range)
+                f.write(json.dumps(rec) + "\n")
+                f.flush()
+                done += 1
+                log(f"room {a.seed0 + r}: K={rec['K']} N={rec['N']} positives {len(rec['positives'])} "
+                    f"({rec['seconds']:.1f} s)")
+        log(f"labelled {done} new rooms in {time.time() - t0:.1f} s; cache has {len(read_cache(a.cache))}")
+        return 0
+    if a.cmd == "train-cached":
+        feats, ys, rooms = [], [], 0
+        for path in a.cache:
+            for rec in read_cache(path).values():
+                fx, yy = cached_samples(rec)
+                feats.append(fx)
+                ys.append(yy)
+                rooms += 1
+        X = torch.cat(feats)
+        Y = np.concatenate(ys)
+        log(f"{rooms} rooms, {X.shape[0]} poses, positives {Y.mean():.4f}")
+        p, m, v, step, losses = train(X, Y, None, None, None, 0, a.epochs, a.batch, a.lr, a.seed, log)
+        meta = {"rooms": rooms, "samples": int(X.shape[0]), "positives": float(Y.mean()), "epochs": a.epochs,
+                "batch": a.batch, "lr": a.lr, "final_loss": losses[-1], "label_rel": LABEL_REL,
+                "feature_height": FEATURE_HEIGHT, "caches": [os.path.basename(c) for c in a.cache]}
+        save_checkpoint(a.out, p, m, v, step, meta)
+        log(json.dumps(meta))
+        return 0
     if a.cmd == "train":
         feats, ys = [], []
         t0 = time.time()
@@ -231,14 +340,29 @@ def _main(argv=None) -> int:
         log(json.dumps(meta))
         return 0
     ck = load_checkpoint(a.weights)
+    modes = tuple(a.modes)
     res = []
+    if a.results and os.path.exists(a.results):
+        with open(a.results) as f:
+            res = [json.loads(line) for line in f if line.strip()]
+    done = {x["room"] for x in res}
+    t0 = time.time()
     for r in range(a.rooms):
-        res.append(evaluate_room(room(a.seed0 + r, tuple(a.n_range), tuple(a.k_range)), ck["params"], a.keep, a.bf16))
-        x = res[-1]
+        w = room(a.seed0 + r, tuple(a.n_range), tuple(a.k_range))
+        if w.name in done:
+            continue
+        if a.time_limit and time.time() - t0 > a.time_limit:
+            log(f"time limit: {len(res)} rooms evaluated")
+            break
+        x = evaluate_room(w, ck["params"], a.keep, a.bf16, modes=modes)
+        res.append(x)
+        if a.results:
+            with open(a.results, "a") as f:
+                f.write(json.dumps(x) + "\n")
         log(f"room {r}: K={x['K']} N={x['N']} full {x['full_ms']:.0f} ms | " +
             " | ".join(f"{m} gap {x[m]['gap']:.1e} rounds {x[m]['rounds']} kept {x[m]['n_kept']} {x[m]['ms']:.0f} ms"
-                       for m in ("mlp", "area")))
-    s = summarize(res)
+                       for m in modes))
+    s = summarize(res, modes)
     log(json.dumps(s))
     if a.json:
         with open(a.json, "w") as f:

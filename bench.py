@@ -94,7 +94,7 @@ def cpu_baseline(w, n_poses=32, n_elems=1024, seed=2024):
             "seconds": dt, "entries_per_s": len(pk) / dt}
 
 
-def extras(uvc, workloads, dev, log):
+def extras(uvc, workloads, dev, log, floorplan_lp=False):
     """The additions around the hot path, each timed once: the 64-room
     batched launch (persistent, hipGraph replay, one launch per room), the
     floor plan as CSR, the dosage LP on one room, and the ranked plan
@@ -165,6 +165,22 @@ def extras(uvc, workloads, dev, log):
     out["floorplan_csr"] = {"K": fp.K, "N": fp.N, "seconds": csr_s, "nnz": nnz, "csr_GB": nnz * 8 / 1e9,
                             "entries_per_s": fp.K * fp.N / csr_s}
     log(f"floorplan csr {out['floorplan_csr']}")
+    if floorplan_lp:
+        # the floor plan's dosage LP straight from the CSR (column generation;
+        # minutes: opt-in, progress per round on stderr)
+        os.environ["UVC_VERBOSE"] = "1"
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        flp = uvc.solve_lp(val, csr=(rp, col, fp.N), allow_notconv=True, max_iter=300)
+        torch.cuda.synchronize()
+        out["floorplan_lp"] = {"seconds": time.perf_counter() - t0, "objective": flp["objective"],
+                               "converged": flp["converged"], "working_poses": flp["working_poses"],
+                               "rounds": flp["rounds"], "iterations": flp["iterations"],
+                               "primal_residual": flp["primal_residual"], "dual_residual": flp["dual_residual"],
+                               "gap": flp["gap"], "n_visible": flp["n_visible"], "dwell_s": float(flp["t"].sum()),
+                               "stops": int((flp["t"] > 1e-5 * flp["t"].sum()).sum())}
+        log(f"floorplan lp {out['floorplan_lp']}")
+        del flp
     del rp, col, val
     sc.close()
     torch.cuda.empty_cache()
@@ -213,15 +229,25 @@ def extras(uvc, workloads, dev, log):
     log(f"lp {out['lp']}")
     sc.close()
     del E
-    # ranked plan vs full on one larger room (trained weights)
-    wpath = os.path.join(ROOT, "paper_2103_14137_amd", "weights", "ranker_tower8.bin")
+    # ranked plan vs full: the committed summary over the 200 held-out rooms
+    # at the batched-room sizes, and one of those rooms (the one whose full
+    # LP takes longest) run live
+    wdir = os.path.join(ROOT, "paper_2103_14137_amd", "weights")
+    wpath = os.path.join(wdir, "ranker_tower8.bin")
     if os.path.exists(wpath):
         ck = ranker.load_checkpoint(wpath)
-        w = ranker.room(950000, (20000, 80000), (1000, 3000))
+        w = ranker.room(200006, (2000, 80000), (500, 8000))
         r = ranker.evaluate_room(w, ck["params"], keep_frac=0.1, modes=("mlp", "area"))
-        out["ranked_plan"] = {"K": r["K"], "N": r["N"], "full_ms": r["full_ms"],
+        out["ranked_plan"] = {"room": "held-out batch room 200006", "K": r["K"], "N": r["N"], "full_ms": r["full_ms"],
                               **{m: {k: r[m][k] for k in ("gap", "ms", "rounds", "n_kept", "fell_back")}
                                  for m in ("mlp", "area")}}
+        sp = os.path.join(wdir, "ranker_tower8_eval_heldout200.json")
+        if os.path.exists(sp):
+            summ = json.load(open(sp))["summary"]
+            out["ranked_plan"]["heldout200_recorded"] = {
+                "rooms": summ["rooms"], "full_ms_total": summ["full_ms_total"],
+                **{m: {k: summ[m][k] for k in ("gap_max", "gap_le_2pct", "fallback_rate", "ms_total",
+                                              "speedup_vs_full")} for m in ("mlp", "area")}}
         log(f"ranked plan {out['ranked_plan']}")
     return out
 
@@ -234,6 +260,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the brute-force path comparison")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched / LP / ranked-plan sections")
+    ap.add_argument("--floorplan-lp", action="store_true",
+                    help="also solve the floor plan's dosage LP from its CSR (column generation; minutes)")
     ap.add_argument("--mode", choices=["bench", "kernel", "copy"], default="bench",
                     help="kernel: only two launches of the irradiance kernel (for counter runs); "
                          "copy: a plain 1 GiB device copy (counter calibration)")
@@ -367,7 +395,7 @@ def main():
     del E
     torch.cuda.empty_cache()
     if not args.no_extras:
-        out["extras"] = extras(uvc, workloads, dev, log)
+        out["extras"] = extras(uvc, workloads, dev, log, floorplan_lp=args.floorplan_lp)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
         log(f"cpu baseline {out['cpu_baseline']}")

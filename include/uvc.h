@@ -66,9 +66,10 @@ typedef struct uvc_scene uvc_scene;
  *               (they are copied to the host once for validation).
  * The scene keeps its own copies; the inputs may be freed on return.  This
  * call synchronises hip_stream.  Errors: UVC_EINVAL for non-finite vertices,
- * indices outside [0, n_verts) or a triangle whose FP64 cross product is
- * exactly zero (the message names the first such triangle); UVC_ENOMEM;
- * UVC_EDEVICE. */
+ * a vertex coordinate above 2^26 in magnitude (the FP32 box tests stay
+ * finite below it), indices outside [0, n_verts) or a triangle whose FP64
+ * cross product is exactly zero (the message names the first such
+ * triangle); UVC_ENOMEM; UVC_EDEVICE. */
 uvc_status uvc_build_scene(const float* verts_xyz, int64_t n_verts,
                            const int32_t* tri_idx, int64_t n_tris,
                            int32_t inputs_on_device, void* hip_stream,
@@ -370,6 +371,9 @@ typedef struct {
     int32_t iterations;
     int64_t n_visible;       /* elements with some E[k,i] > 0                     */
     double penalty;          /* p_0 (the default penalty when penalty_dev = NULL) */
+    int64_t working_poses;   /* column generation (large CSR input): poses in the
+                                final working set; 0 for a direct solve           */
+    int32_t rounds;          /* column generation: working LPs solved; 0 direct  */
 } uvc_lp_info;
 
 /* Solve  min sum_k t_k + sum_i p_i sigma_i
@@ -381,8 +385,17 @@ typedef struct {
  * col_dev: nnz = row_ptr[K] int32 element indices, strictly ascending within
  * each row, in [0, N); E_dev: the nnz FP32 values), e.g. the output of
  * uvc_compute_irradiance_csr_*.  A CSR input is validated on the device (a
- * bad row is named in the error) and expanded once into a library-owned
- * dense copy of K N 4 bytes for the normal-matrix products.  Elements with
+ * bad row is named in the error).  Up to 8,192 poses it is expanded once
+ * into a library-owned dense copy of K N 4 bytes for the normal-matrix
+ * products; with more poses the LP is solved by column generation: the
+ * method below over a working set of poses (initially the ceil(K/10)
+ * poses with the largest row sums of E), every other pose priced against the working
+ * duals (reduced cost 1 + y_b - sum_i E[k,i] y_i from its sparse row) and
+ * those below -1e-6 added (the most negative first, at most max(64, |R|)
+ * per round: the set at most doubles) until
+ * none is left, which makes the working solution optimal over all K poses
+ * (info->working_poses, info->rounds; the dual residual reported covers the
+ * pricing).  Elements with
  * E[k,i] = 0 for every k are dropped (sigma_i = mu_min, excluded from the
  * objective).  penalty_dev: N FP64 device values or NULL for
  * p_i = 1.001 * ||E||_F (the paper asks for p_i > ||I||_F).  Mehrotra

@@ -23,6 +23,10 @@
 // Every device reduction sums in a fixed order: results are deterministic.
 #include "uvc_common.hpp"
 
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
@@ -1422,9 +1426,11 @@ __global__ __launch_bounds__(LP_TB) void k_csr_scatter(const int64_t* __restrict
 // dense whatever the sparsity of E; its product reads E as a dense pose-major
 // matrix.  A CSR input is validated and expanded once into a library-owned
 // dense copy (K N 4 bytes; released after the solve).
-static uvc_status csr_to_dense(const int64_t* rp, const int32_t* col, const float* val, int64_t K, int64_t N,
-                               hipStream_t st, float** out) {
-    *out = nullptr;
+// CSR inputs with more poses than this are solved by column generation.
+constexpr int64_t LP_DENSE_MAX_POSES = 8192;
+
+static uvc_status csr_validate(const int64_t* rp, const int32_t* col, const float* val, int64_t K, int64_t N,
+                               hipStream_t st, int64_t* nnz_out) {
     if (K > (int64_t)0x7fffffff) return fail(UVC_EINVAL, "K too large for a CSR input");
     int64_t ends[2] = {0, 0};
     UVC_HIP(hipMemcpyAsync(&ends[0], rp, 8, hipMemcpyDeviceToHost, st));
@@ -1445,17 +1451,259 @@ static uvc_status csr_to_dense(const int64_t* rp, const int32_t* col, const floa
     if (hb != ~0ull)
         return fail(UVC_EINVAL, "CSR row " + std::to_string(hb) +
                                     ": row_ptr decreasing, or columns outside [0, N) or not strictly ascending");
+    *nnz_out = ends[1];
+    return UVC_OK;
+}
+
+static uvc_status csr_to_dense(const int64_t* rp, const int32_t* col, const float* val, int64_t K, int64_t N,
+                               hipStream_t st, float** out) {
+    *out = nullptr;
+    int64_t nnz = 0;
+    UVC_TRY(csr_validate(rp, col, val, K, N, st, &nnz));
     float* D = nullptr;
     UVC_TRY(dalloc_n(&D, (size_t)K * (size_t)N, "dense copy of the CSR matrix"));
     hipLaunchKernelGGL(k_fill_f32, dim3(4096), dim3(LP_TB), 0, st, D, 0.0f, K * N);
     hipLaunchKernelGGL(k_csr_scatter, dim3((unsigned)K), dim3(LP_TB), 0, st, rp, col, val, N, D);
-    e = hipGetLastError();
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         (void)hipFree(D);
         return fail(UVC_EDEVICE, std::string("csr expand: ") + hipGetErrorString(e));
     }
     *out = D;
     return UVC_OK;
+}
+
+// ------------------------------------------- large CSR input: column generation
+// For a CSR matrix with many poses the K x K normal matrix (and the dense
+// copy of E) would dominate; the LP is instead solved over a working set R
+// of poses, with every other pose priced against the working LP's duals:
+// pose k's reduced cost is 1 + y_b - sum_i E[k,i] y_i (a sparse row times
+// the dual vector); poses with negative reduced costs join R until none is
+// below -1e-6, at which point the working solution is optimal for the LP
+// over all K poses.  R starts with, for every visible element, the pose
+// that sees it best (so every visible element is coverable within R).
+
+// best[i] = max over the entries (k, i) of (bits(E[k,i]) << 32 | k): E >= 0,
+// so the float bits order like the values; nonzero exactly for the visible
+// elements.
+__global__ __launch_bounds__(LP_TB) void k_csr_colbest(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                       const float* __restrict__ val,
+                                                       unsigned long long* __restrict__ best) {
+    const int64_t k = blockIdx.x;
+    for (int64_t q = rp[k] + threadIdx.x; q < rp[k + 1]; q += LP_TB) {
+        const float v = val[q];
+        if (v > 0.0f)
+            atomicMax(best + col[q], ((unsigned long long)__float_as_uint(v) << 32) | (unsigned long long)k);
+    }
+}
+
+// Per-workgroup partial sums of E^2 (FP64, fixed order).
+__global__ __launch_bounds__(LP_TB) void k_csr_sumsq(const float* __restrict__ val, int64_t nnz,
+                                                     double* __restrict__ part) {
+    __shared__ double red[LP_TB];
+    double a = 0.0;
+    for (int64_t q = blockIdx.x * (int64_t)LP_TB + threadIdx.x; q < nnz; q += (int64_t)gridDim.x * LP_TB) {
+        const double v = val[q];
+        a += v * v;
+    }
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = LP_TB / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// D[r * N + col] = val for the entries of pose rows[r] (D zeroed first).
+__global__ __launch_bounds__(LP_TB) void k_csr_gather(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                      const float* __restrict__ val, const int32_t* __restrict__ rows,
+                                                      int64_t N, float* __restrict__ D) {
+    const int64_t r = blockIdx.x, k = rows[r];
+    for (int64_t q = rp[k] + threadIdx.x; q < rp[k + 1]; q += LP_TB) D[r * N + col[q]] = val[q];
+}
+
+// rc[k] = (1 + y_b) - sum_q val[q] y[col[q]] over row k (FP64; strided
+// partials in a fixed tree order).
+__global__ __launch_bounds__(LP_TB) void k_csr_price(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                     const float* __restrict__ val, const double* __restrict__ y,
+                                                     double base, double* __restrict__ rc) {
+    __shared__ double red[LP_TB];
+    const int64_t k = blockIdx.x;
+    double a = 0.0;
+    for (int64_t q = rp[k] + threadIdx.x; q < rp[k + 1]; q += LP_TB) a += (double)val[q] * y[col[q]];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = LP_TB / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) rc[k] = base - red[0];
+}
+
+__global__ void k_scatter_t(const double* __restrict__ src, const int32_t* __restrict__ rows, int64_t n,
+                            double* __restrict__ dst) {
+    const int64_t q = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
+    if (q < n) dst[rows[q]] = src[q];
+}
+
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+static uvc_status solve_csr_colgen(const int64_t* rp, const int32_t* col, const float* val, int64_t K, int64_t N,
+                                   int64_t nnz, const double* pen_dev, double mu, double tmax, double tol,
+                                   int32_t max_iter, double* t_out, double* s_out, double* y_out, uvc_lp_info* info,
+                                   hipStream_t st) {
+    DevBuf<unsigned long long> best;
+    DevBuf<double> part, pen, yd, rc, tr;
+    DevBuf<float> D;
+    DevBuf<int32_t> rows;
+    UVC_TRY(dalloc_n(&best.p, (size_t)N, "column best poses"));
+    UVC_TRY(dalloc_n(&part.p, 1024, "norm partials"));
+    UVC_TRY(dalloc_n(&pen.p, (size_t)N, "penalties"));
+    UVC_TRY(dalloc_n(&yd.p, (size_t)N + 1, "working duals"));
+    UVC_TRY(dalloc_n(&rc.p, (size_t)K, "reduced costs"));
+    hipLaunchKernelGGL(k_lp_fill, dim3(nblk(N)), dim3(LP_TB), 0, st, (double*)best.p, 0.0, N);  // zero bits
+    hipLaunchKernelGGL(k_csr_colbest, dim3((unsigned)K), dim3(LP_TB), 0, st, rp, col, val, best.p);
+    hipLaunchKernelGGL(k_csr_sumsq, dim3(1024), dim3(LP_TB), 0, st, val, nnz, part.p);
+    UVC_HIP(hipGetLastError());
+    std::vector<unsigned long long> hb((size_t)N);
+    std::vector<double> hpart(1024);
+    UVC_HIP(hipMemcpyAsync(hb.data(), best.p, (size_t)N * 8, hipMemcpyDeviceToHost, st));
+    UVC_HIP(hipMemcpyAsync(hpart.data(), part.p, 1024 * 8, hipMemcpyDeviceToHost, st));
+    UVC_HIP(hipStreamSynchronize(st));
+    double fro2 = 0.0;
+    for (double v : hpart) fro2 += v;
+    if (!std::isfinite(fro2)) return fail(UVC_EINVAL, "E has a non-finite entry");
+    const double pdef = 1.001 * std::sqrt(fro2);
+    if (pen_dev)
+        hipLaunchKernelGGL(k_lp_copy, dim3(nblk(N)), dim3(LP_TB), 0, st, pen.p, pen_dev, N);
+    else
+        hipLaunchKernelGGL(k_lp_fill, dim3(nblk(N)), dim3(LP_TB), 0, st, pen.p, pdef, N);
+    int64_t nvis = 0;
+    for (int64_t i = 0; i < N; ++i) nvis += hb[(size_t)i] ? 1 : 0;
+    if (nvis == 0)
+        return solve_empty(K, N, pen_dev, mu, t_out, s_out, y_out, info, st);
+    // working set: the ceil(K / 10) poses with the largest row sums of E
+    // (the most irradiance delivered in all; ties: the lower index); elements
+    // they leave unseen are dropped from the working LP, priced at their
+    // penalty, and the poses that see them join in the first rounds
+    std::vector<double> hrs((size_t)K);
+    {
+        DevBuf<double> ones;
+        UVC_TRY(dalloc_n(&ones.p, (size_t)N, "ones"));
+        hipLaunchKernelGGL(k_lp_fill, dim3(nblk(N)), dim3(LP_TB), 0, st, ones.p, 1.0, N);
+        hipLaunchKernelGGL(k_csr_price, dim3((unsigned)K), dim3(LP_TB), 0, st, rp, col, val, (const double*)ones.p,
+                           0.0, rc.p);
+        UVC_HIP(hipGetLastError());
+        UVC_HIP(hipMemcpyAsync(hrs.data(), rc.p, (size_t)K * 8, hipMemcpyDeviceToHost, st));
+        UVC_HIP(hipStreamSynchronize(st));
+    }
+    const int64_t keep0 = std::max<int64_t>(1, (K + 9) / 10);
+    std::vector<int32_t> order((size_t)K);
+    for (int64_t k = 0; k < K; ++k) order[(size_t)k] = (int32_t)k;
+    std::partial_sort(order.begin(), order.begin() + keep0, order.end(), [&](int32_t a, int32_t b) {
+        return hrs[(size_t)a] != hrs[(size_t)b] ? hrs[(size_t)a] < hrs[(size_t)b] : a < b;  // -row sums
+    });
+    std::vector<uint8_t> in((size_t)K, 0);
+    std::vector<int32_t> R(order.begin(), order.begin() + keep0);
+    for (int32_t k : R) in[(size_t)k] = 1;
+    std::sort(R.begin(), R.end());
+    uvc_lp_info li{};
+    int32_t iters = 0, rounds = 0;
+    double rmin = 0.0;
+    uvc_status r = UVC_OK;
+    std::vector<double> hr((size_t)K);
+    // UVC_VERBOSE set: one progress line per round on stderr
+    const bool verbose = std::getenv("UVC_VERBOSE") != nullptr;
+    const auto t_start = std::chrono::steady_clock::now();
+    while (true) {
+        const int64_t m = (int64_t)R.size();
+        if ((double)m * (double)m * 8.0 > 64e9) return fail(UVC_EUNSUPPORTED, "working pose set too large");
+        for (void** q : {(void**)&rows.p, (void**)&D.p, (void**)&tr.p})
+            if (*q) {
+                (void)hipFree(*q);
+                *q = nullptr;
+            }
+        UVC_TRY(dalloc_n(&rows.p, (size_t)m, "working poses"));
+        UVC_TRY(dalloc_n(&D.p, (size_t)m * N, "working matrix"));
+        UVC_TRY(dalloc_n(&tr.p, (size_t)m, "working dwell times"));
+        UVC_HIP(hipMemcpyAsync(rows.p, R.data(), (size_t)m * 4, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_fill_f32, dim3(4096), dim3(LP_TB), 0, st, D.p, 0.0f, m * N);
+        hipLaunchKernelGGL(k_csr_gather, dim3((unsigned)m), dim3(LP_TB), 0, st, rp, col, val, rows.p, N, D.p);
+        UVC_HIP(hipGetLastError());
+        r = solve_ipm(D.p, m, N, pen.p, mu, tmax, tol, max_iter, tr.p, s_out, yd.p, &li, st);
+        iters += li.iterations;
+        ++rounds;
+        if (r != UVC_OK) break;
+        // price every pose against the working duals (working poses price at >= 0 up to rounding)
+        double yb = 0.0;
+        UVC_HIP(hipMemcpyAsync(&yb, yd.p + N, 8, hipMemcpyDeviceToHost, st));
+        UVC_HIP(hipStreamSynchronize(st));
+        hipLaunchKernelGGL(k_csr_price, dim3((unsigned)K), dim3(LP_TB), 0, st, rp, col, val, (const double*)yd.p,
+                           1.0 + yb, rc.p);
+        UVC_HIP(hipGetLastError());
+        UVC_HIP(hipMemcpyAsync(hr.data(), rc.p, (size_t)K * 8, hipMemcpyDeviceToHost, st));
+        UVC_HIP(hipStreamSynchronize(st));
+        std::vector<int32_t> cand;
+        rmin = 0.0;
+        for (int64_t k = 0; k < K; ++k)
+            if (!in[(size_t)k]) {
+                rmin = std::min(rmin, hr[(size_t)k]);
+                if (hr[(size_t)k] < -1e-6) cand.push_back((int32_t)k);
+            }
+        if (verbose) {
+            const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+            std::fprintf(stderr, "[uvc lp] round %d: %lld working poses, %d iterations, objective %.9e, "
+                                 "%zu poses price below -1e-6 (min %.3e), %.2f s\n",
+                         rounds, (long long)m, li.iterations, li.objective, cand.size(), rmin, el);
+            std::fflush(stderr);
+        }
+        if (cand.empty()) break;
+        // at most as many poses as the set already holds (the set at most
+        // doubles per round): the working LPs grow geometrically, so few
+        // rounds are needed even when the final set is several times R_0
+        const int64_t na = std::min<int64_t>((int64_t)cand.size(), std::max<int64_t>(64, m));
+        std::partial_sort(cand.begin(), cand.begin() + na, cand.end(), [&](int32_t a, int32_t b) {
+            return hr[(size_t)a] != hr[(size_t)b] ? hr[(size_t)a] < hr[(size_t)b] : a < b;
+        });
+        for (int64_t q = 0; q < na; ++q) {
+            in[(size_t)cand[(size_t)q]] = 1;
+            R.push_back(cand[(size_t)q]);
+        }
+        std::sort(R.begin(), R.end());
+        if (rounds >= 200) {
+            r = fail(UVC_ENOTCONV, "column generation: pricing still finds improving poses after 200 rounds");
+            break;
+        }
+    }
+    if (r != UVC_OK && r != UVC_ENOTCONV) return r;
+    // outputs in the full problem's terms: t scattered (0 outside R), the
+    // working sigma and duals; residuals of the working LP, the dual
+    // residual also covering the pricing of the poses outside R
+    if (t_out) {
+        hipLaunchKernelGGL(k_lp_fill, dim3(nblk(K)), dim3(LP_TB), 0, st, t_out, 0.0, K);
+        hipLaunchKernelGGL(k_scatter_t, dim3(nblk((int64_t)R.size())), dim3(LP_TB), 0, st, (const double*)tr.p,
+                           (const int32_t*)rows.p, (int64_t)R.size(), t_out);
+    }
+    if (y_out) hipLaunchKernelGGL(k_lp_copy, dim3(nblk(N + 1)), dim3(LP_TB), 0, st, y_out, (const double*)yd.p, N + 1);
+    UVC_HIP(hipGetLastError());
+    UVC_HIP(hipStreamSynchronize(st));
+    if (info) {
+        *info = li;
+        info->iterations = iters;
+        info->n_visible = nvis;
+        info->penalty = pen_dev ? info->penalty : pdef;
+        info->dual_residual = std::max(li.dual_residual, std::max(0.0, -rmin));
+        info->working_poses = (int64_t)R.size();
+        info->rounds = rounds;
+    }
+    return r;
 }
 
 }  // namespace uvc
@@ -1480,6 +1728,12 @@ extern "C" uvc_status uvc_solve_dosage_lp(const float* E_dev, const int64_t* row
         if (!row_ptr_dev)
             return solve_ipm(E_dev, K, N, penalty_dev, mu_min, t_max, tol, max_iter, t_out_dev, sigma_out_dev,
                              y_out_dev, info, st);
+        int64_t nnz = 0;
+        if (K > LP_DENSE_MAX_POSES) {
+            UVC_TRY(csr_validate(row_ptr_dev, col_dev, E_dev, K, N, st, &nnz));
+            return solve_csr_colgen(row_ptr_dev, col_dev, E_dev, K, N, nnz, penalty_dev, mu_min, t_max, tol,
+                                    max_iter, t_out_dev, sigma_out_dev, y_out_dev, info, st);
+        }
         float* dense = nullptr;
         UVC_TRY(csr_to_dense(row_ptr_dev, col_dev, E_dev, K, N, st, &dense));
         const uvc_status r = solve_ipm(dense, K, N, penalty_dev, mu_min, t_max, tol, max_iter, t_out_dev,

@@ -537,6 +537,11 @@ static uvc_status build_impl(const float* verts_in, int64_t nv, const int32_t* t
         if (m0 == 0.0 && m1 == 0.0 && m2 == 0.0)
             return fail(UVC_EINVAL, "triangle " + std::to_string(t) + " has zero area");
     }
+    // The slab test replaces a zero direction component by +-1e-30 and
+    // multiplies coordinates by its reciprocal: with |coordinates| (and pose
+    // coordinates, limited to twice this) up to 2^26 every such product
+    // stays finite in FP32.
+    if (max_abs > 67108864.0f) return fail(UVC_EINVAL, "a vertex coordinate exceeds 2^26 in magnitude");
     uvc_scene* s = new uvc_scene();
     (void)hipGetDevice(&s->device);
     s->n = nt;

@@ -299,20 +299,24 @@ def _main(argv=None) -> int:
         log(f"labelled {done} new rooms in {time.time() - t0:.1f} s; cache has {len(read_cache(a.cache))}")
         return 0
     if a.cmd == "train-cached":
-        feats, ys, rooms = [], [], 0
+        feats, ys, rooms, skipped = [], [], 0, 0
         for path in a.cache:
             for rec in read_cache(path).values():
+                if not rec["converged"]:  # labels of an LP that hit its iteration limit are left out
+                    skipped += 1
+                    continue
                 fx, yy = cached_samples(rec)
                 feats.append(fx)
                 ys.append(yy)
                 rooms += 1
         X = torch.cat(feats)
         Y = np.concatenate(ys)
-        log(f"{rooms} rooms, {X.shape[0]} poses, positives {Y.mean():.4f}")
+        log(f"{rooms} rooms ({skipped} unconverged left out), {X.shape[0]} poses, positives {Y.mean():.4f}")
         p, m, v, step, losses = train(X, Y, None, None, None, 0, a.epochs, a.batch, a.lr, a.seed, log)
-        meta = {"rooms": rooms, "samples": int(X.shape[0]), "positives": float(Y.mean()), "epochs": a.epochs,
-                "batch": a.batch, "lr": a.lr, "final_loss": losses[-1], "label_rel": LABEL_REL,
-                "feature_height": FEATURE_HEIGHT, "caches": [os.path.basename(c) for c in a.cache]}
+        meta = {"rooms": rooms, "skipped_unconverged": skipped, "samples": int(X.shape[0]),
+                "positives": float(Y.mean()), "epochs": a.epochs, "batch": a.batch, "lr": a.lr,
+                "final_loss": losses[-1], "label_rel": LABEL_REL, "feature_height": FEATURE_HEIGHT,
+                "caches": [os.path.basename(c) for c in a.cache]}
         save_checkpoint(a.out, p, m, v, step, meta)
         log(json.dumps(meta))
         return 0

@@ -42,7 +42,7 @@ class LampC(ctypes.Structure):
 class LpInfoC(ctypes.Structure):
     _fields_ = [("objective", ctypes.c_double), ("primal_residual", ctypes.c_double),
                 ("dual_residual", ctypes.c_double), ("gap", ctypes.c_double), ("iterations", _I32),
-                ("n_visible", _I64), ("penalty", ctypes.c_double)]
+                ("n_visible", _I64), ("penalty", ctypes.c_double), ("working_poses", _I64), ("rounds", _I32)]
 
 
 class OptsC(ctypes.Structure):
@@ -396,7 +396,8 @@ def solve_lp(E: torch.Tensor, mu_min: float = 280.0, t_max: float = 3.6e5, penal
         check(st)
     return {"t": t, "sigma": sg, "y": y, "objective": info.objective, "primal_residual": info.primal_residual,
             "dual_residual": info.dual_residual, "gap": info.gap, "iterations": info.iterations,
-            "n_visible": info.n_visible, "penalty": info.penalty, "converged": st == 0}
+            "n_visible": info.n_visible, "penalty": info.penalty, "working_poses": info.working_poses,
+            "rounds": info.rounds, "converged": st == 0}
 
 
 BATCH_MODES = {"persistent": 0, "graph": 1, "per_room": 2}

@@ -235,6 +235,10 @@ def test_invalid_inputs_rejected(uvc):
     v[3, 1] = np.nan
     with pytest.raises(uvc.UvcError, match="non-finite"):
         uvc.Scene(v, w.mesh.tris)
+    v = w.mesh.verts.copy()
+    v[3, 0] = 1e8
+    with pytest.raises(uvc.UvcError, match="2\\^26"):
+        uvc.Scene(v, w.mesh.tris)
     t = w.mesh.tris.copy()
     t[5, 2] = len(w.mesh.verts)
     with pytest.raises(uvc.UvcError, match="outside"):

@@ -233,7 +233,7 @@ def extras(uvc, workloads, dev, log, floorplan_lp=False):
     # at the batched-room sizes, and one of those rooms (the one whose full
     # LP takes longest) run live
     wdir = os.path.join(ROOT, "paper_2103_14137_amd", "weights")
-    wpath = os.path.join(wdir, "ranker_tower8.bin")
+    wpath = os.path.join(wdir, "ranker_tower8_batchrooms.bin")
     if os.path.exists(wpath):
         ck = ranker.load_checkpoint(wpath)
         w = ranker.room(200006, (2000, 80000), (500, 8000))
@@ -241,7 +241,7 @@ def extras(uvc, workloads, dev, log, floorplan_lp=False):
         out["ranked_plan"] = {"room": "held-out batch room 200006", "K": r["K"], "N": r["N"], "full_ms": r["full_ms"],
                               **{m: {k: r[m][k] for k in ("gap", "ms", "rounds", "n_kept", "fell_back")}
                                  for m in ("mlp", "area")}}
-        sp = os.path.join(wdir, "ranker_tower8_eval_heldout200.json")
+        sp = os.path.join(wdir, "ranker_tower8_batchrooms_eval_heldout200.json")
         if os.path.exists(sp):
             summ = json.load(open(sp))["summary"]
             out["ranked_plan"]["heldout200_recorded"] = {
@@ -353,6 +353,10 @@ def main():
         t = ctypes.c_float(0.0)
         uvc.irradiance_dense(sc, poses, lamp, path="lbvh", out=E, timing=t, flags=uvc.FLAG_NO_NEAR)
         paths["lbvh_no_near"] = {"kernel_ms": t.value, "rays_per_s": rays / (t.value * 1e-3)}
+        for pc in (1, 2, 4, 8, 16):
+            t = ctypes.c_float(0.0)
+            uvc.irradiance_dense(sc, poses, lamp, path="lbvh", out=E, timing=t, pose_chunk=pc)
+            paths[f"lbvh_chunk{pc}"] = {"kernel_ms": t.value, "rays_per_s": rays / (t.value * 1e-3)}
         sub = poses[:: max(1, K // 16)][:16].contiguous()
         for pth in ("lbvh", "brute"):
             sst = uvc.new_stats(dev)

@@ -353,10 +353,7 @@ def main():
         t = ctypes.c_float(0.0)
         uvc.irradiance_dense(sc, poses, lamp, path="lbvh", out=E, timing=t, flags=uvc.FLAG_NO_NEAR)
         paths["lbvh_no_near"] = {"kernel_ms": t.value, "rays_per_s": rays / (t.value * 1e-3)}
-        for pc in (1, 2, 4, 8, 16):
-            t = ctypes.c_float(0.0)
-            uvc.irradiance_dense(sc, poses, lamp, path="lbvh", out=E, timing=t, pose_chunk=pc)
-            paths[f"lbvh_chunk{pc}"] = {"kernel_ms": t.value, "rays_per_s": rays / (t.value * 1e-3)}
+
         sub = poses[:: max(1, K // 16)][:16].contiguous()
         for pth in ("lbvh", "brute"):
             sst = uvc.new_stats(dev)

@@ -175,7 +175,7 @@ typedef struct {
     int32_t flags;       /* UVC_FLAG_* bits                                   */
     int32_t waves;       /* hierarchy path: kernel variant compiled for this
                             many waves per SIMD: 5 (no register cap), 6 or
-                            8 (0 = 8)                                         */
+                            8 (0 = 6)                                         */
     uint64_t* stats_dev; /* NULL, or UVC_STAT_N device counters that an
                             instrumented (slower) kernel adds to              */
     float* kernel_ms;    /* NULL, or host float: HIP events are recorded on

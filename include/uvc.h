@@ -391,11 +391,13 @@ typedef struct {
  * method below over a working set of poses (initially the ceil(K/10)
  * poses with the largest row sums of E), every other pose priced against the working
  * duals (reduced cost 1 + y_b - sum_i E[k,i] y_i from its sparse row) and
- * those below -1e-6 added (the most negative first, at most max(64, |R|)
- * per round: the set at most doubles) until
- * none is left, which makes the working solution optimal over all K poses
- * (info->working_poses, info->rounds; the dual residual reported covers the
- * pricing).  Elements with
+ * those below -1e-6 added (the most negative first, at most
+ * max(64, ceil(K/10)/4) per round) until none is left, which makes the
+ * working solution optimal over
+ * all K poses (info->working_poses, info->rounds; the dual residual
+ * reported covers the pricing; an element no working pose sees keeps
+ * sigma_i = mu_min and dual p_i, and counts in the objective when some
+ * pose sees it).  Elements with
  * E[k,i] = 0 for every k are dropped (sigma_i = mu_min, excluded from the
  * objective).  penalty_dev: N FP64 device values or NULL for
  * p_i = 1.001 * ||E||_F (the paper asks for p_i > ||I||_F).  Mehrotra
@@ -475,7 +477,8 @@ uvc_status uvc_ranker_train_step(float* params_dev, float* adam_m,
 enum { UVC_RANK_MLP = 0, UVC_RANK_AREA = 1, UVC_RANK_NONE = 2 };
 
 typedef struct {
-    double objective;        /* LP objective of the returned plan                    */
+    double objective;        /* LP objective of the returned plan (over the elements
+                                some candidate pose sees)                            */
     double penalty;          /* the LP penalty p used                                */
     double min_reduced_cost; /* smallest reduced cost of a pruned pose at the end    */
     int64_t n_kept;          /* poses in the LP that produced the plan               */

@@ -1220,6 +1220,10 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
         const double hn = std::sqrt((double)nvis * mu * mu + tmax * tmax);  // |h| in the problem's units
         const double cn = std::sqrt((double)K + psq);
         const double ncomp = (double)(nvis * 2 + K + 1);
+        // UVC_VERBOSE=2: one line per iteration on stderr
+        const char* venv = std::getenv("UVC_VERBOSE");
+        const bool trace = venv && std::atoi(venv) >= 2;
+        double tr_ap = 0.0, tr_ad = 0.0, tr_sig = 0.0;
         for (it = 0; it < max_iter; ++it) {
             // residuals and convergence
             Etu(P.xt, P.mvN);
@@ -1236,6 +1240,12 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
             dres = std::sqrt(red[5]) / (1.0 + cn);
             rgap = std::fabs(po - dob) / (1.0 + std::fabs(po) + std::fabs(dob));
             obj = po;
+            if (trace) {
+                std::fprintf(stderr, "[uvc ipm] K %lld it %3d pres %.2e dres %.2e gap %.2e obj %.9e mu %.2e "
+                                     "| last ap %.3f ad %.3f sigma %.2e\n",
+                             (long long)K, it, pres, dres, rgap, po, gap / ncomp, tr_ap, tr_ad, tr_sig);
+                std::fflush(stderr);
+            }
             if (std::max(pres, std::max(dres, rgap)) <= tol) {
                 converged = true;
                 break;
@@ -1305,6 +1315,9 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
             }
             ap *= 0.99;
             ad *= 0.99;
+            tr_ap = ap;
+            tr_ad = ad;
+            tr_sig = sig;
             hipLaunchKernelGGL(k_ipm_update, dim3(gKN), dim3(LP_TB), 0, st, P, K, N, ap, ad, cd);
             UVC_HIP(hipGetLastError());
             sb += ap * dsbc;
@@ -1480,8 +1493,11 @@ static uvc_status csr_to_dense(const int64_t* rp, const int32_t* col, const floa
 // pose k's reduced cost is 1 + y_b - sum_i E[k,i] y_i (a sparse row times
 // the dual vector); poses with negative reduced costs join R until none is
 // below -1e-6, at which point the working solution is optimal for the LP
-// over all K poses.  R starts with, for every visible element, the pose
-// that sees it best (so every visible element is coverable within R).
+// over all K poses.  Elements no pose of R sees are dropped from the
+// working LP (sigma_i = mu_min, dual p_i) and priced at their penalty; their
+// constant p_i mu_min is added back to the reported objective when some pose
+// outside R sees them, so that the objective is the full LP's (over every
+// element some pose sees).
 
 // best[i] = max over the entries (k, i) of (bits(E[k,i]) << 32 | k): E >= 0,
 // so the float bits order like the values; nonzero exactly for the visible
@@ -1539,6 +1555,16 @@ __global__ __launch_bounds__(LP_TB) void k_csr_price(const int64_t* __restrict__
         __syncthreads();
     }
     if (threadIdx.x == 0) rc[k] = base - red[0];
+}
+
+// seen[col] = 1 for the nonzero entries of the poses rows[0..m) (seen
+// zeroed first).
+__global__ __launch_bounds__(LP_TB) void k_csr_mark(const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                                    const float* __restrict__ val, const int32_t* __restrict__ rows,
+                                                    float* __restrict__ seen) {
+    const int64_t k = rows[blockIdx.x];
+    for (int64_t q = rp[k] + threadIdx.x; q < rp[k + 1]; q += LP_TB)
+        if (val[q] > 0.0f) seen[col[q]] = 1.0f;
 }
 
 __global__ void k_scatter_t(const double* __restrict__ src, const int32_t* __restrict__ rows, int64_t n,
@@ -1619,11 +1645,19 @@ static uvc_status solve_csr_colgen(const int64_t* rp, const int32_t* col, const 
     double rmin = 0.0;
     uvc_status r = UVC_OK;
     std::vector<double> hr((size_t)K);
+    // at most max(64, ceil(K/10)/4) poses join per round, the most negative
+    // first: small steps keep the set near the support.  Letting the set
+    // double per round took the floor plan to 9,709 working poses where
+    // 5,281 suffice, and 1.7x the time; solving the rounds that add poses to
+    // a looser tolerance saved few iterations (the early iterations
+    // dominate) and cost extra rounds at the end
+    const int64_t add_cap = std::max<int64_t>(64, keep0 / 4);
     // UVC_VERBOSE set: one progress line per round on stderr
     const bool verbose = std::getenv("UVC_VERBOSE") != nullptr;
     const auto t_start = std::chrono::steady_clock::now();
+    int64_t m = 0;  // poses of the last working LP (rows.p, tr.p); R may have grown since
     while (true) {
-        const int64_t m = (int64_t)R.size();
+        m = (int64_t)R.size();
         if ((double)m * (double)m * 8.0 > 64e9) return fail(UVC_EUNSUPPORTED, "working pose set too large");
         for (void** q : {(void**)&rows.p, (void**)&D.p, (void**)&tr.p})
             if (*q) {
@@ -1665,10 +1699,7 @@ static uvc_status solve_csr_colgen(const int64_t* rp, const int32_t* col, const 
             std::fflush(stderr);
         }
         if (cand.empty()) break;
-        // at most as many poses as the set already holds (the set at most
-        // doubles per round): the working LPs grow geometrically, so few
-        // rounds are needed even when the final set is several times R_0
-        const int64_t na = std::min<int64_t>((int64_t)cand.size(), std::max<int64_t>(64, m));
+        const int64_t na = std::min<int64_t>((int64_t)cand.size(), add_cap);
         std::partial_sort(cand.begin(), cand.begin() + na, cand.end(), [&](int32_t a, int32_t b) {
             return hr[(size_t)a] != hr[(size_t)b] ? hr[(size_t)a] < hr[(size_t)b] : a < b;
         });
@@ -1683,13 +1714,31 @@ static uvc_status solve_csr_colgen(const int64_t* rp, const int32_t* col, const 
         }
     }
     if (r != UVC_OK && r != UVC_ENOTCONV) return r;
+    // elements some pose sees but no working pose does: their constant
+    // p_i mu_min belongs to the full LP's objective
+    double dropped = 0.0;
+    {
+        DevBuf<float> seen;
+        UVC_TRY(dalloc_n(&seen.p, (size_t)N, "working visibility"));
+        hipLaunchKernelGGL(k_fill_f32, dim3(nblk(N)), dim3(LP_TB), 0, st, seen.p, 0.0f, N);
+        hipLaunchKernelGGL(k_csr_mark, dim3((unsigned)m), dim3(LP_TB), 0, st, rp, col, val, (const int32_t*)rows.p,
+                           seen.p);
+        UVC_HIP(hipGetLastError());
+        std::vector<float> hs((size_t)N);
+        std::vector<double> hp((size_t)N);
+        UVC_HIP(hipMemcpyAsync(hs.data(), seen.p, (size_t)N * 4, hipMemcpyDeviceToHost, st));
+        UVC_HIP(hipMemcpyAsync(hp.data(), pen.p, (size_t)N * 8, hipMemcpyDeviceToHost, st));
+        UVC_HIP(hipStreamSynchronize(st));
+        for (int64_t i = 0; i < N; ++i)
+            if (hb[(size_t)i] && hs[(size_t)i] == 0.0f) dropped += hp[(size_t)i] * mu;
+    }
     // outputs in the full problem's terms: t scattered (0 outside R), the
     // working sigma and duals; residuals of the working LP, the dual
     // residual also covering the pricing of the poses outside R
     if (t_out) {
         hipLaunchKernelGGL(k_lp_fill, dim3(nblk(K)), dim3(LP_TB), 0, st, t_out, 0.0, K);
-        hipLaunchKernelGGL(k_scatter_t, dim3(nblk((int64_t)R.size())), dim3(LP_TB), 0, st, (const double*)tr.p,
-                           (const int32_t*)rows.p, (int64_t)R.size(), t_out);
+        hipLaunchKernelGGL(k_scatter_t, dim3(nblk(m)), dim3(LP_TB), 0, st, (const double*)tr.p,
+                           (const int32_t*)rows.p, m, t_out);
     }
     if (y_out) hipLaunchKernelGGL(k_lp_copy, dim3(nblk(N + 1)), dim3(LP_TB), 0, st, y_out, (const double*)yd.p, N + 1);
     UVC_HIP(hipGetLastError());
@@ -1697,10 +1746,11 @@ static uvc_status solve_csr_colgen(const int64_t* rp, const int32_t* col, const 
     if (info) {
         *info = li;
         info->iterations = iters;
+        info->objective += dropped;
         info->n_visible = nvis;
         info->penalty = pen_dev ? info->penalty : pdef;
         info->dual_residual = std::max(li.dual_residual, std::max(0.0, -rmin));
-        info->working_poses = (int64_t)R.size();
+        info->working_poses = m;
         info->rounds = rounds;
     }
     return r;

@@ -313,6 +313,7 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
     for (int32_t k : kept) in_set[(size_t)k] = 1;
     Dev tred, dkept;
     std::vector<hipEvent_t> marks;  // per round: E start, LP start, pricing start, pricing end
+    std::vector<float> seen_kept;   // last round: per element, max of E over the kept poses
     bool fallback = false, optimal = false;
     for (int round = 0; !fallback && !optimal; ++round) {
         const int64_t keep = (int64_t)kept.size();
@@ -357,6 +358,15 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
             optimal = true;
             UVC_HIP(hipEventRecord(mk[3], st));
             break;
+        }
+        {
+            Dev cmk;
+            UVC_TRY(alloc<float>(cmk, N, "kept column maxima"));
+            hipLaunchKernelGGL(k_colmax_any, dim3(grid_of(N, 256)), dim3(256), 0, st, (const float*)Ered.p, keep, N,
+                               (float*)cmk.p);
+            UVC_HIP(hipGetLastError());
+            seen_kept.resize((size_t)N);
+            UVC_HIP(hipMemcpyAsync(seen_kept.data(), cmk.p, (size_t)N * 4, hipMemcpyDeviceToHost, st));
         }
         // price every pruned pose against the elements with a nonzero dual
         std::vector<double> hy((size_t)N + 1);
@@ -444,6 +454,14 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
         UVC_TRY(full_plan(ev.e[6], ev.e[7], penalty));
     } else {
         const int64_t keep = (int64_t)kept.size();
+        // elements the kept poses leave unseen sit out of the restricted LP
+        // at sigma_i = mu_min; those some candidate sees (priced, not dark)
+        // belong to the full LP's objective with their p mu_min
+        if (keep < K && !seen_kept.empty()) {
+            int64_t unseen = 0;
+            for (int64_t i = 0; i < N; ++i) unseen += (seen_kept[(size_t)i] == 0.f && !dark[(size_t)i]) ? 1 : 0;
+            info->objective += (double)unseen * p_lp * mu_min;
+        }
         hipLaunchKernelGGL(k_fill_f64, dim3(grid_of(K, 256)), dim3(256), 0, st, t_out_dev, 0.0, K);
         hipLaunchKernelGGL(k_scatter_f64, dim3(grid_of(keep, 256)), dim3(256), 0, st, (const double*)tred.p,
                            (const int32_t*)dkept.p, keep, t_out_dev);

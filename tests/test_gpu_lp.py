@@ -195,11 +195,17 @@ def test_large_csr_lp_by_column_generation(uvc):
     column generation over a working set of poses; its objective equals the
     direct solve of the same matrix given dense (within 1e-6), t is zero
     outside the working set, and the reference module's KKT check passes on
-    the full matrix (every pose priced)."""
+    the full matrix (every pose priced).  Four elements are each seen by one
+    pose only, so faintly that covering them costs more than their penalty:
+    no working pose sees them, yet they count in the objective."""
     rng = np.random.default_rng(21)
     K, N = 9000, 2500
     E = (rng.lognormal(0.0, 1.0, size=(K, N)) * (rng.uniform(size=(K, N)) < 0.04)).astype(np.float32)
-    E[:, rng.choice(N, 25, replace=False)] = 0.0
+    dark = rng.choice(N, 29, replace=False)
+    E[:, dark] = 0.0
+    faint, faint_poses = dark[25:], np.arange(K - 4, K)
+    E[faint_poses, :] = 0.0
+    E[faint_poses, faint] = 1e-5
     rp, col, val = _to_csr(E)
     sc = uvc.solve_lp(torch.from_numpy(val).cuda(), tol=1e-9, max_iter=300,
                       csr=(torch.from_numpy(rp).cuda(), torch.from_numpy(col).cuda(), N))
@@ -216,4 +222,6 @@ def test_large_csr_lp_by_column_generation(uvc):
             "duals": np.concatenate([y[:N][vis], y[N:]])}
     prim, dual, gap = lp.kkt_residuals(E.astype(np.float64), cert)
     assert prim <= 1e-6 * 280.0 and dual <= 1e-6 * (1.0 + sc["penalty"]) and gap <= 1e-7, (prim, dual, gap)
+    assert np.all(t[faint_poses] == 0.0) and np.allclose(cert["sigma"][faint], 280.0, rtol=1e-12)
+    assert sc["n_visible"] == sd["n_visible"] == int(vis.sum())
     assert sc["penalty"] == pytest.approx(lp.default_penalty(E.astype(np.float64)), rel=1e-12)

@@ -204,6 +204,20 @@ __global__ void k_lp_sum_pairs(const double* __restrict__ part, int nb, double* 
 // ------------------------------------------------------- dense FP64 algebra
 constexpr int SY_T = 64;   // output tile
 constexpr int SY_KC = 32;  // inner chunk (columns of E per LDS stage)
+constexpr int SY_OC = 256; // occupancy block: 64 rows x 256 columns of E
+
+// occ[r * nc + c] = 1 iff E has a nonzero in rows [64 r, 64 r + 64) and
+// columns [256 c, 256 c + 256); one workgroup per block, thread q on column q.
+__global__ __launch_bounds__(256) void k_occ(const float* __restrict__ E, int64_t K, int64_t N, int64_t nc,
+                                             unsigned char* __restrict__ occ) {
+    const int64_t c = blockIdx.x, r = blockIdx.y;
+    const int64_t i = c * SY_OC + threadIdx.x;
+    int nz = 0;
+    if (i < N)
+        for (int64_t a = r * SY_T; a < std::min<int64_t>(K, r * SY_T + SY_T); ++a) nz |= E[a * N + i] != 0.0f;
+    nz = __syncthreads_or(nz);
+    if (threadIdx.x == 0) occ[r * nc + c] = nz ? 1 : 0;
+}
 
 // M[a][b] = sum_i E[a,i] d[i] E[b,i] for the lower tiles (tile row >= tile
 // col) of the K x K row-major M, on the FP64 matrix cores.  A workgroup of
@@ -215,9 +229,14 @@ constexpr int SY_KC = 32;  // inner chunk (columns of E per LDS stage)
 // j + 16 k; result D[i][j] in lane j + 16 (i % 4), element i / 4.
 // With splits > 1, workgroup (tile, s) covers columns [s N / splits,
 // (s + 1) N / splits) and writes the partial product to M + s K^2.
+// With occ (k_occ's map, nc blocks per row tile), a 256-column block where
+// either tile's rows of E are all zero is skipped: its products are exact
+// zeros (E >= 0, d >= 0), so M is the same bit for bit, and a sparse E (poses
+// that see only their own rooms) costs only the blocks both tiles touch.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_syrk(const float* __restrict__ E, int64_t K, int64_t N,
-                                              const double* __restrict__ d, double* __restrict__ M, int splits) {
+                                              const double* __restrict__ d, double* __restrict__ M, int splits,
+                                              const unsigned char* __restrict__ occ, int64_t nc) {
     __shared__ double As[SY_KC][SY_T + 1];
     __shared__ double Bs[SY_KC][SY_T + 1];
     // lower-triangular tile index -> (tr, tc)
@@ -261,15 +280,25 @@ __global__ __launch_bounds__(256) void k_syrk(const float* __restrict__ E, int64
             eb[u] = (iok && b < K) ? vb : 0.0f;
         }
     };
-    if (ib < ie) fetch(ib);
-    for (int64_t i0 = ib; i0 < ie; i0 += SY_KC) {
+    // first column >= i of a block both tiles touch (ie if none); the chunks
+    // of SY_KC columns stay aligned, since ib and SY_OC are multiples of SY_KC
+    auto next_active = [&](int64_t i) -> int64_t {
+        if (occ)
+            while (i < ie && !(occ[tr * nc + i / SY_OC] && occ[tc * nc + i / SY_OC])) i = (i / SY_OC + 1) * SY_OC;
+        return std::min(i, ie);
+    };
+    int64_t i0 = next_active(ib);
+    if (i0 < ie) fetch(i0);
+    while (i0 < ie) {
 #pragma unroll
         for (int u = 0; u < SU; ++u) {
             As[skk][sr + (256 / SY_KC) * u] = (double)ea[u] * di;
             Bs[skk][sr + (256 / SY_KC) * u] = (double)eb[u];
         }
         __syncthreads();
-        if (i0 + SY_KC < ie) fetch(i0 + SY_KC);
+        // the map is consulted only where a new 256-column block starts
+        const int64_t i1 = ((i0 + SY_KC) % SY_OC) ? std::min(i0 + SY_KC, ie) : next_active(i0 + SY_KC);
+        if (i1 < ie) fetch(i1);
 #pragma unroll
         for (int ks = 0; ks < SY_KC / 4; ++ks) {
             const int kk = 4 * ks + lk;
@@ -281,6 +310,7 @@ __global__ __launch_bounds__(256) void k_syrk(const float* __restrict__ E, int64
             acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa1, fb1, acc[1][1], 0, 0, 0);
         }
         __syncthreads();
+        i0 = i1;
     }
 #pragma unroll
     for (int m = 0; m < 2; ++m)
@@ -1025,8 +1055,9 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
     while (splits > 1 && ((double)splits * K * K * 8.0 > 512e6 || N / splits < 4 * SY_KC)) --splits;
     float *cmax_part = nullptr, *cmax = nullptr;
     double *sq_part = nullptr, *sq = nullptr, *part = nullptr, *M = nullptr, *Mpart = nullptr, *rpart = nullptr;
-    unsigned char* vis_d = nullptr;
+    unsigned char *vis_d = nullptr, *occ = nullptr;
     int* failf = nullptr;
+    const int64_t nc_occ = (N + SY_OC - 1) / SY_OC;
     UVC_TRY(W.alloc(&cmax_part, (size_t)chunks * N, "lp colmax"));
     UVC_TRY(W.alloc(&cmax, N, "lp colmax"));
     UVC_TRY(W.alloc(&sq_part, (size_t)chunks * N, "lp norm"));
@@ -1035,6 +1066,7 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
     UVC_TRY(W.alloc(&M, (size_t)K * K, "lp normal matrix"));
     if (splits > 1) UVC_TRY(W.alloc(&Mpart, (size_t)splits * K * K, "lp normal matrix partials"));
     UVC_TRY(W.alloc(&vis_d, N, "lp visibility"));
+    UVC_TRY(W.alloc(&occ, (size_t)T * nc_occ, "lp occupancy map"));
     UVC_TRY(W.alloc(&failf, 1, "lp flag"));
     const int RB = 512;  // reduction workgroups
     UVC_TRY(W.alloc(&rpart, (size_t)RB * IPM_SUMS, "lp reduction partials"));
@@ -1081,6 +1113,8 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
     // column statistics: visibility, ||E||_F, finiteness
     hipLaunchKernelGGL(k_lp_colstats, dim3(nblk(N), (unsigned)chunks), dim3(LP_TB), 0, st, E, K, N, rows_per,
                        cmax_part, sq_part);
+    if (K > 0 && N > 0)
+        hipLaunchKernelGGL(k_occ, dim3((unsigned)nc_occ, (unsigned)T), dim3(256), 0, st, E, K, N, nc_occ, occ);
     hipLaunchKernelGGL(k_lp_max_parts, dim3(nblk(N)), dim3(LP_TB), 0, st, cmax_part, chunks, N, cmax);
     hipLaunchKernelGGL(k_lp_sum_parts, dim3(nblk(N)), dim3(LP_TB), 0, st, sq_part, chunks, N, sq, 1.0);
     std::vector<float> hcmax((size_t)N);
@@ -1137,10 +1171,11 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
         auto factor = [&](double Db) -> uvc_status {
             if (splits > 1) {
                 hipLaunchKernelGGL(k_syrk, dim3((unsigned)tiles, (unsigned)splits), dim3(256), 0, st, E, K, N, P.dtil,
-                                   Mpart, splits);
+                                   Mpart, splits, (const unsigned char*)occ, nc_occ);
                 hipLaunchKernelGGL(k_sum_splits, dim3(nblk(K), (unsigned)K), dim3(LP_TB), 0, st, Mpart, splits, K, M);
             } else {
-                hipLaunchKernelGGL(k_syrk, dim3((unsigned)tiles, 1u), dim3(256), 0, st, E, K, N, P.dtil, M, 1);
+                hipLaunchKernelGGL(k_syrk, dim3((unsigned)tiles, 1u), dim3(256), 0, st, E, K, N, P.dtil, M, 1,
+                                   (const unsigned char*)occ, nc_occ);
             }
             hipLaunchKernelGGL(k_mat_finish, dim3(nblk(K), (unsigned)K), dim3(LP_TB), 0, st, M, K, rs * rs, Db, P.tht,
                                0.0);

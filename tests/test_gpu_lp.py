@@ -95,6 +95,41 @@ def test_duals_certify_optimality(uvc, seed, K, N, t_max):
     assert np.all(y[:N][~vis] == sol["penalty"]) and y[N] >= 0
 
 
+def _rooms_instance(seed, K, N, rooms):
+    """Poses and elements split into rooms; a pose sees (30 % of) its own
+    room's elements and a few of the next room's: most 64-pose x 256-element
+    blocks of E are zero, so the normal matrix skips them."""
+    rng = np.random.default_rng(seed)
+    E = np.zeros((K, N), np.float32)
+    pk = np.arange(K) * rooms // K
+    ei = np.arange(N) * rooms // N
+    own = pk[:, None] == ei[None, :]
+    near = (pk[:, None] + 1) % rooms == ei[None, :]
+    mask = (own & (rng.uniform(size=(K, N)) < 0.3)) | (near & (rng.uniform(size=(K, N)) < 0.002))
+    E[mask] = rng.lognormal(0.0, 1.0, size=int(mask.sum())).astype(np.float32)
+    return E
+
+
+@pytest.mark.parametrize("K,N,rooms,highs", [(600, 3000, 3, True), (3000, 6000, 6, False)])
+def test_block_sparse_lp(uvc, K, N, rooms, highs):
+    """An LP whose E is block-sparse (rooms): the normal-matrix product skips
+    the all-zero blocks.  The small case (split normal-matrix product) matches
+    HiGHS; both pass the reference module's KKT check at tol 1e-9 (the large
+    case takes the unsplit product)."""
+    E = _rooms_instance(7, K, N, rooms)
+    sol = uvc.solve_lp(torch.from_numpy(E).cuda(), mu_min=280.0, t_max=3.6e5, tol=1e-9)
+    assert sol["converged"]
+    if highs:
+        ref_sol = lp.solve(E.astype(np.float64), mu_min=280.0, t_max=3.6e5)
+        assert lp.relative_objective_gap(sol["objective"], ref_sol["objective"]) <= 1e-6
+    y = sol["y"].cpu().numpy()
+    vis = E.max(0) > 0
+    cert = {"t": sol["t"].cpu().numpy(), "sigma": sol["sigma"].cpu().numpy(), "visible": vis,
+            "penalty": np.full(N, sol["penalty"]), "duals": np.concatenate([y[:N][vis], y[N:]])}
+    prim, dual, gap = lp.kkt_residuals(E.astype(np.float64), cert, mu_min=280.0, t_max=3.6e5)
+    assert prim <= 1e-6 * 280.0 and dual <= 1e-6 * (1.0 + sol["penalty"]) and gap <= 1e-7, (prim, dual, gap)
+
+
 def test_large_lp_certified_single_split(uvc):
     """K = 4,451 poses (a batched-workload room, N = 6,604 triangles): at this
     size the normal matrix is formed without splitting the element range

@@ -252,6 +252,53 @@ def extras(uvc, workloads, dev, log, floorplan_lp=False):
     return out
 
 
+def floorplan_run(uvc, workloads, dev, log):
+    """The floor plan (12 rooms, ~488k triangles, 20,000 poses): CSR matrix
+    timed, the same launch again with counters (occlusion rays), then the
+    dosage LP straight from the CSR by column generation, with its KKT
+    residuals."""
+    import numpy as np
+    import torch
+
+    fp = workloads.floorplan()
+    sc = uvc.Scene(torch.from_numpy(fp.mesh.verts).to(dev), torch.from_numpy(fp.mesh.tris).to(dev))
+    P = torch.from_numpy(np.ascontiguousarray(fp.poses)).to(dev)
+    flamp = uvc.Lamp(fp.lamp.dz, fp.lamp.power)
+    log(f"floor plan: K={fp.K} N={fp.N} S={flamp.n_src}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rp, col, val = uvc.irradiance_csr(sc, P, flamp, path="lbvh")
+    torch.cuda.synchronize()
+    csr_s = time.perf_counter() - t0
+    nnz = int(rp[-1])
+    log(f"csr {csr_s:.2f} s, nnz {nnz}")
+    st = uvc.new_stats()
+    rp2, col2, val2 = uvc.irradiance_csr(sc, P, flamp, path="lbvh", stats=st)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(rp, rp2) and torch.equal(col, col2) and torch.equal(val, val2))
+    del rp2, col2, val2
+    counts = uvc.stats_dict(st)
+    log(f"counted launch: {counts['rays']} rays, identical CSR: {same}")
+    out = {"mode": "floorplan", "workload": "floor plan 12 rooms, N=%d triangles, K=%d poses, tower lamp 8 x 20 W"
+           % (fp.N, fp.K),
+           "csr": {"K": fp.K, "N": fp.N, "seconds": csr_s, "entries_per_s": fp.K * fp.N / csr_s,
+                   "rays": counts["rays"], "rays_per_s": counts["rays"] / csr_s, "nnz": nnz, "nnz_per_s": nnz / csr_s,
+                   "csr_GB": nnz * 8 / 1e9, "counted_launch_identical": same}}
+    os.environ["UVC_VERBOSE"] = "1"
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    flp = uvc.solve_lp(val, csr=(rp, col, fp.N), allow_notconv=True, max_iter=300)
+    torch.cuda.synchronize()
+    out["lp"] = {"seconds": time.perf_counter() - t0, "objective": flp["objective"], "converged": flp["converged"],
+                 "working_poses": flp["working_poses"], "rounds": flp["rounds"], "iterations": flp["iterations"],
+                 "primal_residual": flp["primal_residual"], "dual_residual": flp["dual_residual"], "gap": flp["gap"],
+                 "n_visible": flp["n_visible"], "penalty": flp["penalty"], "dwell_s": float(flp["t"].sum()),
+                 "stops": int((flp["t"] > 1e-5 * flp["t"].sum()).sum())}
+    log(f"lp {out['lp']}")
+    sc.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -262,9 +309,11 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the batched / LP / ranked-plan sections")
     ap.add_argument("--floorplan-lp", action="store_true",
                     help="also solve the floor plan's dosage LP from its CSR (column generation; minutes)")
-    ap.add_argument("--mode", choices=["bench", "kernel", "copy"], default="bench",
+    ap.add_argument("--mode", choices=["bench", "kernel", "copy", "floorplan"], default="bench",
                     help="kernel: only two launches of the irradiance kernel (for counter runs); "
-                         "copy: a plain 1 GiB device copy (counter calibration)")
+                         "copy: a plain 1 GiB device copy (counter calibration); "
+                         "floorplan: the floor plan's CSR matrix (timed, then counted) and its dosage LP "
+                         "by column generation (minutes)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -288,6 +337,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"mode": "copy", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
                           "copies": 3}), flush=True)
+        return
+    if args.mode == "floorplan":
+        print(json.dumps(floorplan_run(uvc, workloads, dev, log)), flush=True)
         return
     w = workloads.ward()
     K, N, S = w.K, w.N, w.lamp.n_src

@@ -88,25 +88,53 @@ __global__ void k_lp_colmax_w(const float* __restrict__ E, int64_t K, int64_t N,
 }
 
 // part[chunk][i] = sum_{k in chunk} E[k,i] * u[k]   (E^T u, column sums)
+// Both products below take the occupancy map of E (64 rows x 256 columns
+// per block, see k_occ; occ = nullptr: none) and skip the all-zero blocks.
+// A skipped term is E[k,i] * x = +-0 added to a sum that starts at +0 and
+// never is -0, so the results are the same bits as without the map.
+constexpr int OCC_R = 64, OCC_C = 256;
+static_assert(OCC_C == LP_TB, "a workgroup of k_lp_Etu covers one occupancy block of columns");
+
 __global__ void k_lp_Etu(const float* __restrict__ E, int64_t K, int64_t N, int64_t rows_per,
-                         const double* __restrict__ u, double* __restrict__ part) {
+                         const double* __restrict__ u, double* __restrict__ part,
+                         const unsigned char* __restrict__ occ, int64_t nc) {
     const int64_t i = blockIdx.x * (int64_t)LP_TB + threadIdx.x;
     const int64_t k0 = blockIdx.y * rows_per, k1 = std::min<int64_t>(K, k0 + rows_per);
     double acc = 0.0;
     if (i < N)
-        for (int64_t k = k0; k < k1; ++k) acc += (double)E[k * N + i] * u[k];
+        for (int64_t k = k0; k < k1;) {
+            const int64_t t = k / OCC_R, kend = std::min<int64_t>(k1, (t + 1) * OCC_R);
+            if (occ && !occ[t * nc + blockIdx.x]) {
+                k = kend;
+                continue;
+            }
+            for (; k < kend; ++k) acc += (double)E[k * N + i] * u[k];
+        }
     if (i < N) part[blockIdx.y * N + i] = acc;
 }
 
 // out[k] = sum_i E[k,i] * v[i]  (E v, row dot products; one block per row,
 // fixed-order tree reduction)
 __global__ void k_lp_Ev(const float* __restrict__ E, int64_t N, const double* __restrict__ v,
-                        double* __restrict__ out, double scale) {
+                        double* __restrict__ out, double scale, const unsigned char* __restrict__ occ, int64_t nc) {
     __shared__ double red[LP_TB];
     const int64_t k = blockIdx.x;
     double acc = 0.0;
     const float* row = E + k * N;
-    for (int64_t i = threadIdx.x; i < N; i += LP_TB) acc += (double)row[i] * v[i];
+    const unsigned char* orow = occ ? occ + (k / OCC_R) * nc : nullptr;
+    // 64 blocks' flags per ballot (one per lane, the same in every wave),
+    // then the set blocks in ascending order: no load waits on a flag
+    const int lane = threadIdx.x & 63;
+    const int64_t nb = (N + OCC_C - 1) / OCC_C;
+    for (int64_t jb = 0; jb < nb; jb += 64) {
+        unsigned long long m = __ballot(jb + lane < nb && (!orow || orow[jb + lane]));
+        while (m) {
+            const int b = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            const int64_t i = (jb + b) * OCC_C + threadIdx.x;
+            if (i < N) acc += (double)row[i] * v[i];
+        }
+    }
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int s = LP_TB / 2; s > 0; s >>= 1) {
@@ -205,6 +233,7 @@ __global__ void k_lp_sum_pairs(const double* __restrict__ part, int nb, double* 
 constexpr int SY_T = 64;   // output tile
 constexpr int SY_KC = 32;  // inner chunk (columns of E per LDS stage)
 constexpr int SY_OC = 256; // occupancy block: 64 rows x 256 columns of E
+static_assert(SY_T == OCC_R && SY_OC == OCC_C, "one occupancy map serves the products and the normal matrix");
 
 // occ[r * nc + c] = 1 iff E has a nonzero in rows [64 r, 64 r + 64) and
 // columns [256 c, 256 c + 256); one workgroup per block, thread q on column q.
@@ -1089,11 +1118,13 @@ static uvc_status solve_ipm(const float* E, int64_t K, int64_t N, const double* 
     // from its scale and budget-bound rooms took up to twice the iterations.
     const double rs = 1.0 / mu;
     auto Etu = [&](const double* u, double* out) {  // out[i] = rs sum_k E[k,i] u[k]
-        hipLaunchKernelGGL(k_lp_Etu, dim3(nblk(N), (unsigned)chunks), dim3(LP_TB), 0, st, E, K, N, rows_per, u, part);
+        hipLaunchKernelGGL(k_lp_Etu, dim3(nblk(N), (unsigned)chunks), dim3(LP_TB), 0, st, E, K, N, rows_per, u, part,
+                           (const unsigned char*)occ, nc_occ);
         hipLaunchKernelGGL(k_lp_sum_parts, dim3(nblk(N)), dim3(LP_TB), 0, st, part, chunks, N, out, rs);
     };
     auto Ev = [&](const double* v, double* out) {  // out[k] = sum_i E[k,i] v[i]
-        hipLaunchKernelGGL(k_lp_Ev, dim3((unsigned)K), dim3(LP_TB), 0, st, E, N, v, out, rs);
+        hipLaunchKernelGGL(k_lp_Ev, dim3((unsigned)K), dim3(LP_TB), 0, st, E, N, v, out, rs,
+                           (const unsigned char*)occ, nc_occ);
     };
     double red[IPM_SUMS];
     double hS[S_RED + IPM_SUMS];

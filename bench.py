@@ -165,6 +165,16 @@ def extras(uvc, workloads, dev, log, floorplan_lp=False):
     out["floorplan_csr"] = {"K": fp.K, "N": fp.N, "seconds": csr_s, "nnz": nnz, "csr_GB": nnz * 8 / 1e9,
                             "entries_per_s": fp.K * fp.N / csr_s}
     log(f"floorplan csr {out['floorplan_csr']}")
+    # the floor plan's LP and ray count as recorded by bench.py --mode
+    # floorplan (minutes: not rerun here unless --floorplan-lp)
+    rec = os.path.join(ROOT, "profiles", "floorplan_csr_lp.json")
+    if os.path.exists(rec):
+        r = json.load(open(rec))
+        out["floorplan_recorded"] = {"command": r["command"], "csr_rays_per_s": r["csr"]["rays_per_s"],
+                                     "csr_nnz_per_s": r["csr"]["nnz_per_s"],
+                                     **{"lp_" + k: r["lp"][k] for k in ("seconds", "rounds", "working_poses",
+                                                                        "iterations", "primal_residual",
+                                                                        "dual_residual", "gap", "objective")}}
     if floorplan_lp:
         # the floor plan's dosage LP straight from the CSR (column generation;
         # minutes: opt-in, progress per round on stderr)

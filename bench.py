@@ -97,7 +97,8 @@ def cpu_baseline(w, n_poses=32, n_elems=1024, seed=2024):
 def extras(uvc, workloads, dev, log, floorplan_lp=False):
     """The additions around the hot path, each timed once: the 64-room
     batched launch (persistent, hipGraph replay, one launch per room), the
-    floor plan as CSR, the dosage LP on one room, and the ranked plan
+    floor plan as CSR and its dosage LP (column generation), the area-integrated
+    matrix, the route stage, the dosage LP on one room, and the ranked plan
     (learned ranker + column generation) against the full-candidate LP on
     one larger room."""
     import numpy as np
@@ -165,19 +166,9 @@ def extras(uvc, workloads, dev, log, floorplan_lp=False):
     out["floorplan_csr"] = {"K": fp.K, "N": fp.N, "seconds": csr_s, "nnz": nnz, "csr_GB": nnz * 8 / 1e9,
                             "entries_per_s": fp.K * fp.N / csr_s}
     log(f"floorplan csr {out['floorplan_csr']}")
-    # the floor plan's LP and ray count as recorded by bench.py --mode
-    # floorplan (minutes: not rerun here unless --floorplan-lp)
-    rec = os.path.join(ROOT, "profiles", "floorplan_csr_lp.json")
-    if os.path.exists(rec):
-        r = json.load(open(rec))
-        out["floorplan_recorded"] = {"command": r["command"], "csr_rays_per_s": r["csr"]["rays_per_s"],
-                                     "csr_nnz_per_s": r["csr"]["nnz_per_s"],
-                                     **{"lp_" + k: r["lp"][k] for k in ("seconds", "rounds", "working_poses",
-                                                                        "iterations", "primal_residual",
-                                                                        "dual_residual", "gap", "objective")}}
     if floorplan_lp:
         # the floor plan's dosage LP straight from the CSR (column generation;
-        # minutes: opt-in, progress per round on stderr)
+        # progress per round on stderr)
         os.environ["UVC_VERBOSE"] = "1"
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -191,6 +182,7 @@ def extras(uvc, workloads, dev, log, floorplan_lp=False):
                                "stops": int((flp["t"] > 1e-5 * flp["t"].sum()).sum())}
         log(f"floorplan lp {out['floorplan_lp']}")
         del flp
+        os.environ.pop("UVC_VERBOSE", None)
     del rp, col, val
     sc.close()
     torch.cuda.empty_cache()
@@ -317,13 +309,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the brute-force path comparison")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched / LP / ranked-plan sections")
-    ap.add_argument("--floorplan-lp", action="store_true",
-                    help="also solve the floor plan's dosage LP from its CSR (column generation; minutes)")
+    ap.add_argument("--no-floorplan-lp", action="store_true",
+                    help="skip the floor plan's dosage LP (column generation from its CSR; ~30 s)")
     ap.add_argument("--mode", choices=["bench", "kernel", "copy", "floorplan"], default="bench",
                     help="kernel: only two launches of the irradiance kernel (for counter runs); "
                          "copy: a plain 1 GiB device copy (counter calibration); "
                          "floorplan: the floor plan's CSR matrix (timed, then counted) and its dosage LP "
-                         "by column generation (minutes)")
+                         "by column generation (about a minute)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -458,7 +450,7 @@ def main():
     del E
     torch.cuda.empty_cache()
     if not args.no_extras:
-        out["extras"] = extras(uvc, workloads, dev, log, floorplan_lp=args.floorplan_lp)
+        out["extras"] = extras(uvc, workloads, dev, log, floorplan_lp=not args.no_floorplan_lp)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
         log(f"cpu baseline {out['cpu_baseline']}")

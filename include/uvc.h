@@ -392,8 +392,9 @@ typedef struct {
  * poses with the largest row sums of E), every other pose priced against the working
  * duals (reduced cost 1 + y_b - sum_i E[k,i] y_i from its sparse row) and
  * those below -1e-6 added (the most negative first, at most
- * max(64, ceil(K/10)/4) per round) until none is left, which makes the
- * working solution optimal over
+ * max(64, ceil(K/10)/4) per round; working poses without dwell whose
+ * reduced cost exceeds 1e-2 (1 + y_b) leave the set, each at most once)
+ * until none is left, which makes the working solution optimal over
  * all K poses (info->working_poses, info->rounds; the dual residual
  * reported covers the pricing; an element no working pose sees keeps
  * sigma_i = mu_min and dual p_i, and counts in the objective when some
@@ -490,6 +491,8 @@ typedef struct {
     int32_t lp_iterations;   /* summed over every LP solved                          */
     int32_t lp_converged;
     float ms_features, ms_score, ms_E, ms_lp, ms_price, ms_fallback, ms_total;
+    int64_t n_dropped;       /* kept poses without dwell that left the set (each at
+                                most once; reduced cost above 1e-2 (1 + y_b))        */
 } uvc_plan_info;
 
 /* Dwell-time plan with pose pruning and column generation.

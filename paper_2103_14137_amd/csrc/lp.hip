@@ -1702,7 +1702,7 @@ static uvc_status solve_csr_colgen(const int64_t* rp, const int32_t* col, const 
     std::partial_sort(order.begin(), order.begin() + keep0, order.end(), [&](int32_t a, int32_t b) {
         return hrs[(size_t)a] != hrs[(size_t)b] ? hrs[(size_t)a] < hrs[(size_t)b] : a < b;  // -row sums
     });
-    std::vector<uint8_t> in((size_t)K, 0);
+    std::vector<uint8_t> in((size_t)K, 0), dropped_once((size_t)K, 0);
     std::vector<int32_t> R(order.begin(), order.begin() + keep0);
     for (int32_t k : R) in[(size_t)k] = 1;
     std::sort(R.begin(), R.end());
@@ -1765,6 +1765,30 @@ static uvc_status solve_csr_colgen(const int64_t* rp, const int32_t* col, const 
             std::fflush(stderr);
         }
         if (cand.empty()) break;
+        // poses of R without dwell whose reduced cost is clearly positive
+        // leave the set (each pose at most once, so the rounds end): the
+        // working LPs stay near the support instead of growing with every
+        // round; should one price negative again later, it rejoins
+        {
+            std::vector<double> ht((size_t)m);
+            UVC_HIP(hipMemcpyAsync(ht.data(), tr.p, (size_t)m * 8, hipMemcpyDeviceToHost, st));
+            UVC_HIP(hipStreamSynchronize(st));
+            double tmax_w = 0.0;
+            for (double v : ht) tmax_w = std::max(tmax_w, v);
+            const double margin = 1e-2 * (1.0 + std::fabs(yb));
+            std::vector<int32_t> keep;
+            keep.reserve(R.size());
+            for (int64_t q = 0; q < m; ++q) {
+                const int32_t k = R[(size_t)q];
+                if (!dropped_once[(size_t)k] && ht[(size_t)q] <= 1e-9 * tmax_w && hr[(size_t)k] > margin) {
+                    in[(size_t)k] = 0;
+                    dropped_once[(size_t)k] = 1;
+                } else {
+                    keep.push_back(k);
+                }
+            }
+            R.swap(keep);
+        }
         const int64_t na = std::min<int64_t>((int64_t)cand.size(), add_cap);
         std::partial_sort(cand.begin(), cand.begin() + na, cand.end(), [&](int32_t a, int32_t b) {
             return hr[(size_t)a] != hr[(size_t)b] ? hr[(size_t)a] < hr[(size_t)b] : a < b;

@@ -310,6 +310,7 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
     const double tol_loose = std::max(tol, 1e-4);
     bool final_pass = tol_loose <= tol;
     std::vector<uint8_t> in_set((size_t)K, 0), dark((size_t)N, 0);  // dark: no candidate sees it
+    std::vector<uint8_t> dropped_once((size_t)K, 0);
     for (int32_t k : kept) in_set[(size_t)k] = 1;
     Dev tred, dkept;
     std::vector<hipEvent_t> marks;  // per round: E start, LP start, pricing start, pricing end
@@ -431,6 +432,30 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
         } else if (info->rounds_added >= max_rounds) {
             fallback = true;
         } else {
+            // kept poses without dwell whose reduced cost is clearly positive
+            // leave the set (each pose at most once): the restricted LPs stay
+            // near the support; a pose that prices negative later rejoins
+            {
+                std::vector<double> ht((size_t)keep);
+                UVC_HIP(hipMemcpyAsync(ht.data(), tred.p, (size_t)keep * 8, hipMemcpyDeviceToHost, st));
+                UVC_HIP(hipStreamSynchronize(st));
+                double tmx = 0.0;
+                for (double v : ht) tmx = std::max(tmx, v);
+                const double margin = 1e-2 * (1.0 + std::fabs(yb));
+                std::vector<int32_t> stay;
+                stay.reserve(kept.size());
+                for (int64_t q = 0; q < keep; ++q) {
+                    const int32_t k = kept[(size_t)q];
+                    if (!dropped_once[(size_t)k] && ht[(size_t)q] <= 1e-9 * tmx && rc[(size_t)k] > margin) {
+                        in_set[(size_t)k] = 0;
+                        dropped_once[(size_t)k] = 1;
+                        info->n_dropped += 1;
+                    } else {
+                        stay.push_back(k);
+                    }
+                }
+                kept.swap(stay);
+            }
             const int64_t na = std::min<int64_t>((int64_t)cand.size(), add_cap);
             std::partial_sort(cand.begin(), cand.begin() + na, cand.end(), [&](int32_t a, int32_t b) {
                 return rc[(size_t)a] != rc[(size_t)b] ? rc[(size_t)a] < rc[(size_t)b] : a < b;

@@ -209,6 +209,7 @@ def evaluate_room(w: workloads.Workload, params: np.ndarray, keep_frac: float = 
                          "gap": (ev["objective"] - ref["objective"]) / ref["objective"],
                          "fell_back": r["fell_back"], "n_kept": r["n_kept"], "n_added": r["n_added"],
                          "rounds": r["rounds"], "rounds_added": r["rounds_added"], "n_priced": r["n_priced"],
+                         "n_dropped": r["n_dropped"],
                          "ms": r["ms_total"],
                          "lp_iterations": r["lp_iterations"],
                          "ms_parts": {k: r[k] for k in ("ms_features", "ms_score", "ms_E", "ms_lp", "ms_price",

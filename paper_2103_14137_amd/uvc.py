@@ -58,7 +58,7 @@ class PlanInfoC(ctypes.Structure):
                 ("lp_iterations", _I32), ("lp_converged", _I32),
                 ("ms_features", ctypes.c_float), ("ms_score", ctypes.c_float), ("ms_E", ctypes.c_float),
                 ("ms_lp", ctypes.c_float), ("ms_price", ctypes.c_float), ("ms_fallback", ctypes.c_float),
-                ("ms_total", ctypes.c_float)]
+                ("ms_total", ctypes.c_float), ("n_dropped", _I64)]
 
 
 _lib = None

@@ -516,10 +516,9 @@ typedef struct {
  * elements no candidate sees are skipped afterwards).  If none is below
  * -1e-6 the restricted plan is optimal for the LP over all K poses and is
  * returned; otherwise up to max(16, |R_0|) poses with the most negative
- * reduced costs join and the next round starts.  Rounds that go on to add
- * poses solve their LP to max(tol, 1e-4); when pricing finds nothing the
- * same set is solved to tol and priced once more before the plan is
- * accepted.  After max_rounds rounds that added poses with pricing still
+ * reduced costs join (kept poses without dwell whose reduced cost exceeds
+ * 1e-2 (1 + y_b) leave first, each at most once) and the next round
+ * starts; every restricted LP is solved to tol.  After max_rounds rounds that added poses with pricing still
  * negative, or if an LP does not converge, the
  * plan is recomputed from all K poses (fell_back = 1).  Outputs: t_out_dev
  * (K FP64, zero for pruned poses), sigma_out_dev (N FP64), kept_host (NULL

@@ -181,15 +181,22 @@ def test_plan_fallback_forced(plan_room):
 
 def test_plan_column_generation_from_one_pose(plan_room):
     """Starting from a single pose, pricing rounds reach the optimum of the
-    LP over all candidates (same penalty), without the fallback."""
+    LP over all candidates (same penalty), without the fallback; the kept
+    set is the start pose plus the added poses minus those that left (no
+    dwell, reduced cost clearly positive), and every kept pose was added or
+    started the set."""
     w, sc, poses, E = plan_room
     p = _p_full(E)
     full = uvc.plan_ranked(sc, poses, w.lamp, mode="none", penalty=p)
     r = uvc.plan_ranked(sc, poses, w.lamp, mode="area", keep_frac=1e-6, penalty=p, max_rounds=100)
-    print({k: r[k] for k in ("n_kept", "n_added", "rounds", "rounds_added", "fell_back", "n_priced",
+    print({k: r[k] for k in ("n_kept", "n_added", "n_dropped", "rounds", "rounds_added", "fell_back", "n_priced",
                              "min_reduced_cost")},
           flush=True)
-    assert r["fell_back"] == 0 and r["n_kept"] == 1 + r["n_added"] and r["min_reduced_cost"] >= -1e-6
+    assert r["fell_back"] == 0 and r["min_reduced_cost"] >= -1e-6
+    assert r["n_kept"] == 1 + r["n_added"] - r["n_dropped"] and 0 <= r["n_dropped"] <= r["n_added"] + 1
+    assert len(set(r["kept"].tolist())) == r["n_kept"]
+    t = r["t"].cpu().numpy()
+    assert np.all(t[np.setdiff1d(np.arange(w.K), r["kept"])] == 0.0)
     ev = uvc.plan_evaluate(E, r["t"], penalty=p)
     ref = uvc.plan_evaluate(E, full["t"], penalty=p)
     assert abs(ev["objective"] - ref["objective"]) <= 1e-6 * ref["objective"]
@@ -203,12 +210,13 @@ def test_plan_pruned_reaches_full_optimum(plan_room):
     ref = uvc.plan_evaluate(E, full["t"], penalty=p)
     for mode in ("area", "mlp"):
         r = uvc.plan_ranked(sc, poses, w.lamp, mode=mode, params=params, keep_frac=0.1, penalty=p)
-        print(mode, {k: r[k] for k in ("n_kept", "n_added", "rounds", "fell_back", "n_priced", "ms_total")},
+        print(mode, {k: r[k] for k in ("n_kept", "n_added", "n_dropped", "rounds", "fell_back", "n_priced",
+                                       "ms_total")},
               flush=True)
         t = r["t"]
         assert torch.all(t >= 0)
         if r["fell_back"] == 0:
-            assert r["n_kept"] == int(np.ceil(0.1 * w.K)) + r["n_added"]
+            assert r["n_kept"] == int(np.ceil(0.1 * w.K)) + r["n_added"] - r["n_dropped"]
             pruned = np.setdiff1d(np.arange(w.K), r["kept"])
             assert torch.all(t[torch.from_numpy(pruned).cuda()] == 0)
         ev = uvc.plan_evaluate(E, t, penalty=p)

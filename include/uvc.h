@@ -518,8 +518,10 @@ typedef struct {
  * returned; otherwise up to max(16, |R_0|) poses with the most negative
  * reduced costs join (kept poses without dwell whose reduced cost exceeds
  * 1e-2 (1 + y_b) leave first, each at most once) and the next round
- * starts; every restricted LP is solved to tol.  After max_rounds rounds that added poses with pricing still
- * negative, or if an LP does not converge, the
+ * starts; every restricted LP is solved to tol (one that stops at max_iter
+ * with relative residuals and gap within 1e-6 is used as it is, and
+ * lp_converged = 0 reports it).  After max_rounds rounds that added poses with pricing still
+ * negative, or if an LP stops farther from convergence, the
  * plan is recomputed from all K poses (fell_back = 1).  Outputs: t_out_dev
  * (K FP64, zero for pruned poses), sigma_out_dev (N FP64), kept_host (NULL
  * or K int32: the first n_kept entries list the poses of the final LP,

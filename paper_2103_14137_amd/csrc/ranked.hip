@@ -350,7 +350,13 @@ extern "C" uvc_status uvc_plan_ranked(const uvc_scene* scene, const float* poses
         info->lp_iterations += li.iterations;
         info->lp_converged = lps == UVC_OK ? 1 : 0;
         info->rounds = round + 1;
-        if (lps != UVC_OK) {
+        // an LP stopped at its iteration limit is used as it is when its
+        // relative residuals and gap are within 1e-6 (a few LPs stall near
+        // 1e-7, and so does the full LP of the same room); otherwise the
+        // plan falls back to the full candidate set
+        const bool near = lps == UVC_ENOTCONV &&
+                          std::max(li.primal_residual, std::max(li.dual_residual, li.gap)) <= 1e-6;
+        if (lps != UVC_OK && !near) {
             fallback = true;
             UVC_HIP(hipEventRecord(mk[3], st));
             break;
